@@ -1,0 +1,136 @@
+/*
+ * lsbdg -- matrix-free discontinuous-Galerkin operators for the
+ * scale-resolved lithium-sulfur cathode model of arXiv 2511.05233
+ * ("Structure Matters"), for AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Sec. 2.4-2.6, Tab. 4): on a voxelised porous cathode of
+ * nx x ny x nz cubic voxels of edge h (x = transport axis), the unknowns per
+ * DG node are the six dissolved-species concentrations
+ *     c = (Li+, S8(L), S8^2-, S6^2-, S4^2-, S^2-)  [mol/m^3],
+ * the liquid potential Phi_L [V], and the solid volume fractions
+ * (eps_S8, eps_Li2S) of Tab. 4's solid-phase mass equations.  The solid is
+ * equipotential at V = dPhi0 of Tab. InitialState (the gauge of Sec. 2.9).
+ * Species obey Nernst-Planck transport with Bruggeman-effective,
+ * viscosity-scaled diffusivities (Eq. 02-03, 16a); Phi_L obeys the
+ * anion-eliminated charge balance (Tab. 4, Sec. 2.6 item (i)); reactions
+ * are the Tradeoff Chemistry of Tab. 3 with Butler-Volmer kinetics
+ * (Eq. 05-06, 18-24).  Space: interior-penalty DG with harmonic-mean
+ * coefficients (Eq. 43-47) on tensor-product Gauss-Legendre nodes of degree
+ * k in {0, 1} per axis; time: backward Euler (Eq. 50).  The separator face
+ * x = L_x receives the Li+ flux j_el/F and the ionic current j_el; all other
+ * faces are no-flux (Eq. 47 with the paper's galvanostatic condition).
+ *
+ * Memory layout of every state-like array: field-major  a[f][e][n]
+ *     f  field index (9 for a state, 7 for Krylov vectors, 8 for old mass)
+ *     e  = ix + nx*(iy + ny*iz)            (x fastest)
+ *     n  = a0 + K*(a1 + K*a2), K = k + 1   (x fastest within the voxel)
+ * in the precision selected per call (double for DG_F64, float for DG_F32).
+ *
+ * Ownership: the caller owns every array passed in (state, residual and
+ * vector buffers, on the device unless stated).  The library allocates its
+ * own device tables in dg_setup and frees them in dg_destroy.  Work is
+ * enqueued on the caller's HIP stream (0 = the null stream); entry points
+ * that return host scalars synchronise that stream.
+ *
+ * Errors: every entry point returns a dg_status; no C++ exception crosses
+ * the boundary.  On failure dg_last_error() describes the cause (valid
+ * until the next call on the same thread).
+ */
+#ifndef LSBDG_H
+#define LSBDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;           /* opaque, library-owned */
+typedef void* dg_stream;                 /* a hipStream_t */
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument: null pointer, size, order, ... */
+  DG_ENOMEM = -2,        /* device allocation failed */
+  DG_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+  DG_ENOCONV = -4,       /* Newton did not converge (report filled) */
+  DG_ENAN = -5,          /* non-finite residual norm */
+  DG_ESTATE = -6,        /* call out of order (e.g. apply before setup) */
+  DG_EUNSUPPORTED = -7   /* valid but not implemented (order, precision) */
+} dg_status;
+
+typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_prec;
+
+/* Mesh: voxel counts, voxel edge h [m], polynomial degree per axis. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t order;
+  double h;
+} dg_mesh;
+
+/* Physical and numerical parameters, SI units.  dg_params_default() fills
+ * the paper's values (Tab. 5, Tab. 2, Eq. 02); workloads override D0 and kE.
+ * Fields set to a negative value are derived in dg_setup as noted. */
+typedef struct {
+  double T;             /* temperature [K] (298.15: reproduces Tab. 5 "Equi.") */
+  double D0[7];         /* infinite-dilution diffusivities [m^2/s]:
+                           Li+, S8(L), S8^2-, S6^2-, S4^2-, S^2-, anion */
+  double kE[6];         /* electrochemical rate constants E1..E6 [mol/(s m^2)] */
+  double f_C;           /* discharge rate [1/h] (Eq. 18 passivation, App. C) */
+  double j_el;          /* applied current density [A/m^2]; < 0: App. C,
+                           f_C * c_theo * m_A with m_A from the structure */
+  double eps_struct;    /* structure fraction of Eq. 57; < 0: 1 - pore fraction */
+  double sigma;         /* interior-penalty factor; <= 0: 1 for k = 0, (k+1)^2 else */
+  double c_min;         /* activity clamp [mol/m^3] */
+  double epsL_min;      /* floor of the liquid fraction */
+  int32_t use_TH;       /* 1: multiply C2 and E4 by T_H(t) (Eq. 56, Sec. 2.9) */
+  int32_t reserved;
+} dg_params;
+
+/* Fill *p with the paper's parameters (Tab. 5) and defaults. */
+void dg_params_default(dg_params* p);
+
+/* Create a context for one voxel structure.
+ *   mesh   mesh and degree (order 0 or 1)
+ *   phase  HOST array of nx*ny*nz bytes, x fastest: 0 = pore voxel
+ *          (electrolyte only, no reactions), 1 = cathode structure voxel
+ *          (Eq. 57 localisation); copied, may be freed after the call
+ *   params parameters (copied)
+ *   out    receives the context
+ * Errors: DG_EINVAL (null pointer, non-positive size, phase not 0/1),
+ * DG_EUNSUPPORTED (order), DG_ENOMEM, DG_EHIP. */
+int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params,
+             dg_ctx** out);
+
+/* Free the context and its device tables (never the caller's arrays). */
+int dg_destroy(dg_ctx* ctx);
+
+/* Derived scalars of the context (host): dPhi0 = V of Tab. InitialState,
+ * the equilibrium concentrations c0[6], U0[6] (U0_5, U0_6 recomputed from
+ * Tab. InitialState), the applied current j_el [A/m^2] and eps_struct. */
+int dg_info(const dg_ctx* ctx, double* V, double* c0, double* U0, double* j_el,
+            double* eps_struct);
+
+/* Old mass of a state (Eq. 50 with Eq. 16a/17a time derivatives):
+ *   m[i] = eps_L c_i (i = 0..5),  m[6 + s] = eps_s (s = 0, 1)
+ * u: device, 9 fields; m: device, 8 fields; same precision. */
+int dg_mass(dg_ctx* ctx, dg_prec prec, const void* u, void* m, dg_stream stream);
+
+/* DG residual of the backward-Euler step ending at t_new [s] with step dt:
+ *   species i: W (eps_L c_i - m_i)/dt + transport_i - W S_i - separator inflow
+ *   charge:    transport_Phi - W S_Phi - separator current
+ *   solids s:  W ((rho/M)_s (eps_s - m_{6+s})/dt - S_s)
+ * (Eq. 43-47 and 50; W = nodal quadrature weight times (h/2)^3).
+ * u: device, 9 fields; m_old: device, 8 fields from dg_mass of the old
+ * state; r: device, 9 fields.  T_H is evaluated at t_new. */
+int dg_residual(dg_ctx* ctx, dg_prec prec, const void* u, const void* m_old,
+                double t_new, double dt, void* r, dg_stream stream);
+
+/* Human-readable description of the last error on this thread. */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSBDG_H */

@@ -1,0 +1,203 @@
+// Q1 (trilinear, 2x2x2 Gauss-Legendre nodes) DG residual on gfx950.
+//
+// Work decomposition: one lane per DG node, eight consecutive lanes per
+// voxel (lane & 7 = node index n = a0 + 2 a1 + 4 a2).  Along axis d the two
+// nodes of a line differ in bit d of n, so every line partner is the lane
+// n ^ (1 << d) of the same 8-lane group and line gradients, traces and the
+// two-node face distribution are single cross-lane swizzles.
+//
+// Q1 facts used (nodes at xi = -+1/sqrt(3), weights 1):
+//   line derivative  d/dx = sqrt(3)/h (u_1 - u_0) at both nodes of the line;
+//   trace at the near face = lam1 u_near + lam0 u_far,
+//   lam1 = (1 + sqrt(3))/2, lam0 = (1 - sqrt(3))/2;
+//   grad phi_a . e_d at either node of a's d-line = sqrt(3)/h sgn(a_d).
+// Each lane evaluates the single face point on its own normal line at its
+// own side of the voxel, so the 8 lanes cover the 6 faces x 4 points.
+//
+// Residual rows (Eq. 43-47, 50): see include/lsbdg.h.  Face flux seen from
+// the element with outward normal n = s e_d:
+//   q = -1/2 s (F^- + F^+)_d + sigma/h [ {D}_H (c^- - c^+) + {M}_H (Phi^- - Phi^+) ]
+// with every coefficient taken from the traced state on its own side.
+// Because D_i = D0_i f, M_i = z_i F/RT D0_i f c_i, K_j = z_j F (D0_j - D0_A) f
+// and kappa = F^2/RT f sum_j wL_j c_j, the harmonic means factor as
+// D0_i H(f^-, f^+), z_i F/RT D0_i H(f^- c^-, f^+ c^+), etc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "model.hpp"
+#include "pointwise.hpp"
+
+namespace lsbdg {
+
+constexpr double kSqrt3 = 1.7320508075688772;
+constexpr double kLam1 = 0.5 * (1.0 + kSqrt3);
+constexpr double kLam0 = 0.5 * (1.0 - kSqrt3);
+
+// XCD-aware block order: the grid is a multiple of 8 blocks; hardware
+// dispatches block b to XCD b % 8, so each XCD receives a contiguous range
+// of voxels and their face neighbours hit that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks_padded) {
+  const int64_t b = blockIdx.x;
+  const int64_t per = nblocks_padded / 8;
+  return (b % 8) * per + b / 8;
+}
+
+template <typename T>
+__device__ __forceinline__ T xlane(T v, int mask) { return __shfl_xor(v, mask); }
+
+// Volume flux components (species 0..5 and charge) along one axis at a node
+// with transport factor f, nodal state u and line gradients g[0..6].
+template <typename T>
+__device__ __forceinline__ void axis_flux(const DevParams& P, T f, const T* u, const T* g, T* out) {
+  const T frt = T(P.frt);
+  T lam = T(0), sdiff = T(0);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    out[j] = T(P.D0[j]) * f * (g[j] + T(kZ[j]) * frt * u[j] * g[6]);
+    lam += T(P.wL[j]) * u[j];
+    sdiff += T(P.zDA[j]) * g[j];
+  }
+  out[6] = f * T(P.F) * (sdiff + frt * lam * g[6]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+resid_q1_kernel(const T* __restrict__ U, const T* __restrict__ M, T* __restrict__ R,
+                const uint8_t* __restrict__ phase, DevParams P, int64_t nblocks_padded) {
+  const int64_t blk = xcd_block(nblocks_padded);
+  const int64_t gid = blk * 256 + threadIdx.x;
+  const int64_t Ne = P.Ne;
+  const int64_t e = gid >> 3;
+  if (e >= Ne) return;                       // whole 8-lane groups leave together
+  const int n = int(gid & 7);
+  const int64_t FS = Ne * 8;                 // field stride
+  const int ix = int(e % P.nx);
+  const int iy = int((e / P.nx) % P.ny);
+  const int iz = int(e / (int64_t(P.nx) * P.ny));
+  const int ph = phase[e];
+
+  T u[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) u[f] = U[f * FS + e * 8 + n];
+
+  const T epsCBD = T(P.epsCBD[ph]);
+  const T eL = liquid_fraction(epsCBD, u[7], u[8], T(P.epsL_min));
+  const T fN = transport_factor(u, eL);
+  const T W3 = T(P.W3), W2 = T(P.W2), sq3h = T(P.sq3_h), sigh = T(P.sig_h);
+  const T lam1 = T(kLam1), lam0 = T(kLam0);
+
+  T r[9];
+  {
+    const T idt = T(P.inv_dt);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r[i] = W3 * (eL * u[i] - M[i * FS + e * 8 + n]) * idt;
+    r[6] = T(0);
+    r[7] = W3 * T(P.rhoM[0]) * (u[7] - M[6 * FS + e * 8 + n]) * idt;
+    r[8] = W3 * T(P.rhoM[1]) * (u[8] - M[7 * FS + e * 8 + n]) * idt;
+  }
+
+  const int coord[3] = {ix, iy, iz};
+  const int ncell[3] = {P.nx, P.ny, P.nz};
+  const int64_t stride[3] = {1, int64_t(P.nx), int64_t(P.nx) * P.ny};
+
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int mask = 1 << d;
+    const bool hi = (n & mask) != 0;
+    const T sgn = hi ? T(1) : T(-1);
+    T up[9];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) up[f] = xlane(u[f], mask);
+    T g[7];
+#pragma unroll
+    for (int f = 0; f < 7; ++f) g[f] = sq3h * (hi ? u[f] - up[f] : up[f] - u[f]);
+
+    // volume term along d: sqrt(3)/h sgn(a_d) W3 (F_d(a) + F_d(a'))
+    {
+      T Fd[7];
+      axis_flux(P, fN, u, g, Fd);
+#pragma unroll
+      for (int f = 0; f < 7; ++f) r[f] += sq3h * sgn * W3 * (Fd[f] + xlane(Fd[f], mask));
+    }
+
+    // face point on this lane's line at its own side s = sgn
+    T q[7];
+#pragma unroll
+    for (int f = 0; f < 7; ++f) q[f] = T(0);
+    const int cn = coord[d] + (hi ? 1 : -1);
+    if (cn >= 0 && cn < ncell[d]) {
+      const int64_t e2 = e + (hi ? stride[d] : -stride[d]);
+      const int ph2 = phase[e2];
+      T tm[9], tp[9], gp[7];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) {
+        const T vn = U[f * FS + e2 * 8 + (n ^ mask)];   // neighbour node nearest the face
+        const T vf = U[f * FS + e2 * 8 + n];            // neighbour node on the far side
+        tm[f] = lam1 * u[f] + lam0 * up[f];
+        tp[f] = lam1 * vn + lam0 * vf;
+        if (f < 7) gp[f] = sq3h * (hi ? vf - vn : vn - vf);
+      }
+      const T fm = transport_factor(tm, liquid_fraction(epsCBD, tm[7], tm[8], T(P.epsL_min)));
+      const T fp = transport_factor(tp, liquid_fraction(T(P.epsCBD[ph2]), tp[7], tp[8], T(P.epsL_min)));
+      const T Hf = harm(fm, fp);
+      const T frt = T(P.frt);
+      const T dphi = tm[6] - tp[6];
+      T lamm = T(0), lamp = T(0), sdm = T(0), sdp = T(0), pen6 = T(0);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const T D0 = T(P.D0[i]);
+        const T z = T(kZ[i]);
+        const T Fm = fm * (g[i] + z * frt * tm[i] * g[6]);
+        const T Fp = fp * (gp[i] + z * frt * tp[i] * gp[6]);
+        q[i] = -T(0.5) * sgn * D0 * (Fm + Fp) +
+               sigh * D0 * (Hf * (tm[i] - tp[i]) + z * frt * harm(fm * tm[i], fp * tp[i]) * dphi);
+        lamm += T(P.wL[i]) * tm[i];
+        lamp += T(P.wL[i]) * tp[i];
+        sdm += T(P.zDA[i]) * g[i];
+        sdp += T(P.zDA[i]) * gp[i];
+        pen6 += T(P.zDA[i]) * (tm[i] - tp[i]);
+      }
+      const T Fq = T(P.F);
+      const T Gm = fm * Fq * (sdm + frt * lamm * g[6]);
+      const T Gp = fp * Fq * (sdp + frt * lamp * gp[6]);
+      q[6] = -T(0.5) * sgn * (Gm + Gp) +
+             sigh * Fq * (Hf * pen6 + frt * harm(fm * lamm, fp * lamp) * dphi);
+    } else if (d == 0 && hi) {
+      // separator face x = L_x: inward Li+ flux j_el/F and ionic current j_el
+      q[0] = -T(P.jel) / T(P.F);
+      q[6] = -T(P.jel);
+    }
+#pragma unroll
+    for (int f = 0; f < 7; ++f) r[f] += W2 * (lam1 * q[f] + lam0 * xlane(q[f], mask));
+  }
+
+  if (P.react[ph] != 0.0) {
+    T S[9];
+    node_sources(P, ph, u, S);
+#pragma unroll
+    for (int f = 0; f < 9; ++f) r[f] -= W3 * S[f];
+  }
+#pragma unroll
+  for (int f = 0; f < 9; ++f) R[f * FS + e * 8 + n] = r[f];
+}
+
+// Old mass: m[i] = eps_L c_i (i < 6), m[6 + s] = eps_s.
+template <typename T>
+__global__ void __launch_bounds__(256)
+mass_kernel(const T* __restrict__ U, T* __restrict__ M, const uint8_t* __restrict__ phase,
+            DevParams P, int np) {
+  const int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t FS = P.Ne * np;
+  if (gid >= FS) return;
+  const int64_t e = gid / np;
+  const int ph = phase[e];
+  const T e7 = U[7 * FS + gid], e8 = U[8 * FS + gid];
+  const T eL = liquid_fraction(T(P.epsCBD[ph]), e7, e8, T(P.epsL_min));
+#pragma unroll
+  for (int i = 0; i < 6; ++i) M[i * FS + gid] = eL * U[i * FS + gid];
+  M[6 * FS + gid] = e7;
+  M[7 * FS + gid] = e8;
+}
+
+}  // namespace lsbdg

@@ -1,0 +1,196 @@
+"""ctypes binding of liblsbdg (include/lsbdg.h), argument marshalling only.
+
+Every computation happens in the HIP library.  Arrays are torch device
+tensors in the field-major layout a[f][e][n]; the current torch stream is
+passed to each call.  A missing library raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsbdg.so")
+
+DG_F64, DG_F32 = 0, 1
+
+_STATUS = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_ENOCONV",
+           -5: "DG_ENAN", -6: "DG_ESTATE", -7: "DG_EUNSUPPORTED"}
+
+# exported entry points and their ctypes signatures
+_SIGNATURES = {
+    "dg_params_default": (None, [C.c_void_p]),
+    "dg_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dg_destroy": (C.c_int, [C.c_void_p]),
+    "dg_info": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5),
+    "dg_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                              C.c_double, C.c_void_p, C.c_void_p]),
+    "dg_last_error": (C.c_char_p, []),
+}
+
+
+class DgMesh(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("order", C.c_int32), ("h", C.c_double)]
+
+
+class DgParams(C.Structure):
+    _fields_ = [("T", C.c_double), ("D0", C.c_double * 7), ("kE", C.c_double * 6),
+                ("f_C", C.c_double), ("j_el", C.c_double), ("eps_struct", C.c_double),
+                ("sigma", C.c_double), ("c_min", C.c_double), ("epsL_min", C.c_double),
+                ("use_TH", C.c_int32), ("reserved", C.c_int32)]
+
+
+class DgError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed: {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblsbdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2511_05233_amd.build)")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _check(fn, code):
+    if code != 0:
+        raise DgError(fn, code, _lib.dg_last_error().decode())
+
+
+def _ptr(t):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("arrays must be HIP device tensors")
+    if not t.is_contiguous():
+        raise ValueError("arrays must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _prec(t):
+    import torch
+    if t.dtype == torch.float64:
+        return DG_F64
+    if t.dtype == torch.float32:
+        return DG_F32
+    raise ValueError(f"unsupported dtype {t.dtype}")
+
+
+def default_params():
+    lib = load()
+    p = DgParams()
+    lib.dg_params_default(C.byref(p))
+    return p
+
+
+class Context:
+    """One voxel structure: mesh, phase map and parameters on the device."""
+
+    def __init__(self, nx, ny, nz, h, order, phase, D0=None, kE=None, f_C=None, j_el=None,
+                 eps_struct=None, sigma=None, use_TH=None, T=None):
+        lib = load()
+        self.nx, self.ny, self.nz, self.h, self.order = int(nx), int(ny), int(nz), float(h), int(order)
+        self.n_elem = self.nx * self.ny * self.nz
+        self.n_nodes = (self.order + 1) ** 3
+        ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8).reshape(-1))
+        if ph.size != self.n_elem:
+            raise ValueError("phase map size does not match the mesh")
+        p = default_params()
+        if D0 is not None:
+            p.D0[:] = [float(x) for x in D0]
+        if kE is not None:
+            p.kE[:] = [float(x) for x in kE]
+        if f_C is not None:
+            p.f_C = float(f_C)
+        if j_el is not None:
+            p.j_el = float(j_el)
+        if eps_struct is not None:
+            p.eps_struct = float(eps_struct)
+        if sigma is not None:
+            p.sigma = float(sigma)
+        if use_TH is not None:
+            p.use_TH = int(bool(use_TH))
+        if T is not None:
+            p.T = float(T)
+        self.params = p
+        mesh = DgMesh(self.nx, self.ny, self.nz, self.order, self.h)
+        handle = C.c_void_p()
+        _check("dg_setup", lib.dg_setup(C.byref(mesh), ph.ctypes.data_as(C.c_void_p),
+                                        C.byref(p), C.byref(handle)))
+        self._h = handle
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        V = C.c_double()
+        c0 = (C.c_double * 6)()
+        U0 = (C.c_double * 6)()
+        j = C.c_double()
+        es = C.c_double()
+        _check("dg_info", self._lib.dg_info(self._h, C.byref(V), c0, U0, C.byref(j), C.byref(es)))
+        return {"V": V.value, "c0": np.array(c0[:]), "U0": np.array(U0[:]),
+                "j_el": j.value, "eps_struct": es.value}
+
+    def _shape(self, nf):
+        return (nf, self.n_elem, self.n_nodes)
+
+    def _check_arr(self, t, nf):
+        if tuple(t.shape) != self._shape(nf):
+            raise ValueError(f"expected shape {self._shape(nf)}, got {tuple(t.shape)}")
+
+    def mass(self, u, out=None):
+        import torch
+        self._check_arr(u, 9)
+        if out is None:
+            out = torch.empty(self._shape(8), dtype=u.dtype, device=u.device)
+        self._check_arr(out, 8)
+        _check("dg_mass", self._lib.dg_mass(self._h, _prec(u), _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def residual(self, u, m_old, t_new, dt, out=None):
+        import torch
+        self._check_arr(u, 9)
+        self._check_arr(m_old, 8)
+        if m_old.dtype != u.dtype:
+            raise ValueError("u and m_old must share a dtype")
+        if out is None:
+            out = torch.empty(self._shape(9), dtype=u.dtype, device=u.device)
+        self._check_arr(out, 9)
+        _check("dg_residual", self._lib.dg_residual(self._h, _prec(u), _ptr(u), _ptr(m_old),
+                                                    float(t_new), float(dt), _ptr(out), _stream()))
+        return out
