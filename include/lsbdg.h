@@ -62,6 +62,13 @@ typedef enum {
 
 typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_prec;
 
+/* Jacobian-vector product modes.
+ *   DG_JVP_FULL9:      v and J v over all 9 fields.
+ *   DG_JVP_CONDENSED7: v and J v over the 7 transported fields; the solid
+ *     fractions are eliminated node by node (their rows hold no spatial
+ *     coupling): J_red v = J_uu v + J_ue w with w = -J_ee^-1 J_eu v. */
+typedef enum { DG_JVP_FULL9 = 0, DG_JVP_CONDENSED7 = 1 } dg_jvp_mode;
+
 /* Mesh: voxel counts, voxel edge h [m], polynomial degree per axis. */
 typedef struct {
   int32_t nx, ny, nz;
@@ -126,6 +133,35 @@ int dg_mass(dg_ctx* ctx, dg_prec prec, const void* u, void* m, dg_stream stream)
  * state; r: device, 9 fields.  T_H is evaluated at t_new. */
 int dg_residual(dg_ctx* ctx, dg_prec prec, const void* u, const void* m_old,
                 double t_new, double dt, void* r, dg_stream stream);
+
+/* Jacobian-vector product of dg_residual at (u, t_new, dt) in direction v:
+ * the exact derivative of the same arithmetic (forward-mode dual numbers),
+ * with zero derivative where a clamp is active.  The old mass does not
+ * enter.  u: device, 9 fields; v and jv: device, 9 fields (DG_JVP_FULL9) or
+ * 7 fields (DG_JVP_CONDENSED7); all in the precision prec. */
+int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const void* v,
+           double t_new, double dt, void* jv, dg_stream stream);
+
+/* Element block-Jacobi preconditioner (replaces the paper's BoomerAMG
+ * preconditioner of Sec. 2.8 inside GMRES).  Builds the exact
+ * element-diagonal blocks of the condensed 7-field Jacobian at (u, t_new,
+ * dt) -- volume, own-face, time and source terms of each voxel's rows with
+ * respect to its own 56 unknowns (Q1) -- and inverts them in place (Gauss-
+ * Jordan with partial pivoting) into library-owned device storage of
+ * Ne * 56 * 56 values of precision prec (FP32 at the 96x96x192 slab: 22 GB).
+ * Synchronises the stream.  DG_ENAN if a block is singular or not finite;
+ * DG_EUNSUPPORTED for orders other than 1. */
+int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt,
+                         dg_stream stream);
+
+/* y_e = B_e^{-1} x_e for every voxel e, with the blocks of the last setup.
+ * x, y: device, 7 fields, precision of the setup (DG_EINVAL otherwise;
+ * DG_ESTATE before any setup). x and y must not overlap. */
+int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_stream stream);
+
+/* Copy the stored inverse blocks (Ne blocks of 56 x 56, column-major:
+ * out[e][col][row], row/col = field * 8 + node) to the device buffer out. */
+int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream);
 
 /* Human-readable description of the last error on this thread. */
 const char* dg_last_error(void);

@@ -1,0 +1,176 @@
+// Element block-Jacobi preconditioner for the Q1 operator on gfx950.
+//
+// Assembly: the element-diagonal block J_EE of the (condensed) Jacobian is
+// the tangent of the element's own rows with respect to its own unknowns,
+// every neighbour held fixed.  Column j is the dual-number evaluation of
+// the Q1 operator body seeded with the unit direction e_j on this element
+// and zero on its neighbours.  Block index = field * 8 + node; storage is
+// column-major per element, B[e][col][row].
+//
+// Inversion: one wavefront per element, lane i holds row i in registers.
+// In-place Gauss-Jordan with partial pivoting and no physical row swaps:
+// at step k the unused row p with the largest |a_ik| becomes the pivot of
+// column k, its row is broadcast with readlane, every other row is
+// eliminated, and column k is replaced by the corresponding column of the
+// partial inverse.  Rotating each row left by one after every step keeps
+// the active column at register 0, so no register is indexed dynamically.
+// With pivot rows p_0..p_{n-1} the result B satisfies
+//     A^{-1}[k][p_m] = B[p_k][m],
+// which the write-out applies.
+//
+// Apply: y_e = B_e^{-1} x_e, one wavefront per element, lane r = row r,
+// columns streamed with one coalesced load each.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dual.hpp"
+#include "resid_q1.hpp"
+
+namespace lsbdg {
+
+__device__ __forceinline__ float bcast(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double bcast(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Element-diagonal blocks.  Mode kJvpFull (9 fields, nb = 72) or
+// kJvpCondensed (7 fields, nb = 56).  One lane per node, as q1_kernel.
+template <typename S, int Mode>
+__global__ void __launch_bounds__(256)
+q1_block_kernel(const S* __restrict__ U, S* __restrict__ Bout, const uint8_t* __restrict__ phase,
+                DevParams P, int64_t nblocks_padded) {
+  using N = Dual<S>;
+  constexpr int NF = (Mode == kJvpFull) ? 9 : 7;
+  constexpr int NB = NF * 8;
+  const int64_t blk = xcd_block(nblocks_padded);
+  const int64_t gid = blk * 256 + threadIdx.x;
+  const int64_t Ne = P.Ne;
+  const int64_t e = gid >> 3;
+  if (e >= Ne) return;
+  const int n = int(gid & 7);
+  const int64_t FS = Ne * 8;
+  const int ix = int(e % P.nx);
+  const int iy = int((e / P.nx) % P.ny);
+  const int iz = int(e / (int64_t(P.nx) * P.ny));
+  const int ph = phase[e];
+  S us[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) us[f] = U[f * FS + e * 8 + n];
+  S* Be = Bout + e * int64_t(NB) * NB;
+
+#pragma unroll 1
+  for (int col = 0; col < NB; ++col) {
+    const int fj = col >> 3, nj = col & 7;
+    N u[9];
+    {
+      S vs[9];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) vs[f] = (f == fj && n == nj) ? S(1) : S(0);
+      if constexpr (Mode == kJvpCondensed) {
+        S w0, w1;
+        condense_solids(P, ph, us, vs, w0, w1);
+        vs[7] = w0;
+        vs[8] = w1;
+      }
+#pragma unroll
+      for (int f = 0; f < 9; ++f) u[f] = N(us[f], vs[f]);
+    }
+    N r[9];
+    q1_rows<S, N, kJvpFull, true>(U, nullptr, nullptr, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Be[col * NB + f * 8 + n] = r[f].d;
+  }
+}
+
+// Wave-wide argmax of a non-negative key (-1 = excluded); returns the lane.
+__device__ __forceinline__ int wave_argmax(float key, int lane) {
+  float k = key;
+  int l = lane;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float ok = __shfl_xor(k, off);
+    const int ol = __shfl_xor(l, off);
+    if (ok > k || (ok == k && ol < l)) {
+      k = ok;
+      l = ol;
+    }
+  }
+  return l;
+}
+
+// In-place inversion of every element block (see header comment).  A block
+// whose best available pivot is zero or not finite sets *status = 1.
+template <typename S, int NB>
+__global__ void __launch_bounds__(256)
+invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status) {
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t e = int64_t(blockIdx.x) * 4 + w;
+  if (e >= Ne) return;                       // whole wavefronts leave together
+  const bool act = lane < NB;
+  S* Be = B + e * int64_t(NB) * NB;
+  S r[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) r[j] = act ? Be[j * NB + lane] : S(0);
+  bool used = !act;
+  int kk = 0;        // step at which this lane's row was the pivot
+  int mypiv = 0;     // lane m keeps the pivot row of step m
+  bool bad = false;
+#pragma unroll 1
+  for (int k = 0; k < NB; ++k) {
+    const float key = used ? -1.0f : float(fabs(r[0]));
+    const int p = wave_argmax(key, lane);
+    const S pv = bcast(r[0], p);
+    if (!(fabs(pv) > S(0)) || !isfinite(pv)) bad = true;
+    if (lane == k) mypiv = p;
+    if (lane == p) {
+      used = true;
+      kk = k;
+    }
+    const S inv = S(1) / pv;
+    const S f = r[0];
+#pragma unroll
+    for (int j = 1; j < NB; ++j) {
+      const S prow = bcast(r[j], p) * inv;
+      r[j - 1] = (lane == p) ? prow : r[j] - f * prow;
+    }
+    r[NB - 1] = (lane == p) ? inv : -f * inv;
+  }
+  if (bad && lane == 0) atomicOr(status, 1);
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    const int pm = __builtin_amdgcn_readlane(mypiv, m);
+    if (act) Be[pm * NB + kk] = r[m];
+  }
+}
+
+// y_e = B_e x_e for vectors in the field-major layout [f][e][n] (NF fields).
+template <typename S, int NF>
+__global__ void __launch_bounds__(256)
+apply_blocks_kernel(const S* __restrict__ B, const S* __restrict__ X, S* __restrict__ Y, int64_t Ne) {
+  constexpr int NB = NF * 8;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t e = int64_t(blockIdx.x) * 4 + w;
+  if (e >= Ne) return;
+  const int64_t FS = Ne * 8;
+  const bool act = lane < NB;
+  const int fl = lane >> 3, nl = lane & 7;
+  const S xl = act ? X[fl * FS + e * 8 + nl] : S(0);
+  const S* Be = B + e * int64_t(NB) * NB;
+  S acc = S(0);
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const S bc = act ? Be[c * NB + lane] : S(0);
+    acc += bc * bcast(xl, c);
+  }
+  if (act) Y[fl * FS + e * 8 + nl] = acc;
+}
+
+}  // namespace lsbdg

@@ -17,6 +17,7 @@
 #include "model.hpp"
 #include "pointwise.hpp"
 #include "resid_q1.hpp"
+#include "blockjacobi.hpp"
 
 using namespace lsbdg;
 
@@ -31,6 +32,11 @@ struct dg_ctx {
   int64_t Ne = 0;
   int np = 1;
   uint8_t* d_phase = nullptr;
+  // element block-Jacobi storage (condensed 56 x 56 inverses, column-major)
+  void* d_blocks = nullptr;
+  size_t blocks_bytes = 0;
+  int blocks_prec = -1;
+  int* d_status = nullptr;
 };
 
 namespace {
@@ -97,6 +103,22 @@ DevParams make_params(const dg_ctx* c, double t_eval, double dt) {
 int check_ctx(const dg_ctx* c) {
   if (!c) return fail(DG_EINVAL, "null context");
   return DG_OK;
+}
+
+}  // namespace
+
+namespace {
+
+template <typename S, typename N, int Mode>
+void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void* v, const void* m,
+               void* out, hipStream_t st) {
+  const int64_t threads = ctx->Ne * 8;
+  int64_t nb = (threads + 255) / 256;
+  nb = (nb + 7) / 8 * 8;
+  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
+  hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
+                     static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
+                     ctx->d_phase, P, nb);
 }
 
 }  // namespace
@@ -188,6 +210,8 @@ int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params,
 int dg_destroy(dg_ctx* ctx) {
   if (!ctx) return DG_OK;
   if (ctx->d_phase) (void)hipFree(ctx->d_phase);
+  if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
   delete ctx;
   return DG_OK;
 }
@@ -229,22 +253,126 @@ int dg_residual(dg_ctx* ctx, dg_prec prec, const void* u, const void* m_old, dou
   if (!u || !m_old || !r) return fail(DG_EINVAL, "dg_residual: null array");
   if (!(dt > 0)) return fail(DG_EINVAL, "dg_residual: dt must be positive");
   const DevParams P = make_params(ctx, t_new, dt);
-  const int64_t threads = ctx->Ne * 8;
-  int64_t nb = (threads + 255) / 256;
-  nb = (nb + 7) / 8 * 8;
-  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (prec == DG_F64)
-    hipLaunchKernelGGL(resid_q1_kernel<double>, grid, block, 0, st,
-                       static_cast<const double*>(u), static_cast<const double*>(m_old),
-                       static_cast<double*>(r), ctx->d_phase, P, nb);
+    launch_q1<double, double, kResidual>(ctx, P, u, nullptr, m_old, r, st);
   else if (prec == DG_F32)
-    hipLaunchKernelGGL(resid_q1_kernel<float>, grid, block, 0, st,
-                       static_cast<const float*>(u), static_cast<const float*>(m_old),
-                       static_cast<float*>(r), ctx->d_phase, P, nb);
+    launch_q1<float, float, kResidual>(ctx, P, u, nullptr, m_old, r, st);
   else
     return fail(DG_EINVAL, "dg_residual: bad precision");
   DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const void* v,
+           double t_new, double dt, void* jv, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!u || !v || !jv) return fail(DG_EINVAL, "dg_jvp: null array");
+  if (!(dt > 0)) return fail(DG_EINVAL, "dg_jvp: dt must be positive");
+  const DevParams P = make_params(ctx, t_new, dt);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (mode == DG_JVP_FULL9) {
+    if (prec == DG_F64)
+      launch_q1<double, Dual<double>, kJvpFull>(ctx, P, u, v, nullptr, jv, st);
+    else if (prec == DG_F32)
+      launch_q1<float, Dual<float>, kJvpFull>(ctx, P, u, v, nullptr, jv, st);
+    else
+      return fail(DG_EINVAL, "dg_jvp: bad precision");
+  } else if (mode == DG_JVP_CONDENSED7) {
+    if (prec == DG_F64)
+      launch_q1<double, Dual<double>, kJvpCondensed>(ctx, P, u, v, nullptr, jv, st);
+    else if (prec == DG_F32)
+      launch_q1<float, Dual<float>, kJvpCondensed>(ctx, P, u, v, nullptr, jv, st);
+    else
+      return fail(DG_EINVAL, "dg_jvp: bad precision");
+  } else {
+    return fail(DG_EINVAL, "dg_jvp: bad mode");
+  }
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+
+constexpr int kNB = 56;   // condensed Q1 block size: 7 fields x 8 nodes
+
+int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt,
+                         dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!u) return fail(DG_EINVAL, "dg_blockjacobi_setup: null array");
+  if (!(dt > 0)) return fail(DG_EINVAL, "dg_blockjacobi_setup: dt must be positive");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_blockjacobi_setup: bad precision");
+  const size_t esz = prec == DG_F64 ? sizeof(double) : sizeof(float);
+  const size_t need = size_t(ctx->Ne) * kNB * kNB * esz;
+  if (ctx->blocks_bytes < need) {
+    if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
+    ctx->d_blocks = nullptr;
+    ctx->blocks_bytes = 0;
+    hipError_t err = hipMalloc(&ctx->d_blocks, need);
+    if (err != hipSuccess)
+      return fail(DG_ENOMEM, std::string("dg_blockjacobi_setup: hipMalloc of ") +
+                                 std::to_string(need) + " bytes: " + hipGetErrorString(err));
+    ctx->blocks_bytes = need;
+  }
+  if (!ctx->d_status) {
+    hipError_t err = hipMalloc(&ctx->d_status, sizeof(int));
+    if (err != hipSuccess) return fail(DG_ENOMEM, "dg_blockjacobi_setup: status allocation");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DG_HIP(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+  const DevParams P = make_params(ctx, t_new, dt);
+  int64_t nb = (ctx->Ne * 8 + 255) / 256;
+  nb = (nb + 7) / 8 * 8;
+  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
+  const dim3 grid_w{unsigned((ctx->Ne + 3) / 4), 1, 1};
+  if (prec == DG_F64) {
+    hipLaunchKernelGGL((q1_block_kernel<double, kJvpCondensed>), grid, block, 0, st,
+                       static_cast<const double*>(u), static_cast<double*>(ctx->d_blocks),
+                       ctx->d_phase, P, nb);
+    hipLaunchKernelGGL((invert_blocks_kernel<double, kNB>), grid_w, block, 0, st,
+                       static_cast<double*>(ctx->d_blocks), ctx->Ne, ctx->d_status);
+  } else {
+    hipLaunchKernelGGL((q1_block_kernel<float, kJvpCondensed>), grid, block, 0, st,
+                       static_cast<const float*>(u), static_cast<float*>(ctx->d_blocks),
+                       ctx->d_phase, P, nb);
+    hipLaunchKernelGGL((invert_blocks_kernel<float, kNB>), grid_w, block, 0, st,
+                       static_cast<float*>(ctx->d_blocks), ctx->Ne, ctx->d_status);
+  }
+  DG_HIP(hipGetLastError());
+  int h_status = 0;
+  DG_HIP(hipMemcpyAsync(&h_status, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipStreamSynchronize(st));
+  ctx->blocks_prec = int(prec);
+  if (h_status) return fail(DG_ENAN, "dg_blockjacobi_setup: singular or non-finite element block");
+  return DG_OK;
+}
+
+int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!x || !y) return fail(DG_EINVAL, "dg_blockjacobi_apply: null array");
+  if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_apply: no setup yet");
+  if (int(prec) != ctx->blocks_prec)
+    return fail(DG_EINVAL, "dg_blockjacobi_apply: precision differs from the setup");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid{unsigned((ctx->Ne + 3) / 4), 1, 1}, block{256, 1, 1};
+  if (prec == DG_F64)
+    hipLaunchKernelGGL((apply_blocks_kernel<double, 7>), grid, block, 0, st,
+                       static_cast<const double*>(ctx->d_blocks), static_cast<const double*>(x),
+                       static_cast<double*>(y), ctx->Ne);
+  else
+    hipLaunchKernelGGL((apply_blocks_kernel<float, 7>), grid, block, 0, st,
+                       static_cast<const float*>(ctx->d_blocks), static_cast<const float*>(x),
+                       static_cast<float*>(y), ctx->Ne);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!out) return fail(DG_EINVAL, "dg_blockjacobi_export: null array");
+  if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_export: no setup yet");
+  const size_t esz = ctx->blocks_prec == DG_F64 ? sizeof(double) : sizeof(float);
+  DG_HIP(hipMemcpyAsync(out, ctx->d_blocks, size_t(ctx->Ne) * kNB * kNB * esz,
+                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   return DG_OK;
 }
 

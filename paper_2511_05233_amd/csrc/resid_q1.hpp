@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "model.hpp"
+#include "dual.hpp"
 #include "pointwise.hpp"
 
 namespace lsbdg {
@@ -45,6 +46,10 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblocks_padded) {
 
 template <typename T>
 __device__ __forceinline__ T xlane(T v, int mask) { return __shfl_xor(v, mask); }
+template <typename S>
+__device__ __forceinline__ Dual<S> xlane(Dual<S> v, int mask) {
+  return {__shfl_xor(v.v, mask), __shfl_xor(v.d, mask)};
+}
 
 // Volume flux components (species 0..5 and charge) along one axis at a node
 // with transport factor f, nodal state u and line gradients g[0..6].
@@ -61,47 +66,104 @@ __device__ __forceinline__ void axis_flux(const DevParams& P, T f, const T* u, c
   out[6] = f * T(P.F) * (sdiff + frt * lam * g[6]);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-resid_q1_kernel(const T* __restrict__ U, const T* __restrict__ M, T* __restrict__ R,
-                const uint8_t* __restrict__ phase, DevParams P, int64_t nblocks_padded) {
-  const int64_t blk = xcd_block(nblocks_padded);
-  const int64_t gid = blk * 256 + threadIdx.x;
-  const int64_t Ne = P.Ne;
-  const int64_t e = gid >> 3;
-  if (e >= Ne) return;                       // whole 8-lane groups leave together
-  const int n = int(gid & 7);
-  const int64_t FS = Ne * 8;                 // field stride
-  const int ix = int(e % P.nx);
-  const int iy = int((e / P.nx) % P.ny);
-  const int iz = int(e / (int64_t(P.nx) * P.ny));
-  const int ph = phase[e];
+// Operator modes of the Q1 kernel.
+enum Q1Mode { kResidual = 0, kJvpFull = 1, kJvpCondensed = 2 };
 
-  T u[9];
+// Node-local elimination of the solid fractions for a direction v on the
+// transported fields: the solid rows W ((rho/M)(eps - m)/dt - S_eps) have
+// tangent zero when  A w = dS_eps/du v,  A = diag(rho/M)/dt - dS_eps/deps.
+// Returns w (the solid-fraction tangents).  Non-reactive voxels give w = 0.
+template <typename S>
+__device__ __forceinline__ void condense_solids(const DevParams& P, int ph, const S* us, const S* v7,
+                                                S& w0, S& w1) {
+  w0 = S(0);
+  w1 = S(0);
+  if (P.react[ph] == 0.0) return;
+  using D = Dual<S>;
+  D x[9], Sx[9];
 #pragma unroll
-  for (int f = 0; f < 9; ++f) u[f] = U[f * FS + e * 8 + n];
+  for (int f = 0; f < 7; ++f) x[f] = D(us[f], v7[f]);
+  x[7] = D(us[7], S(0));
+  x[8] = D(us[8], S(0));
+  node_sources(P, ph, x, Sx);
+  const S t7 = Sx[7].d, t8 = Sx[8].d;
+#pragma unroll
+  for (int f = 0; f < 7; ++f) x[f].d = S(0);
+  x[7].d = S(1);
+  node_sources(P, ph, x, Sx);
+  const S c70 = Sx[7].d, c80 = Sx[8].d;
+  x[7].d = S(0);
+  x[8].d = S(1);
+  node_sources(P, ph, x, Sx);
+  const S c71 = Sx[7].d, c81 = Sx[8].d;
+  const S idt = S(P.inv_dt);
+  const S a00 = S(P.rhoM[0]) * idt - c70, a01 = -c71;
+  const S a10 = -c80, a11 = S(P.rhoM[1]) * idt - c81;
+  const S det = a00 * a11 - a01 * a10;
+  w0 = (a11 * t7 - a01 * t8) / det;
+  w1 = (a00 * t8 - a10 * t7) / det;
+}
 
+// Load the nine unknowns of one node as operator numbers.
+template <typename S, typename N, int Mode>
+__device__ __forceinline__ void load_node(const S* __restrict__ U, const S* __restrict__ V, int64_t FS,
+                                          int64_t idx, int ph, const DevParams& P, N* x) {
+  if constexpr (Mode == kResidual) {
+#pragma unroll
+    for (int f = 0; f < 9; ++f) x[f] = U[f * FS + idx];
+  } else if constexpr (Mode == kJvpFull) {
+#pragma unroll
+    for (int f = 0; f < 9; ++f) x[f] = N(U[f * FS + idx], V[f * FS + idx]);
+  } else {
+    S us[9], vs[7];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) us[f] = U[f * FS + idx];
+#pragma unroll
+    for (int f = 0; f < 7; ++f) vs[f] = V[f * FS + idx];
+    S w0, w1;
+    condense_solids(P, ph, us, vs, w0, w1);
+#pragma unroll
+    for (int f = 0; f < 7; ++f) x[f] = N(us[f], vs[f]);
+    x[7] = N(us[7], w0);
+    x[8] = N(us[8], w1);
+  }
+}
+
+// Rows of the Q1 operator at one node (lane): residual rows (N = S) or their
+// tangents (N = Dual<S>).  u holds the lane's own nine unknowns as N.
+// Neighbour nodes are read from U (and from V in the JVP modes); with
+// kNbrZero their direction is zero (element-diagonal Jacobian blocks).
+template <typename S, typename N, int Mode, bool kNbrZero>
+__device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __restrict__ V,
+                                        const S* __restrict__ M, const uint8_t* __restrict__ phase,
+                                        const DevParams& P, int64_t e, int n, int ph, int ix, int iy,
+                                        int iz, int64_t FS, const N* u, N* r) {
+  using T = N;
   const T epsCBD = T(P.epsCBD[ph]);
   const T eL = liquid_fraction(epsCBD, u[7], u[8], T(P.epsL_min));
   const T fN = transport_factor(u, eL);
   const T W3 = T(P.W3), W2 = T(P.W2), sq3h = T(P.sq3_h), sigh = T(P.sig_h);
   const T lam1 = T(kLam1), lam0 = T(kLam0);
-
-  T r[9];
   {
     const T idt = T(P.inv_dt);
+    // the old mass is a constant of the step: it enters the residual only
 #pragma unroll
-    for (int i = 0; i < 6; ++i) r[i] = W3 * (eL * u[i] - M[i * FS + e * 8 + n]) * idt;
+    for (int i = 0; i < 6; ++i) {
+      const T mi = (Mode == kResidual) ? T(M[i * FS + e * 8 + n]) : T(0);
+      r[i] = W3 * (eL * u[i] - mi) * idt;
+    }
     r[6] = T(0);
-    r[7] = W3 * T(P.rhoM[0]) * (u[7] - M[6 * FS + e * 8 + n]) * idt;
-    r[8] = W3 * T(P.rhoM[1]) * (u[8] - M[7 * FS + e * 8 + n]) * idt;
+    const T m6 = (Mode == kResidual) ? T(M[6 * FS + e * 8 + n]) : T(0);
+    const T m7 = (Mode == kResidual) ? T(M[7 * FS + e * 8 + n]) : T(0);
+    r[7] = W3 * T(P.rhoM[0]) * (u[7] - m6) * idt;
+    r[8] = W3 * T(P.rhoM[1]) * (u[8] - m7) * idt;
   }
 
   const int coord[3] = {ix, iy, iz};
   const int ncell[3] = {P.nx, P.ny, P.nz};
   const int64_t stride[3] = {1, int64_t(P.nx), int64_t(P.nx) * P.ny};
 
-#pragma unroll
+#pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     const int mask = 1 << d;
     const bool hi = (n & mask) != 0;
@@ -130,13 +192,25 @@ resid_q1_kernel(const T* __restrict__ U, const T* __restrict__ M, T* __restrict_
       const int64_t e2 = e + (hi ? stride[d] : -stride[d]);
       const int ph2 = phase[e2];
       T tm[9], tp[9], gp[7];
+      {
+        T vn[9], vf[9];
+        const int64_t in_ = e2 * 8 + (n ^ mask), if_ = e2 * 8 + n;   // nearest the face, far side
+        if constexpr (kNbrZero) {
 #pragma unroll
-      for (int f = 0; f < 9; ++f) {
-        const T vn = U[f * FS + e2 * 8 + (n ^ mask)];   // neighbour node nearest the face
-        const T vf = U[f * FS + e2 * 8 + n];            // neighbour node on the far side
-        tm[f] = lam1 * u[f] + lam0 * up[f];
-        tp[f] = lam1 * vn + lam0 * vf;
-        if (f < 7) gp[f] = sq3h * (hi ? vf - vn : vn - vf);
+          for (int f = 0; f < 9; ++f) {
+            vn[f] = T(U[f * FS + in_]);
+            vf[f] = T(U[f * FS + if_]);
+          }
+        } else {
+          load_node<S, N, Mode>(U, V, FS, in_, ph2, P, vn);
+          load_node<S, N, Mode>(U, V, FS, if_, ph2, P, vf);
+        }
+#pragma unroll
+        for (int f = 0; f < 9; ++f) {
+          tm[f] = lam1 * u[f] + lam0 * up[f];
+          tp[f] = lam1 * vn[f] + lam0 * vf[f];
+          if (f < 7) gp[f] = sq3h * (hi ? vf[f] - vn[f] : vn[f] - vf[f]);
+        }
       }
       const T fm = transport_factor(tm, liquid_fraction(epsCBD, tm[7], tm[8], T(P.epsL_min)));
       const T fp = transport_factor(tp, liquid_fraction(T(P.epsCBD[ph2]), tp[7], tp[8], T(P.epsL_min)));
@@ -173,13 +247,42 @@ resid_q1_kernel(const T* __restrict__ U, const T* __restrict__ M, T* __restrict_
   }
 
   if (P.react[ph] != 0.0) {
-    T S[9];
-    node_sources(P, ph, u, S);
+    T Sx[9];
+    node_sources(P, ph, u, Sx);
 #pragma unroll
-    for (int f = 0; f < 9; ++f) r[f] -= W3 * S[f];
+    for (int f = 0; f < 9; ++f) r[f] -= W3 * Sx[f];
   }
+}
+
+// Q1 operator: residual (Mode 0, N = S) or Jacobian-vector product (Modes 1
+// and 2, N = Dual<S>, output = derivative part).
+template <typename S, typename N, int Mode>
+__global__ void __launch_bounds__(256)
+q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
+          S* __restrict__ Out, const uint8_t* __restrict__ phase, DevParams P,
+          int64_t nblocks_padded) {
+  const int64_t blk = xcd_block(nblocks_padded);
+  const int64_t gid = blk * 256 + threadIdx.x;
+  const int64_t Ne = P.Ne;
+  const int64_t e = gid >> 3;
+  if (e >= Ne) return;                       // whole 8-lane groups leave together
+  const int n = int(gid & 7);
+  const int64_t FS = Ne * 8;                 // field stride
+  const int ix = int(e % P.nx);
+  const int iy = int((e / P.nx) % P.ny);
+  const int iz = int(e / (int64_t(P.nx) * P.ny));
+  const int ph = phase[e];
+  N u[9], r[9];
+  load_node<S, N, Mode>(U, V, FS, e * 8 + n, ph, P, u);
+  q1_rows<S, N, Mode, false>(U, V, M, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
+  if constexpr (Mode == kResidual) {
 #pragma unroll
-  for (int f = 0; f < 9; ++f) R[f * FS + e * 8 + n] = r[f];
+    for (int f = 0; f < 9; ++f) Out[f * FS + e * 8 + n] = r[f];
+  } else {
+    constexpr int nout = (Mode == kJvpFull) ? 9 : 7;
+#pragma unroll
+    for (int f = 0; f < nout; ++f) Out[f * FS + e * 8 + n] = deriv_of(r[f]);
+  }
 }
 
 // Old mass: m[i] = eps_L c_i (i < 6), m[6 + s] = eps_s.

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblsbdg.so")
 
 DG_F64, DG_F32 = 0, 1
+DG_JVP_FULL9, DG_JVP_CONDENSED7 = 0, 1
 
 _STATUS = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_ENOCONV",
            -5: "DG_ENAN", -6: "DG_ESTATE", -7: "DG_EUNSUPPORTED"}
@@ -28,6 +29,12 @@ _SIGNATURES = {
     "dg_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                               C.c_double, C.c_void_p, C.c_void_p]),
+    "dg_jvp": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                         C.c_double, C.c_void_p, C.c_void_p]),
+    "dg_blockjacobi_setup": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double,
+                                       C.c_void_p]),
+    "dg_blockjacobi_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_blockjacobi_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -193,4 +200,44 @@ class Context:
         self._check_arr(out, 9)
         _check("dg_residual", self._lib.dg_residual(self._h, _prec(u), _ptr(u), _ptr(m_old),
                                                     float(t_new), float(dt), _ptr(out), _stream()))
+        return out
+
+    def jvp(self, u, v, t_new, dt, out=None, condensed=False):
+        """J(u) v: 9 fields, or 7 with the solid fractions condensed out."""
+        import torch
+        nf = 7 if condensed else 9
+        self._check_arr(u, 9)
+        self._check_arr(v, nf)
+        if v.dtype != u.dtype:
+            raise ValueError("u and v must share a dtype")
+        if out is None:
+            out = torch.empty(self._shape(nf), dtype=u.dtype, device=u.device)
+        self._check_arr(out, nf)
+        mode = DG_JVP_CONDENSED7 if condensed else DG_JVP_FULL9
+        _check("dg_jvp", self._lib.dg_jvp(self._h, _prec(u), mode, _ptr(u), _ptr(v), float(t_new),
+                                          float(dt), _ptr(out), _stream()))
+        return out
+
+    def blockjacobi_setup(self, u, t_new, dt, dtype=None):
+        """Build and invert the condensed element blocks at u (precision dtype)."""
+        self._check_arr(u, 9)
+        uu = u if dtype is None or u.dtype == dtype else u.to(dtype)
+        self._bj_dtype = uu.dtype
+        _check("dg_blockjacobi_setup", self._lib.dg_blockjacobi_setup(
+            self._h, _prec(uu), _ptr(uu), float(t_new), float(dt), _stream()))
+
+    def blockjacobi_apply(self, x, out=None):
+        import torch
+        self._check_arr(x, 7)
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_arr(out, 7)
+        _check("dg_blockjacobi_apply", self._lib.dg_blockjacobi_apply(
+            self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def blockjacobi_export(self):
+        import torch
+        out = torch.empty((self.n_elem, 56, 56), dtype=self._bj_dtype, device="cuda")
+        _check("dg_blockjacobi_export", self._lib.dg_blockjacobi_export(self._h, _ptr(out), _stream()))
         return out

@@ -1,0 +1,62 @@
+"""HIP element block-Jacobi vs the oracle's probed element blocks (GPU)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dg as odg
+from oracle import solve as osolve
+from tests.helpers import problem_and_context
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _backward_error(Bor, y, x):
+    """max_e ||B_e y_e - x_e|| / (||B_e|| ||y_e|| + ||x_e||) per element."""
+    Ne = Bor.shape[0]
+    ye = y.transpose(1, 0, 2).reshape(Ne, -1)
+    xe = x.transpose(1, 0, 2).reshape(Ne, -1)
+    r = np.einsum("eij,ej->ei", Bor, ye) - xe
+    num = np.linalg.norm(r, axis=1)
+    den = np.linalg.norm(Bor, axis=(1, 2)) * np.linalg.norm(ye, axis=1) + np.linalg.norm(xe, axis=1)
+    return float(np.max(num / den))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("shape,seed", [((5, 4, 3), 0), ((3, 3, 7), 1)])
+def test_blockjacobi_apply_inverts_oracle_blocks(shape, seed, dtype, tol):
+    nx, ny, nz = shape
+    print(f"[bj] mesh {shape} seed {seed} {dtype}", flush=True)
+    P, ctx, mask = problem_and_context(nx, ny, nz, mask_seed=seed, param_seed=seed)
+    u = synth.random_state(P.n_elem, P.n_nodes, 500 + seed, phase=mask, phi_spread=5e-3)
+    m = odg.old_mass(P, u)
+    dev = torch.device("cuda:0")
+    ut = torch.tensor(u, device=dev, dtype=dtype)
+    ctx.blockjacobi_setup(ut, 0.9, 0.05)
+    x = synth.random_vector(7, P.n_elem, P.n_nodes, 600 + seed)
+    y = ctx.blockjacobi_apply(torch.tensor(x, device=dev, dtype=dtype)).cpu().numpy().astype(np.float64)
+    uu = ut.cpu().numpy().astype(np.float64)
+    Bor = osolve.element_blocks(P, uu, m, 0.9, 0.05, fields=range(7), condensed=True)
+    err = _backward_error(Bor, y, x)
+    print("  backward error", err, flush=True)
+    assert err < tol
+    # exported inverse blocks agree with the apply
+    Binv = ctx.blockjacobi_export().cpu().numpy().astype(np.float64)       # [e][col][row]
+    xe = x.transpose(1, 0, 2).reshape(P.n_elem, -1)
+    y2 = np.einsum("ecr,ec->er", Binv, xe)
+    ye = y.transpose(1, 0, 2).reshape(P.n_elem, -1)
+    rel = np.linalg.norm(y2 - ye, axis=1) / np.linalg.norm(ye, axis=1)
+    assert np.max(rel) < (1e-12 if dtype == torch.float64 else 1e-5)
+
+
+def test_blockjacobi_errors():
+    from paper_2511_05233_amd import lsbdg
+    P, ctx, mask = problem_and_context(3, 2, 2, mask_seed=1, param_seed=1)
+    dev = torch.device("cuda:0")
+    x = torch.zeros((7, P.n_elem, 8), dtype=torch.float64, device=dev)
+    with pytest.raises(lsbdg.DgError, match="DG_ESTATE"):
+        ctx.blockjacobi_apply(x)
+    u = torch.tensor(synth.random_state(P.n_elem, 8, 1, phase=mask), device=dev, dtype=torch.float32)
+    ctx.blockjacobi_setup(u, 1.0, 0.1)
+    with pytest.raises(lsbdg.DgError, match="DG_EINVAL"):
+        ctx.blockjacobi_apply(x)
