@@ -163,6 +163,57 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
  * out[e][col][row], row/col = field * 8 + node) to the device buffer out. */
 int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream);
 
+/* Options of the Newton-Krylov step solver. */
+typedef struct {
+  int32_t inner_prec;    /* DG_F32: FP32 JVP, blocks and GMRES (mixed precision);
+                            DG_F64: everything in FP64 */
+  int32_t gmres_restart; /* GMRES restart length m, 1..30 (default 30) */
+  int32_t gmres_maxit;   /* GMRES iterations per Newton iteration (default 1500) */
+  int32_t newton_maxit;  /* Newton iterations (default 60) */
+  double gmres_rtol;     /* relative reduction of the preconditioned, scaled
+                            residual per Newton iteration (default 1e-4) */
+  double gmres_rtol_final; /* tolerance once the Newton update is below 1e-7
+                            (default 1e-9) */
+  double newton_tol;     /* converged when a full step changes no unknown by
+                            more than this relative amount (default 1e-11) */
+  int32_t coarse;        /* global per-field coarse space: 0 = by precision
+                            (1 for DG_F32, 2 for DG_F64), 1 = additive
+                            correction, 2 = deflation (exact coarse solve),
+                            -1 = none */
+  int32_t verbose;       /* 1: one line per Newton iteration on stderr */
+} dg_solver_opts;
+
+void dg_solver_opts_default(dg_solver_opts* o);
+
+typedef struct {
+  int32_t newton_its, gmres_its, line_search_cuts, status;
+  int32_t stalled;        /* 1: stopped because full steps no longer shrank the
+                             update (below 1e-7): the attainable accuracy */
+  int32_t pad;
+  double merit0;          /* preconditioned scaled residual norm at the start */
+  double merit_final;     /* ... after the last accepted update */
+  double last_update;     /* largest relative change of the last update */
+  double gmres_last_rel;  /* relative GMRES residual of the last solve */
+} dg_step_report;
+
+/* One backward-Euler step (Eq. 50) from t_n to t_n + dt: on entry u holds
+ * u^n (device, FP64, 9 fields), on exit the Newton root u^{n+1} of
+ * dg_residual (T_H at t_n + dt).  Newton's method in FP64 with a backtracking
+ * line search (the paper uses PETSc newtonls, Sec. 2.8); positive unknowns
+ * are updated multiplicatively (Newton in their logarithms).  Each linear
+ * solve is GMRES(m) on the condensed 7-field Jacobian, scaled by the unknown
+ * magnitudes and preconditioned by the element blocks plus a global
+ * per-field coarse correction, in the inner precision of opts (NULL:
+ * defaults).  Device workspace is allocated on first use and kept.
+ * Converged when a full step changes no unknown by more than newton_tol,
+ * or when, below 1e-7, three full steps in a row (six with DG_F32 inner
+ * solves, whose refinement contracts more slowly) fail to halve the update.
+ * Synchronises the stream.  DG_ENOCONV: u holds the last iterate and the
+ * report is filled; the controller halves dt (Sec. 2.7).  DG_ENAN: non-finite
+ * residual. */
+int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,
+            dg_step_report* report, dg_stream stream);
+
 /* Human-readable description of the last error on this thread. */
 const char* dg_last_error(void);
 

@@ -1,0 +1,309 @@
+// Vector kernels of the Newton-Krylov solver (gfx950).
+//
+// All vectors use the field-major layout [f][e][n]; a Krylov vector holds
+// the 7 transported fields (length 7 * Ne * np).  Reductions accumulate in
+// the vector precision S inside a thread, then in a block tree, then over
+// block partials; FP32 vectors therefore use FP32 accumulation throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dual.hpp"
+#include "model.hpp"
+#include "pointwise.hpp"
+#include "resid_q1.hpp"
+
+namespace lsbdg {
+
+constexpr int kRedBlocks = 1024;   // partial sums per reduction
+constexpr int kMaxDots = 32;       // vectors per multi-dot (restart + 2)
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(256) cast_kernel(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    y[i] = B(x[i]);
+}
+
+// y = a * x (elementwise) or y = x / a
+template <typename S, bool kDiv>
+__global__ void __launch_bounds__(256) emul_kernel(const S* __restrict__ a, const S* __restrict__ x,
+                                                   S* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    y[i] = kDiv ? x[i] / a[i] : a[i] * x[i];
+}
+
+// y = alpha x + beta y
+template <typename S>
+__global__ void __launch_bounds__(256) axpby_kernel(S alpha, const S* __restrict__ x, S beta,
+                                                    S* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    y[i] = alpha * x[i] + (beta == S(0) ? S(0) : beta * y[i]);
+}
+
+template <typename S>
+__device__ __forceinline__ S block_sum(S v, S* sh) {
+  // 256 threads: wave reduction then across the 4 waves
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// partial[i * gridDim + b] = sum over block b's share of V_i . w, i < nv
+template <typename S>
+__global__ void __launch_bounds__(256)
+multi_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ w, int64_t n,
+                 S* __restrict__ partial) {
+  __shared__ S sh[4];
+  S acc[kMaxDots];
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) {
+    const S wk = w[k];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) acc[i] += V[i * ldv + k] * wk;
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) {
+    if (i < nv) {
+      const S s = block_sum(acc[i], sh);
+      if (threadIdx.x == 0) partial[i * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// out[i] = sum_b partial[i * nb + b]; one block per i
+template <typename S>
+__global__ void __launch_bounds__(256) finish_sum_kernel(const S* __restrict__ partial, int nb,
+                                                         S* __restrict__ out) {
+  __shared__ S sh[4];
+  S v = S(0);
+  for (int b = threadIdx.x; b < nb; b += 256) v += partial[blockIdx.x * nb + b];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+// w -= sum_i h[i] V_i   (h in device memory)
+template <typename S>
+__global__ void __launch_bounds__(256)
+multi_axpy_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h, S sign,
+                  S* __restrict__ w, int64_t n) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) {
+    S acc = S(0);
+    for (int i = 0; i < nv; ++i) acc += h[i] * V[i * ldv + k];
+    w[k] += sign * acc;
+  }
+}
+
+// partial sums per field f < 7 of a_f * b_f (field stride FS)
+template <typename S>
+__global__ void __launch_bounds__(256)
+field_dot_kernel(const S* __restrict__ a, const S* __restrict__ b, int64_t FS, S* __restrict__ partial) {
+  __shared__ S sh[4];
+  S acc[7];
+#pragma unroll
+  for (int f = 0; f < 7; ++f) acc[f] = S(0);
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f) acc[f] += a[f * FS + k] * b[f * FS + k];
+  }
+#pragma unroll
+  for (int f = 0; f < 7; ++f) {
+    const S s = block_sum(acc[f], sh);
+    if (threadIdx.x == 0) partial[f * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Coarse correction coefficients yc = Ainv zr with zr = sums of partials.
+template <typename S>
+__global__ void __launch_bounds__(256)
+coarse_solve_kernel(const S* __restrict__ partial, int nb, const double* __restrict__ Ainv,
+                    S* __restrict__ yc) {
+  __shared__ S sh[4];
+  __shared__ double zr[7];
+  for (int f = 0; f < 7; ++f) {
+    S v = S(0);
+    for (int b = threadIdx.x; b < nb; b += 256) v += partial[f * nb + b];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) zr[f] = double(v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    double s = 0.0;
+    for (int g = 0; g < 7; ++g) s += Ainv[threadIdx.x * 7 + g] * zr[g];
+    yc[threadIdx.x] = S(s);
+  }
+}
+
+// out_f += sc_f * yc_f
+template <typename S>
+__global__ void __launch_bounds__(256)
+coarse_add_kernel(const S* __restrict__ sc, const S* __restrict__ yc, S* __restrict__ out, int64_t FS) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256)
+    out[k] += sc[k] * yc[k / FS];
+}
+
+// t = sc on field f, zero elsewhere (coarse basis vector)
+template <typename S>
+__global__ void __launch_bounds__(256)
+field_select_kernel(const S* __restrict__ sc, int f, S* __restrict__ t, int64_t FS) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256)
+    t[k] = (k / FS == f) ? sc[k] : S(0);
+}
+
+// rhs = -(R_u - y_u) on the 7 transported fields (R in FP64)
+template <typename S>
+__global__ void __launch_bounds__(256)
+condensed_rhs_kernel(const double* __restrict__ R, const S* __restrict__ y9, S* __restrict__ rhs, int64_t n7) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n7; k += int64_t(gridDim.x) * 256)
+    rhs[k] = -(S(R[k]) - y9[k]);
+}
+
+// v9 = (0 on the 7 transported fields, w_R on the solid fractions)
+template <typename S>
+__global__ void __launch_bounds__(256)
+solid_direction_kernel(const double* __restrict__ wR, S* __restrict__ v9, int64_t FS) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 9 * FS; k += int64_t(gridDim.x) * 256)
+    v9[k] = (k < 7 * FS) ? S(0) : S(wR[k - 7 * FS]);
+}
+
+// Unknown scales of the 7 transported fields: max(|u_f|, floor_f).
+template <typename S>
+__global__ void __launch_bounds__(256)
+scales_kernel(const double* __restrict__ u, S* __restrict__ sc, int64_t FS, double phi_floor) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256) {
+    const double x = fabs(u[k]);
+    const double fl = (k / FS == 6) ? phi_floor : 1e-20;
+    sc[k] = S(x > fl ? x : fl);
+  }
+}
+
+// w_R = J_ee^-1 R_eps per node (node-local 2x2, see condense_solids).
+__global__ void __launch_bounds__(256)
+solid_rhs_kernel(const double* __restrict__ U, const double* __restrict__ R, double* __restrict__ wR,
+                 const uint8_t* __restrict__ phase, DevParams P, int np) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t FS = P.Ne * np;
+  if (k >= FS) return;
+  const int ph = phase[k / np];
+  double us[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) us[f] = U[f * FS + k];
+  const double W3 = P.W3, idt = P.inv_dt;
+  double a00 = P.rhoM[0] * idt, a01 = 0.0, a10 = 0.0, a11 = P.rhoM[1] * idt;
+  if (P.react[ph] != 0.0) {
+    using D = Dual<double>;
+    D x[9], Sx[9];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) x[f] = D(us[f], f == 7 ? 1.0 : 0.0);
+    node_sources(P, ph, x, Sx);
+    a00 -= Sx[7].d;
+    a10 -= Sx[8].d;
+    x[7].d = 0.0;
+    x[8].d = 1.0;
+    node_sources(P, ph, x, Sx);
+    a01 -= Sx[7].d;
+    a11 -= Sx[8].d;
+  }
+  const double r0 = R[7 * FS + k] / W3, r1 = R[8 * FS + k] / W3;
+  const double det = a00 * a11 - a01 * a10;
+  wR[k] = (a11 * r0 - a01 * r1) / det;
+  wR[FS + k] = (a00 * r1 - a10 * r0) / det;
+}
+
+// Solid-fraction part of the Newton direction: d_eps = -w_R + w(du).
+__global__ void __launch_bounds__(256)
+solid_delta_kernel(const double* __restrict__ U, const double* __restrict__ du7,
+                   const double* __restrict__ wR, double* __restrict__ deps,
+                   const uint8_t* __restrict__ phase, DevParams P, int np) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t FS = P.Ne * np;
+  if (k >= FS) return;
+  const int ph = phase[k / np];
+  double us[9], vs[7];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) us[f] = U[f * FS + k];
+#pragma unroll
+  for (int f = 0; f < 7; ++f) vs[f] = du7[f * FS + k];
+  double w0, w1;
+  condense_solids(P, ph, us, vs, w0, w1);
+  deps[k] = -wR[k] + w0;
+  deps[FS + k] = -wR[FS + k] + w1;
+}
+
+// u_out = u (+) lam du: positive unknowns multiplicatively, x exp(lam du/x)
+// with the exponent clamped to [-ln 10, ln 10] (at most a factor 10 per
+// iteration either way, so no unknown collapses to zero or to the scale
+// floor in one step); Phi_L and non-positive entries additively.  Also returns per-block maxima of |du|/scale (full step).
+__global__ void __launch_bounds__(256)
+newton_update_kernel(const double* __restrict__ U, const double* __restrict__ dU, double lam,
+                     double* __restrict__ Uout, int64_t FS, double phi_floor, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double mx = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 9 * FS; k += int64_t(gridDim.x) * 256) {
+    const int f = int(k / FS);
+    const double x = U[k], d = dU[k];
+    const double fl = (f == 6) ? phi_floor : (f < 6 ? 1e-20 : 1e-12);
+    const double s = fabs(x) > fl ? fabs(x) : fl;
+    const double rel = fabs(d) / s;
+    mx = rel > mx ? rel : mx;
+    double y;
+    if (f == 6 || !(x > 0.0)) {
+      y = x + lam * d;
+    } else {
+      double ex = lam * d / x;
+      ex = ex < 2.302585092994046 ? ex : 2.302585092994046;
+      ex = ex > -2.302585092994046 ? ex : -2.302585092994046;
+      y = x * exp(ex);
+    }
+    Uout[k] = y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sh[0];
+    for (int i = 1; i < 4; ++i) m = sh[i] > m ? sh[i] : m;
+    partial[blockIdx.x] = m;
+  }
+}
+
+// Merit contributions: sum of squares of x (n entries) into block partials.
+template <typename S>
+__global__ void __launch_bounds__(256)
+sumsq_kernel(const S* __restrict__ x, int64_t n, S* __restrict__ partial) {
+  __shared__ S sh[4];
+  S acc = S(0);
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256)
+    acc += x[k] * x[k];
+  const S s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Solid rows scaled by their time-term diagonal and the unknown scale.
+__global__ void __launch_bounds__(256)
+solid_merit_kernel(const double* __restrict__ R, const double* __restrict__ U, int64_t FS, DevParams P,
+                   double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 2 * FS; k += int64_t(gridDim.x) * 256) {
+    const int s = int(k / FS);
+    const double x = fabs(U[(7 + s) * FS + (k % FS)]);
+    const double sc = x > 1e-12 ? x : 1e-12;
+    const double v = R[7 * FS + k] / (P.W3 * P.rhoM[s] * P.inv_dt * sc);
+    acc += v * v;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+}  // namespace lsbdg

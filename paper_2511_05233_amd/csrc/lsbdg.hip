@@ -18,6 +18,7 @@
 #include "pointwise.hpp"
 #include "resid_q1.hpp"
 #include "blockjacobi.hpp"
+#include "solver.hpp"
 
 using namespace lsbdg;
 
@@ -37,6 +38,7 @@ struct dg_ctx {
   size_t blocks_bytes = 0;
   int blocks_prec = -1;
   int* d_status = nullptr;
+  SolverWork work;
 };
 
 namespace {
@@ -119,6 +121,419 @@ void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void*
   hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
                      static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
                      ctx->d_phase, P, nb);
+}
+
+}  // namespace
+
+
+namespace {
+
+// Build and invert the condensed element blocks of precision S at uS.
+template <typename S>
+int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
+  const size_t need = size_t(ctx->Ne) * 56 * 56 * sizeof(S);
+  if (ctx->blocks_bytes < need) {
+    if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
+    ctx->d_blocks = nullptr;
+    ctx->blocks_bytes = 0;
+    hipError_t err = hipMalloc(&ctx->d_blocks, need);
+    if (err != hipSuccess)
+      return fail(DG_ENOMEM, std::string("block storage: ") + hipGetErrorString(err));
+    ctx->blocks_bytes = need;
+  }
+  if (!ctx->d_status) {
+    hipError_t err = hipMalloc(&ctx->d_status, sizeof(int));
+    if (err != hipSuccess) return fail(DG_ENOMEM, "status allocation");
+  }
+  DG_HIP(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+  int64_t nb = (ctx->Ne * 8 + 255) / 256;
+  nb = (nb + 7) / 8 * 8;
+  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
+  const dim3 grid_w{unsigned((ctx->Ne + 3) / 4), 1, 1};
+  hipLaunchKernelGGL((q1_block_kernel<S, kJvpCondensed>), grid, block, 0, st, uS,
+                     static_cast<S*>(ctx->d_blocks), ctx->d_phase, P, nb);
+  hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), grid_w, block, 0, st, static_cast<S*>(ctx->d_blocks),
+                     ctx->Ne, ctx->d_status);
+  DG_HIP(hipGetLastError());
+  int h_status = 0;
+  DG_HIP(hipMemcpyAsync(&h_status, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipStreamSynchronize(st));
+  ctx->blocks_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  if (h_status) return fail(DG_ENAN, "singular or non-finite element block");
+  return DG_OK;
+}
+
+template <typename S>
+int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_opts& o,
+                 dg_step_report* rep, hipStream_t st) {
+  const int64_t FS = ctx->Ne * ctx->np, n7 = 7 * FS, n9 = 9 * FS;
+  const int m = o.gmres_restart;
+  SolverWork& W = ctx->work;
+  const size_t sS = sizeof(S);
+  for (auto pr : {std::make_pair(&W.m_old, size_t(8 * FS) * 8), std::make_pair(&W.R, size_t(n9) * 8),
+                  std::make_pair(&W.Rtry, size_t(n9) * 8), std::make_pair(&W.u_try, size_t(n9) * 8),
+                  std::make_pair(&W.du, size_t(n9) * 8), std::make_pair(&W.wR, size_t(2 * FS) * 8),
+                  std::make_pair(&W.uS, size_t(n9) * sS), std::make_pair(&W.sc, size_t(n7) * sS),
+                  std::make_pair(&W.V, size_t(m + 1) * n7 * sS), std::make_pair(&W.w, size_t(n7) * sS),
+                  std::make_pair(&W.t, size_t(n7) * sS), std::make_pair(&W.pJ, size_t(n7) * sS),
+                  std::make_pair(&W.rhs, size_t(n7) * sS), std::make_pair(&W.b, size_t(n7) * sS),
+                  std::make_pair(&W.x, size_t(n7) * sS), std::make_pair(&W.y9, size_t(n9) * sS),
+                  std::make_pair(&W.v9, size_t(n9) * sS), std::make_pair(&W.JZ, size_t(7) * n7 * sS),
+                  std::make_pair(&W.partial, size_t(kMaxDots) * kRedBlocks * sS),
+                  std::make_pair(&W.partial64, size_t(kRedBlocks) * 8),
+                  std::make_pair(&W.dots, size_t(kMaxDots) * 8), std::make_pair(&W.yc, size_t(8) * 8),
+                  std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8)}) {
+    hipError_t e = pr.first->ensure(pr.second);
+    if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_step workspace: ") + hipGetErrorString(e));
+  }
+  const DevParams P = make_params(ctx, t_n + dt, dt);
+  const double phi_floor = kGas * ctx->params.T / kFaraday;
+  double* m_old = W.m_old.as<double>();
+  double* R = W.R.as<double>();
+  double* Rtry = W.Rtry.as<double>();
+  double* u_try = W.u_try.as<double>();
+  double* du = W.du.as<double>();
+  double* wR = W.wR.as<double>();
+  S *uS = W.uS.as<S>(), *sc = W.sc.as<S>(), *V = W.V.as<S>(), *w = W.w.as<S>(), *t = W.t.as<S>();
+  S *pJ = W.pJ.as<S>(), *rhs = W.rhs.as<S>(), *b = W.b.as<S>(), *x = W.x.as<S>();
+  S *y9 = W.y9.as<S>(), *v9 = W.v9.as<S>(), *partial = W.partial.as<S>(), *dots = W.dots.as<S>();
+  S *yc = W.yc.as<S>(), *hbuf = W.hbuf.as<S>(), *JZ = W.JZ.as<S>();
+  double* partial64 = W.partial64.as<double>();
+  double* Ainv = W.Ainv.as<double>();
+  const dim3 blk{256, 1, 1};
+  const dim3 gred{unsigned(kRedBlocks), 1, 1};
+  const dim3 gw{unsigned((ctx->Ne + 3) / 4), 1, 1};
+  const dim3 g1{1, 1, 1}, g7{7, 1, 1};
+
+  auto resid64 = [&](const double* uu, double* out) {
+    launch_q1<double, double, kResidual>(ctx, P, uu, nullptr, m_old, out, st);
+  };
+  auto jvp_cond = [&](const S* v7, S* out) {
+    launch_q1<S, Dual<S>, kJvpCondensed>(ctx, P, uS, v7, nullptr, out, st);
+  };
+  // coarse coefficients yc = E^-1 Z^T r (E = Z^T J Z, Z_f = sc on field f)
+  auto coarse_coeffs = [&](const S* r) {
+    hipLaunchKernelGGL(field_dot_kernel<S>, gred, blk, 0, st, sc, r, FS, partial);
+    hipLaunchKernelGGL(coarse_solve_kernel<S>, g1, blk, 0, st, partial, kRedBlocks, Ainv, yc);
+  };
+  // deflation r <- P r = r - J Z E^-1 Z^T r (leaves yc = E^-1 Z^T r)
+  auto deflate = [&](S* r) {
+    if (o.coarse != 2) return;
+    coarse_coeffs(r);
+    hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, JZ, n7, 7, yc, S(-1), r, n7);
+  };
+  // preconditioner: out = B^-1 r (+ Z E^-1 Z^T r for the additive coarse
+  // space; the deflated variant has already removed that part from r)
+  auto precond = [&](S* r, S* out) {
+    deflate(r);
+    hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), r,
+                       out, ctx->Ne);
+    if (o.coarse == 1) {
+      coarse_coeffs(r);
+      hipLaunchKernelGGL(coarse_add_kernel<S>, grid1(n7), blk, 0, st, sc, yc, out, FS);
+    }
+  };
+  auto opA = [&](const S* v, S* out) {           // out = sc^-1 M^-1 J (sc v)
+    hipLaunchKernelGGL((emul_kernel<S, false>), grid1(n7), blk, 0, st, sc, v, t, n7);
+    jvp_cond(t, pJ);
+    precond(pJ, out);
+    hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, out, out, n7);
+  };
+  auto mdot = [&](const S* Vb, int nv, const S* ww, std::vector<double>& h) -> int {
+    hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, Vb, n7, nv, ww, n7, partial);
+    const dim3 gnv{unsigned(nv), 1, 1};
+    hipLaunchKernelGGL(finish_sum_kernel<S>, gnv, blk, 0, st, partial, kRedBlocks, dots);
+    std::vector<S> hs(nv);
+    DG_HIP(hipMemcpyAsync(hs.data(), dots, nv * sizeof(S), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    h.assign(hs.begin(), hs.end());
+    return DG_OK;
+  };
+  auto sumsq = [&](const S* a, int64_t n, double& out) -> int {
+    hipLaunchKernelGGL(sumsq_kernel<S>, gred, blk, 0, st, a, n, partial);
+    hipLaunchKernelGGL(finish_sum_kernel<S>, g1, blk, 0, st, partial, kRedBlocks, dots);
+    S hs = 0;
+    DG_HIP(hipMemcpyAsync(&hs, dots, sizeof(S), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    out = double(hs);
+    return DG_OK;
+  };
+  // merit(Rv)^2 = ||sc^-1 M^-1 R_u||^2 (+ ||E^-1 Z^T R_u||^2 when deflated)
+  //              + ||R_eps / (W (rho/M)/dt sc_eps)||^2,
+  // with the operators, scales and iterate of this Newton iteration: the
+  // norm in which GMRES reduced the linearised residual (the deflated coarse
+  // part of it vanishes exactly), so the Newton direction descends it.
+  auto merit = [&](const double* Rv, double& out) -> int {
+    hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n7), blk, 0, st, Rv, t, n7);
+    double cpart = 0.0;
+    precond(t, pJ);
+    if (o.coarse == 2) {
+      S hy[7];
+      DG_HIP(hipMemcpyAsync(hy, yc, 7 * sizeof(S), hipMemcpyDeviceToHost, st));
+      DG_HIP(hipStreamSynchronize(st));
+      for (int f = 0; f < 7; ++f) cpart += double(hy[f]) * double(hy[f]);
+    }
+    hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, pJ, pJ, n7);
+    double a = 0.0;
+    if (int s = sumsq(pJ, n7, a)) return s;
+    hipLaunchKernelGGL(solid_merit_kernel, gred, blk, 0, st, Rv, u, FS, P, partial64);
+    hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, kRedBlocks,
+                       reinterpret_cast<double*>(hbuf));
+    double bsum = 0.0;
+    DG_HIP(hipMemcpyAsync(&bsum, hbuf, sizeof(double), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    out = a + cpart + bsum;
+    return DG_OK;
+  };
+
+  // old mass of the step and first residual
+  hipLaunchKernelGGL(mass_kernel<double>, grid1(n9), blk, 0, st, u, m_old, ctx->d_phase, P, ctx->np);
+  resid64(u, R);
+  DG_HIP(hipGetLastError());
+  dg_step_report r{};
+  int status = DG_ENOCONV;
+  // Near the root the linear-solve tolerance is tightened, and the iteration
+  // stops once a full step no longer shrinks the update: the attainable
+  // accuracy of an iterative solve is then reached (the report says so).
+  double gm_rtol = o.gmres_rtol;
+  double best_upd = 1e300;
+  int stall = 0, prev_its = 0;
+  for (int it = 1; it <= o.newton_maxit; ++it) {
+    r.newton_its = it;
+    hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
+    if (int s = blocks_setup<S>(ctx, P, uS, st)) return s;
+    hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
+    // coarse operator Ac[g][f] = sum_g sc_g (J Z_f)_g
+    if (o.coarse) {
+      std::vector<double> Ac(49), col(7);
+      for (int f = 0; f < 7; ++f) {
+        S* JZf = JZ + int64_t(f) * n7;
+        hipLaunchKernelGGL(field_select_kernel<S>, grid1(n7), blk, 0, st, sc, f, t, FS);
+        jvp_cond(t, JZf);
+        hipLaunchKernelGGL(field_dot_kernel<S>, gred, blk, 0, st, sc, JZf, FS, partial);
+        hipLaunchKernelGGL(finish_sum_kernel<S>, g7, blk, 0, st, partial, kRedBlocks, dots);
+        std::vector<S> hs(7);
+        DG_HIP(hipMemcpyAsync(hs.data(), dots, 7 * sizeof(S), hipMemcpyDeviceToHost, st));
+        DG_HIP(hipStreamSynchronize(st));
+        for (int g = 0; g < 7; ++g) Ac[g * 7 + f] = double(hs[g]);
+      }
+      // symmetric equilibration D Ac D, D = |diag|^-1/2, before inverting:
+      // the entries of Ac span many orders of magnitude
+      std::vector<double> dsc(7), As(49), inv(49);
+      for (int g = 0; g < 7; ++g) {
+        const double a = std::fabs(Ac[g * 7 + g]);
+        dsc[g] = (a > 0 && std::isfinite(a)) ? 1.0 / std::sqrt(a) : 1.0;
+      }
+      for (int g = 0; g < 7; ++g)
+        for (int f = 0; f < 7; ++f) As[g * 7 + f] = dsc[g] * Ac[g * 7 + f] * dsc[f];
+      for (int c = 0; c < 7; ++c) {
+        std::vector<double> e(7, 0.0);
+        e[c] = 1.0;
+        if (!dense_solve(7, As, e)) return fail(DG_ENAN, "dg_step: singular coarse operator");
+        for (int g = 0; g < 7; ++g) inv[g * 7 + c] = dsc[g] * e[g] * dsc[c];
+      }
+      DG_HIP(hipMemcpyAsync(Ainv, inv.data(), 49 * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    // condensed right side
+    hipLaunchKernelGGL(solid_rhs_kernel, grid1(FS), blk, 0, st, u, R, wR, ctx->d_phase, P, ctx->np);
+    hipLaunchKernelGGL(solid_direction_kernel<S>, grid1(n9), blk, 0, st, wR, v9, FS);
+    launch_q1<S, Dual<S>, kJvpFull>(ctx, P, uS, v9, nullptr, y9, st);
+    hipLaunchKernelGGL(condensed_rhs_kernel<S>, grid1(n7), blk, 0, st, R, y9, rhs, n7);
+    hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), rhs, S(0), w, n7);
+    precond(w, b);
+    hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, b, b, n7);
+    double merit0 = 0.0;
+    if (int s = merit(R, merit0)) return s;
+    if (!std::isfinite(merit0)) return fail(DG_ENAN, "dg_step: non-finite residual");
+    if (it == 1) r.merit0 = std::sqrt(merit0);
+
+    // GMRES(m) on sc^-1 M^-1 J sc y = b, x0 = 0
+    hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), b, S(0), x, n7);
+    double beta0 = 0.0;
+    if (int s = sumsq(b, n7, beta0)) return s;
+    beta0 = std::sqrt(beta0);
+    if (!std::isfinite(beta0)) return fail(DG_ENAN, "dg_step: non-finite preconditioned right side");
+    int its = 0;
+    // near the root an FP32 Krylov solve may stagnate above its tolerance:
+    // bound its cost by the previous solve instead of running to gmres_maxit
+    const bool near_root = best_upd < 1e-7;
+    const int maxit = near_root ? std::min(o.gmres_maxit, std::max(200, 4 * prev_its)) : o.gmres_maxit;
+    double rel = 0.0;
+    if (beta0 > 0.0) {
+      std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), h, h2;
+      while (its < maxit) {
+        S* V0 = V;
+        if (its == 0) {
+          hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), b, S(0), V0, n7);
+        } else {
+          opA(x, w);
+          hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), b, S(-1), w, n7);
+          hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), w, S(0), V0, n7);
+        }
+        double beta = 0.0;
+        if (int s = sumsq(V0, n7, beta)) return s;
+        beta = std::sqrt(beta);
+        if (!(beta > 0.0)) break;
+        hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1.0 / beta), V0, S(0), V0, n7);
+        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(H.begin(), H.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        bool done = false;
+        for (; j < m && its < maxit; ++j) {
+          S* Vj1 = V + int64_t(j + 1) * n7;
+          opA(V + int64_t(j) * n7, w);
+          if (int s = mdot(V, j + 1, w, h)) return s;
+          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
+          if (int s = mdot(V, j + 1, w, h2)) return s;
+          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
+          for (int i = 0; i <= j; ++i) h[i] += h2[i];
+          double hn = 0.0;
+          if (int s = sumsq(w, n7, hn)) return s;
+          hn = std::sqrt(hn);
+          ++its;
+          for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
+          H[(j + 1) * m + j] = hn;
+          for (int i = 0; i < j; ++i) {
+            const double a = H[i * m + j], c = H[(i + 1) * m + j];
+            H[i * m + j] = cs[i] * a + sn[i] * c;
+            H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+          }
+          const double a = H[j * m + j], c = H[(j + 1) * m + j];
+          const double rr = std::hypot(a, c);
+          cs[j] = rr > 0 ? a / rr : 1.0;
+          sn[j] = rr > 0 ? c / rr : 0.0;
+          H[j * m + j] = rr;
+          H[(j + 1) * m + j] = 0.0;
+          g[j + 1] = -sn[j] * g[j];
+          g[j] = cs[j] * g[j];
+          rel = std::fabs(g[j + 1]) / beta0;
+          if (rel <= gm_rtol || !(hn > 0.0)) {
+            done = true;
+            ++j;
+            break;
+          }
+          hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1.0 / hn), w, S(0), Vj1, n7);
+        }
+        // x += V_j y, H y = g (upper triangular j x j)
+        std::vector<double> y(j);
+        for (int i = j - 1; i >= 0; --i) {
+          double s = g[i];
+          for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
+          y[i] = s / H[i * m + i];
+        }
+        std::vector<S> ys(y.begin(), y.end());
+        DG_HIP(hipMemcpyAsync(hbuf, ys.data(), j * sizeof(S), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j, hbuf, S(1), x, n7);
+        if (done) break;
+      }
+    }
+    r.gmres_its += its;
+    r.gmres_last_rel = rel;
+    prev_its = its;
+    const bool gmres_short = rel > gm_rtol;
+    // Newton direction: xhat = sc x, then the exact coarse component
+    //   du_u = xhat + Z E^-1 Z^T (rhs - J xhat),
+    // solids from the condensation.
+    hipLaunchKernelGGL((emul_kernel<S, false>), grid1(n7), blk, 0, st, sc, x, t, n7);
+    if (o.coarse == 2) {
+      jvp_cond(t, pJ);
+      hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), rhs, S(-1), pJ, n7);
+      coarse_coeffs(pJ);
+      hipLaunchKernelGGL(coarse_add_kernel<S>, grid1(n7), blk, 0, st, sc, yc, t, FS);
+    }
+    hipLaunchKernelGGL((cast_kernel<S, double>), grid1(n7), blk, 0, st, t, du, n7);
+    hipLaunchKernelGGL(solid_delta_kernel, grid1(FS), blk, 0, st, u, du, wR, du + n7, ctx->d_phase, P,
+                       ctx->np);
+    if (o.verbose >= 2) {
+      std::vector<double> hu(n9), hd(n9);
+      DG_HIP(hipMemcpyAsync(hu.data(), u, n9 * 8, hipMemcpyDeviceToHost, st));
+      DG_HIP(hipMemcpyAsync(hd.data(), du, n9 * 8, hipMemcpyDeviceToHost, st));
+      DG_HIP(hipStreamSynchronize(st));
+      std::fprintf(stderr, "[dg_step]   field: min u | max |du|/max(|u|,floor)\n");
+      for (int f = 0; f < 9; ++f) {
+        double mn = 1e300, mx = 0;
+        const double fl = f == 6 ? phi_floor : (f < 6 ? 1e-20 : 1e-12);
+        int64_t at = 0;
+        for (int64_t k = 0; k < FS; ++k) {
+          const double x = hu[f * FS + k];
+          mn = std::min(mn, x);
+          const double r = std::fabs(hd[f * FS + k]) / std::max(std::fabs(x), fl);
+          if (r > mx) { mx = r; at = k; }
+        }
+        std::fprintf(stderr, "[dg_step]   %d: %.3e | %.3e at node %lld (u %.3e du %.3e)\n", f, mn, mx,
+                     (long long)at, hu[f * FS + at], hd[f * FS + at]);
+      }
+    }
+    // backtracking line search on the merit (weights of this iterate)
+    double lam = 1.0, upd = 0.0, mt = 0.0;
+    bool found = false;
+    for (int ls = 0; ls <= (near_root ? 3 : 40); ++ls) {
+      hipLaunchKernelGGL(newton_update_kernel, gred, blk, 0, st, u, du, lam, u_try, FS, phi_floor, partial64);
+      std::vector<double> pm(kRedBlocks);
+      DG_HIP(hipMemcpyAsync(pm.data(), partial64, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, st));
+      resid64(u_try, Rtry);
+      if (int s = merit(Rtry, mt)) return s;
+      upd = *std::max_element(pm.begin(), pm.end());
+      if (std::isfinite(mt) && (mt < merit0 || (lam == 1.0 && upd < 1e-8))) {
+        found = true;
+        break;
+      }
+      lam *= 0.5;
+      ++r.line_search_cuts;
+    }
+    if (!found) {
+      // no decrease along this direction: near the root the linear solve has
+      // reached its attainable accuracy (keep the iterate); elsewhere fail
+      if (o.verbose)
+        std::fprintf(stderr, "[dg_step] newton %d: line search found no decrease (update %.3e)\n", it, upd);
+      if (std::min(best_upd, upd) < 1e-7) {
+        status = DG_OK;
+        r.stalled = 1;
+      }
+      break;
+    }
+    DG_HIP(hipMemcpyAsync(u, u_try, n9 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    DG_HIP(hipMemcpyAsync(R, Rtry, n9 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    r.merit_final = std::sqrt(mt);
+    r.last_update = upd;
+    if (o.verbose)
+      std::fprintf(stderr, "[dg_step] newton %d gmres %d (rel %.2e) update %.3e lambda %.3g merit %.3e -> %.3e\n",
+                   it, its, rel, upd, lam, std::sqrt(merit0), std::sqrt(mt));
+    if (!std::isfinite(mt)) {
+      status = DG_ENAN;
+      break;
+    }
+    if (lam == 1.0 && upd < o.newton_tol) {
+      status = DG_OK;
+      break;
+    }
+    if (near_root && gmres_short) {
+      // the linear solve stagnated at its attainable accuracy: stop here
+      status = DG_OK;
+      r.stalled = 1;
+      break;
+    }
+    if (lam == 1.0 && upd < 1e-7) {
+      // FP32 Krylov vectors cannot resolve much below their unit roundoff
+      const double floor_rtol = std::is_same<S, float>::value ? 1e-5 : 0.0;
+      gm_rtol = std::max(std::min(gm_rtol, o.gmres_rtol_final), floor_rtol);
+      if (upd < 0.5 * best_upd) {
+        stall = 0;
+      } else if (++stall >= (std::is_same<S, float>::value ? 6 : 3)) {
+        status = DG_OK;
+        r.stalled = 1;
+        break;
+      }
+    }
+    best_upd = std::min(best_upd, upd);
+  }
+  DG_HIP(hipStreamSynchronize(st));
+  r.status = status;
+  if (rep) *rep = r;
+  if (status == DG_ENOCONV) return fail(DG_ENOCONV, "dg_step: Newton did not converge");
+  if (status == DG_ENAN) return fail(DG_ENAN, "dg_step: non-finite residual");
+  return DG_OK;
 }
 
 }  // namespace
@@ -212,6 +627,7 @@ int dg_destroy(dg_ctx* ctx) {
   if (ctx->d_phase) (void)hipFree(ctx->d_phase);
   if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
+  ctx->work.release_all();
   delete ctx;
   return DG_OK;
 }
@@ -374,6 +790,48 @@ int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
   DG_HIP(hipMemcpyAsync(out, ctx->d_blocks, size_t(ctx->Ne) * kNB * kNB * esz,
                         hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   return DG_OK;
+}
+
+
+void dg_solver_opts_default(dg_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->inner_prec = DG_F32;
+  o->gmres_restart = 30;
+  o->gmres_maxit = 1500;
+  o->newton_maxit = 60;
+  o->gmres_rtol = 1e-4;
+  o->gmres_rtol_final = 1e-9;
+  o->newton_tol = 1e-11;
+  o->coarse = 0;           // 0: per precision (additive for FP32, deflation for FP64)
+  o->verbose = 0;
+}
+
+int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,
+            dg_step_report* report, dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (!u) return fail(DG_EINVAL, "dg_step: null state");
+    if (!(dt > 0)) return fail(DG_EINVAL, "dg_step: dt must be positive");
+    dg_solver_opts o;
+    if (opts) o = *opts; else dg_solver_opts_default(&o);
+    if (o.gmres_restart < 1 || o.gmres_restart > kMaxDots - 2)
+      return fail(DG_EINVAL, "dg_step: gmres_restart must be in 1..30");
+    if (o.newton_maxit < 1 || o.gmres_maxit < 1) return fail(DG_EINVAL, "dg_step: iteration limits");
+    if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
+    if (o.coarse < 0) o.coarse = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (report) std::memset(report, 0, sizeof(*report));
+    if (o.inner_prec == DG_F32)
+      return newton_solve<float>(ctx, t_n, dt, static_cast<double*>(u), o, report, st);
+    if (o.inner_prec == DG_F64)
+      return newton_solve<double>(ctx, t_n, dt, static_cast<double*>(u), o, report, st);
+    return fail(DG_EINVAL, "dg_step: bad inner precision");
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_step: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_step: unexpected exception");
+  }
 }
 
 const char* dg_last_error(void) { return g_last_error.c_str(); }

@@ -35,6 +35,9 @@ _SIGNATURES = {
                                        C.c_void_p]),
     "dg_blockjacobi_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_blockjacobi_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_solver_opts_default": (None, [C.c_void_p]),
+    "dg_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -49,6 +52,22 @@ class DgParams(C.Structure):
                 ("f_C", C.c_double), ("j_el", C.c_double), ("eps_struct", C.c_double),
                 ("sigma", C.c_double), ("c_min", C.c_double), ("epsL_min", C.c_double),
                 ("use_TH", C.c_int32), ("reserved", C.c_int32)]
+
+
+class DgSolverOpts(C.Structure):
+    _fields_ = [("inner_prec", C.c_int32), ("gmres_restart", C.c_int32), ("gmres_maxit", C.c_int32),
+                ("newton_maxit", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_rtol_final", C.c_double),
+                ("newton_tol", C.c_double),
+                ("coarse", C.c_int32), ("verbose", C.c_int32)]
+
+
+class DgStepReport(C.Structure):
+    _fields_ = [("newton_its", C.c_int32), ("gmres_its", C.c_int32), ("line_search_cuts", C.c_int32),
+                ("status", C.c_int32), ("stalled", C.c_int32), ("pad", C.c_int32), ("merit0", C.c_double), ("merit_final", C.c_double),
+                ("last_update", C.c_double), ("gmres_last_rel", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class DgError(RuntimeError):
@@ -241,3 +260,22 @@ class Context:
         out = torch.empty((self.n_elem, 56, 56), dtype=self._bj_dtype, device="cuda")
         _check("dg_blockjacobi_export", self._lib.dg_blockjacobi_export(self._h, _ptr(out), _stream()))
         return out
+
+    def step(self, u, t_n, dt, inner="f32", **opts):
+        """One backward-Euler step in place on u (FP64, 9 fields); returns the report."""
+        import torch
+        self._check_arr(u, 9)
+        if u.dtype != torch.float64:
+            raise ValueError("the step state is FP64")
+        o = DgSolverOpts()
+        self._lib.dg_solver_opts_default(C.byref(o))
+        o.inner_prec = DG_F32 if inner == "f32" else DG_F64
+        for k, v in opts.items():
+            setattr(o, k, v)
+        rep = DgStepReport()
+        code = self._lib.dg_step(self._h, float(t_n), float(dt), _ptr(u), C.byref(o), C.byref(rep), _stream())
+        if code != 0:
+            err = DgError("dg_step", code, self._lib.dg_last_error().decode())
+            err.report = rep.as_dict()
+            raise err
+        return rep.as_dict()

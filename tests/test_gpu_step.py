@@ -1,0 +1,81 @@
+"""HIP backward-Euler step (Newton-GMRES) vs the oracle's Newton root (GPU)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dg as odg
+from oracle import model as om
+from oracle import outputs as oout
+from oracle import solve as osolve
+from tests.helpers import problem_and_context
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel_l2(a, b):
+    return np.array([np.linalg.norm(a[f] - b[f]) / max(np.linalg.norm(b[f]), 1e-300) for f in range(9)])
+
+
+@pytest.fixture(scope="module")
+def small_case():
+    # a step whose root keeps every concentration positive (checked below):
+    # with the synthetic kinetics larger steps drive S4^2- through zero, a
+    # step the controller rejects by halving dt
+    P, ctx, mask = problem_and_context(5, 4, 3, mask_seed=1, param_seed=1, f_C=0.1)
+    print("[step] oracle initial state 5x4x3", flush=True)
+    u0, _ = osolve.initial_state(P)
+    print("[step] oracle BE step", flush=True)
+    u1, info = osolve.be_step(P, u0, 0.0, 0.1)
+    assert u1[0:6].min() > 0
+    print("[step] oracle", info, flush=True)
+    return P, ctx, u0, u1
+
+
+@pytest.mark.parametrize("inner,tol", [("f64", 1e-10), ("f32", 1e-8)])
+def test_step_matches_oracle_root(small_case, inner, tol):
+    P, ctx, u0, u1 = small_case
+    ut = torch.tensor(u0, device="cuda:0")
+    rep = ctx.step(ut, 0.0, 0.1, inner=inner, verbose=1)
+    assert rep["status"] == 0
+    print(f"[step] {inner} report {rep}", flush=True)
+    got = ut.cpu().numpy()
+    err = rel_l2(got, u1)
+    print("  relative L2 per field", err, flush=True)
+    assert np.all(err[:7] < tol), err
+    # solid fractions in pore voxels are identically zero on both sides
+    assert np.all(err[7:] < tol), err
+
+
+def test_step_invariants_on_cube16():
+    """16^3 voxels, Q1, 0.1C, dt = 0.1 s from the steady initial potential:
+    the GPU root satisfies the oracle's residual and the conservation laws."""
+    w = synth.WORKLOADS["cube16_q1"]
+    P, ctx, mask = problem_and_context(w.nx, w.ny, w.nz, porosity=w.porosity, mask_seed=w.mask_seed,
+                                       param_seed=w.param_seed, f_C=w.f_C)
+    print("[step] oracle initial state 16^3", flush=True)
+    u0, _ = osolve.initial_state(P)
+    ut = torch.tensor(u0, device="cuda:0")
+    rep = ctx.step(ut, 0.0, 0.1, inner="f32", verbose=1)
+    print(f"[step] cube16 report {rep}", flush=True)
+    u1 = ut.cpu().numpy()
+    S0, Li0, Ne0, _ = oout.invariants(P, u0, 0.0)
+    S1, Li1, Ne1, I1 = oout.invariants(P, u1, 0.1)
+    q = 0.1 * P.j_el * oout.separator_area(P) / om.F
+    assert abs(S1 - S0) < 1e-12 * S0
+    assert abs((Li1 - Li0) - q) < 1e-12 * Li0
+    assert abs((Ne1 - Ne0) / q - 1.0) < 1e-7
+    assert abs(I1 / (P.j_el * oout.separator_area(P)) - 1.0) < 1e-7
+    # oracle residual at the GPU root, per field against the larger of the
+    # accumulation term and the field's residual at the start of the step
+    # (trace species such as S^2- are governed by their reaction terms)
+    m_old = odg.old_mass(P, u0)
+    R = odg.residual(P, u1, m_old, 0.1, 0.1)
+    R0 = odg.residual(P, u0, m_old, 0.1, 0.1)
+    W = odg.basis(1).W3[None, :] * (P.h / 2) ** 3
+    assert rep["last_update"] < 1e-7
+    for f in range(6):
+        scale = max(np.max(np.abs(W * u1[f] / 0.1)), np.max(np.abs(R0[f])))
+        ratio = np.max(np.abs(R[f])) / scale
+        print(f"[step] field {f} residual / scale {ratio:.3e}", flush=True)
+        assert ratio <= 1e-6, f
