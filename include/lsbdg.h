@@ -206,13 +206,28 @@ typedef struct {
  * per-field coarse correction, in the inner precision of opts (NULL:
  * defaults).  Device workspace is allocated on first use and kept.
  * Converged when a full step changes no unknown by more than newton_tol,
- * or when, below 1e-7, three full steps in a row (six with DG_F32 inner
- * solves, whose refinement contracts more slowly) fail to halve the update.
+ * or, once an update below 1e-7 has been reached (the attainable accuracy
+ * of the iterative solve; report.stalled = 1), when three full steps in a
+ * row (six with DG_F32 inner solves, whose refinement contracts more
+ * slowly) fail to halve the update, when the linear solve stagnates above
+ * its tolerance, or when the line search finds no decrease.
  * Synchronises the stream.  DG_ENOCONV: u holds the last iterate and the
  * report is filled; the controller halves dt (Sec. 2.7).  DG_ENAN: non-finite
  * residual. */
 int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,
             dg_step_report* report, dg_stream stream);
+
+/* Initial state (Tab. InitialState, Sec. 2.9): u (device, FP64, 9 fields)
+ * is set to the chemical-equilibrium concentrations, the phase's solid
+ * fractions and the electrolyte potential of the steady charge balance at
+ * time t0: the charge rows of dg_residual are solved for Phi_L with the
+ * concentrations and solid fractions frozen and the full current applied.
+ * (The paper reaches the same fixed point by relaxing a pseudo-transient
+ * potential problem under a ramped current.)  The solve is the Newton-GMRES
+ * of dg_step restricted to Phi_L (opts and report as there).  Synchronises
+ * the stream.  Errors as dg_step. */
+int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts,
+                     dg_step_report* report, dg_stream stream);
 
 /* Human-readable description of the last error on this thread. */
 const char* dg_last_error(void);

@@ -67,6 +67,11 @@ q1_block_kernel(const S* __restrict__ U, S* __restrict__ Bout, const uint8_t* __
 #pragma unroll 1
   for (int col = 0; col < NB; ++col) {
     const int fj = col >> 3, nj = col & 7;
+    if (!((P.active >> (fj < 7 ? fj : 7)) & 1)) {   // inactive unknown: identity column
+#pragma unroll
+      for (int f = 0; f < NF; ++f) Be[col * NB + f * 8 + n] = (f == fj && n == nj) ? S(1) : S(0);
+      continue;
+    }
     N u[9];
     {
       S vs[9];
@@ -84,7 +89,8 @@ q1_block_kernel(const S* __restrict__ U, S* __restrict__ Bout, const uint8_t* __
     N r[9];
     q1_rows<S, N, kJvpFull, true>(U, nullptr, nullptr, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) Be[col * NB + f * 8 + n] = r[f].d;
+    for (int f = 0; f < NF; ++f)
+      Be[col * NB + f * 8 + n] = ((P.active >> (f < 7 ? f : 7)) & 1) ? r[f].d : S(0);
   }
 }
 

@@ -37,7 +37,7 @@ template <typename S>
 __global__ void __launch_bounds__(256) axpby_kernel(S alpha, const S* __restrict__ x, S beta,
                                                     S* __restrict__ y, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-    y[i] = alpha * x[i] + (beta == S(0) ? S(0) : beta * y[i]);
+    y[i] = (alpha == S(0) ? S(0) : alpha * x[i]) + (beta == S(0) ? S(0) : beta * y[i]);
 }
 
 template <typename S>
@@ -158,9 +158,34 @@ field_select_kernel(const S* __restrict__ sc, int f, S* __restrict__ t, int64_t 
 // rhs = -(R_u - y_u) on the 7 transported fields (R in FP64)
 template <typename S>
 __global__ void __launch_bounds__(256)
-condensed_rhs_kernel(const double* __restrict__ R, const S* __restrict__ y9, S* __restrict__ rhs, int64_t n7) {
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n7; k += int64_t(gridDim.x) * 256)
-    rhs[k] = -(S(R[k]) - y9[k]);
+condensed_rhs_kernel(const double* __restrict__ R, const S* __restrict__ y9, S* __restrict__ rhs, int64_t FS,
+                     int active) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256)
+    rhs[k] = ((active >> int(k / FS)) & 1) ? -(S(R[k]) - y9[k]) : S(0);
+}
+
+// Zero the inactive fields of a 7-field vector.
+template <typename S>
+__global__ void __launch_bounds__(256)
+mask_fields_kernel(S* __restrict__ a, int64_t FS, int active) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256)
+    if (!((active >> int(k / FS)) & 1)) a[k] = S(0);
+}
+
+// Tab. InitialState concentrations everywhere, Phi_L = 0, solid fractions
+// of the voxel's phase.
+__global__ void __launch_bounds__(256)
+uniform_state_kernel(double* __restrict__ U, const uint8_t* __restrict__ phase, int64_t FS, int np,
+                     Conc6 c0, double epsS8_pore, double epsS8_struct, double epsLi2S_pore,
+                     double epsLi2S_struct) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
+    const int ph = phase[k / np];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) U[f * FS + k] = c0.c[f];
+    U[6 * FS + k] = 0.0;
+    U[7 * FS + k] = ph ? epsS8_struct : epsS8_pore;
+    U[8 * FS + k] = ph ? epsLi2S_struct : epsLi2S_pore;
+  }
 }
 
 // v9 = (0 on the 7 transported fields, w_R on the solid fractions)
@@ -182,13 +207,15 @@ scales_kernel(const double* __restrict__ u, S* __restrict__ sc, int64_t FS, doub
   }
 }
 
-// w_R = J_ee^-1 R_eps per node (node-local 2x2, see condense_solids).
-__global__ void __launch_bounds__(256)
-solid_rhs_kernel(const double* __restrict__ U, const double* __restrict__ R, double* __restrict__ wR,
-                 const uint8_t* __restrict__ phase, DevParams P, int np) {
-  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t FS = P.Ne * np;
-  if (k >= FS) return;
+// w_R at one node (see solid_rhs_kernel).
+__device__ __forceinline__ void solid_rhs_node(const double* __restrict__ U, const double* __restrict__ R,
+                                               double* __restrict__ wR, const uint8_t* __restrict__ phase,
+                                               const DevParams& P, int np, int64_t FS, int64_t k) {
+  if (!(P.active & kSolidsBit)) {             // frozen solid fractions
+    wR[k] = 0.0;
+    wR[FS + k] = 0.0;
+    return;
+  }
   const int ph = phase[k / np];
   double us[9];
 #pragma unroll
@@ -215,24 +242,33 @@ solid_rhs_kernel(const double* __restrict__ U, const double* __restrict__ R, dou
   wR[FS + k] = (a00 * r1 - a10 * r0) / det;
 }
 
+// w_R = J_ee^-1 R_eps per node (node-local 2x2, see condense_solids).
+__global__ void __launch_bounds__(256)
+solid_rhs_kernel(const double* __restrict__ U, const double* __restrict__ R, double* __restrict__ wR,
+                 const uint8_t* __restrict__ phase, DevParams P, int np) {
+  const int64_t FS = P.Ne * np;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256)
+    solid_rhs_node(U, R, wR, phase, P, np, FS, k);
+}
+
 // Solid-fraction part of the Newton direction: d_eps = -w_R + w(du).
 __global__ void __launch_bounds__(256)
 solid_delta_kernel(const double* __restrict__ U, const double* __restrict__ du7,
                    const double* __restrict__ wR, double* __restrict__ deps,
                    const uint8_t* __restrict__ phase, DevParams P, int np) {
-  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const int64_t FS = P.Ne * np;
-  if (k >= FS) return;
-  const int ph = phase[k / np];
-  double us[9], vs[7];
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
+    const int ph = phase[k / np];
+    double us[9], vs[7];
 #pragma unroll
-  for (int f = 0; f < 9; ++f) us[f] = U[f * FS + k];
+    for (int f = 0; f < 9; ++f) us[f] = U[f * FS + k];
 #pragma unroll
-  for (int f = 0; f < 7; ++f) vs[f] = du7[f * FS + k];
-  double w0, w1;
-  condense_solids(P, ph, us, vs, w0, w1);
-  deps[k] = -wR[k] + w0;
-  deps[FS + k] = -wR[FS + k] + w1;
+    for (int f = 0; f < 7; ++f) vs[f] = du7[f * FS + k];
+    double w0, w1;
+    condense_solids(P, ph, us, vs, w0, w1);
+    deps[k] = -wR[k] + w0;
+    deps[FS + k] = -wR[FS + k] + w1;
+  }
 }
 
 // u_out = u (+) lam du: positive unknowns multiplicatively, x exp(lam du/x)
@@ -300,7 +336,7 @@ solid_merit_kernel(const double* __restrict__ R, const double* __restrict__ U, i
     const double x = fabs(U[(7 + s) * FS + (k % FS)]);
     const double sc = x > 1e-12 ? x : 1e-12;
     const double v = R[7 * FS + k] / (P.W3 * P.rhoM[s] * P.inv_dt * sc);
-    acc += v * v;
+    if (P.active & kSolidsBit) acc += v * v;
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;

@@ -99,6 +99,7 @@ DevParams make_params(const dg_ctx* c, double t_eval, double dt) {
   P.ny = c->mesh.ny;
   P.nz = c->mesh.nz;
   P.Ne = c->Ne;
+  P.active = kAllFields;
   return P;
 }
 
@@ -165,7 +166,7 @@ int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
 
 template <typename S>
 int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_opts& o,
-                 dg_step_report* rep, hipStream_t st) {
+                 dg_step_report* rep, hipStream_t st, int active = kAllFields) {
   const int64_t FS = ctx->Ne * ctx->np, n7 = 7 * FS, n9 = 9 * FS;
   const int m = o.gmres_restart;
   SolverWork& W = ctx->work;
@@ -186,7 +187,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipError_t e = pr.first->ensure(pr.second);
     if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_step workspace: ") + hipGetErrorString(e));
   }
-  const DevParams P = make_params(ctx, t_n + dt, dt);
+  DevParams P = make_params(ctx, t_n + dt, dt);
+  P.active = active;
   const double phi_floor = kGas * ctx->params.T / kFaraday;
   double* m_old = W.m_old.as<double>();
   double* R = W.R.as<double>();
@@ -265,6 +267,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // part of it vanishes exactly), so the Newton direction descends it.
   auto merit = [&](const double* Rv, double& out) -> int {
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n7), blk, 0, st, Rv, t, n7);
+    if (active != kAllFields) hipLaunchKernelGGL(mask_fields_kernel<S>, grid1(n7), blk, 0, st, t, FS, active);
     double cpart = 0.0;
     precond(t, pJ);
     if (o.coarse == 2) {
@@ -308,6 +311,11 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       std::vector<double> Ac(49), col(7);
       for (int f = 0; f < 7; ++f) {
         S* JZf = JZ + int64_t(f) * n7;
+        if (!((active >> f) & 1)) {            // inactive field: identity row and column
+          hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), JZf, S(0), JZf, n7);
+          for (int g = 0; g < 7; ++g) Ac[g * 7 + f] = (g == f) ? 1.0 : 0.0;
+          continue;
+        }
         hipLaunchKernelGGL(field_select_kernel<S>, grid1(n7), blk, 0, st, sc, f, t, FS);
         jvp_cond(t, JZf);
         hipLaunchKernelGGL(field_dot_kernel<S>, gred, blk, 0, st, sc, JZf, FS, partial);
@@ -315,7 +323,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
         std::vector<S> hs(7);
         DG_HIP(hipMemcpyAsync(hs.data(), dots, 7 * sizeof(S), hipMemcpyDeviceToHost, st));
         DG_HIP(hipStreamSynchronize(st));
-        for (int g = 0; g < 7; ++g) Ac[g * 7 + f] = double(hs[g]);
+        for (int g = 0; g < 7; ++g) Ac[g * 7 + f] = ((active >> g) & 1) ? double(hs[g]) : 0.0;
       }
       // symmetric equilibration D Ac D, D = |diag|^-1/2, before inverting:
       // the entries of Ac span many orders of magnitude
@@ -338,7 +346,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipLaunchKernelGGL(solid_rhs_kernel, grid1(FS), blk, 0, st, u, R, wR, ctx->d_phase, P, ctx->np);
     hipLaunchKernelGGL(solid_direction_kernel<S>, grid1(n9), blk, 0, st, wR, v9, FS);
     launch_q1<S, Dual<S>, kJvpFull>(ctx, P, uS, v9, nullptr, y9, st);
-    hipLaunchKernelGGL(condensed_rhs_kernel<S>, grid1(n7), blk, 0, st, R, y9, rhs, n7);
+    hipLaunchKernelGGL(condensed_rhs_kernel<S>, grid1(n7), blk, 0, st, R, y9, rhs, FS, active);
     hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), rhs, S(0), w, n7);
     precond(w, b);
     hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, b, b, n7);
@@ -831,6 +839,43 @@ int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* o
     return fail(DG_ENOMEM, "dg_step: host allocation failed");
   } catch (...) {
     return fail(DG_EINVAL, "dg_step: unexpected exception");
+  }
+}
+
+int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts,
+                     dg_step_report* report, dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (!u) return fail(DG_EINVAL, "dg_initial_state: null state");
+    dg_solver_opts o;
+    if (opts) o = *opts; else dg_solver_opts_default(&o);
+    if (o.gmres_restart < 1 || o.gmres_restart > kMaxDots - 2)
+      return fail(DG_EINVAL, "dg_initial_state: gmres_restart must be in 1..30");
+    if (o.newton_maxit < 1 || o.gmres_maxit < 1) return fail(DG_EINVAL, "dg_initial_state: iteration limits");
+    if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
+    if (o.coarse < 0) o.coarse = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (report) std::memset(report, 0, sizeof(*report));
+    const int64_t FS = ctx->Ne * ctx->np;
+    Conc6 c0{};
+    for (int f = 0; f < 6; ++f) c0.c[f] = ctx->eq.c[f];
+    const PhaseTable& pt = ctx->phase_tab;
+    hipLaunchKernelGGL(uniform_state_kernel, grid1(FS), dim3(256), 0, st, static_cast<double*>(u),
+                       ctx->d_phase, FS, ctx->np, c0, pt.epsS8init[0], pt.epsS8init[1], pt.epsLi2Sinit[0],
+                       pt.epsLi2Sinit[1]);
+    DG_HIP(hipGetLastError());
+    // charge rows only, at t0 with unit dt (the time terms of the frozen
+    // unknowns do not enter)
+    constexpr int kPhiOnly = 1 << 6;
+    if (o.inner_prec == DG_F32)
+      return newton_solve<float>(ctx, t0 - 1.0, 1.0, static_cast<double*>(u), o, report, st, kPhiOnly);
+    if (o.inner_prec == DG_F64)
+      return newton_solve<double>(ctx, t0 - 1.0, 1.0, static_cast<double*>(u), o, report, st, kPhiOnly);
+    return fail(DG_EINVAL, "dg_initial_state: bad inner precision");
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_initial_state: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_initial_state: unexpected exception");
   }
 }
 

@@ -81,6 +81,13 @@ struct PhaseTable {
   double epsLi2Sinit[2];
 };
 
+constexpr int32_t kAllFields = 0xff;
+
+struct Conc6 {
+  double c[6];
+};
+constexpr int32_t kSolidsBit = 0x80;
+
 // Parameter block handed to every kernel by value.  All arithmetic that
 // depends only on parameters is folded here on the host in double.
 struct DevParams {
@@ -102,7 +109,11 @@ struct DevParams {
   double TH;           // regularisation factor at the evaluation time
   double inv_dt;
   double epsCBD[2], aV0[2], s8ref[2], pass[2], react[2];
-  int32_t nx, ny, nz, pad;
+  int32_t nx, ny, nz;
+  // Unknowns taking part in a solve: bit f (f < 7) for the transported
+  // fields, bit 7 for the solid fractions.  Inactive rows of a tangent are
+  // zero and inactive solid fractions stay frozen (kAllFields: all active).
+  int32_t active;
   int64_t Ne;
 };
 

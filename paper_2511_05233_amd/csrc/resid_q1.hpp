@@ -78,7 +78,7 @@ __device__ __forceinline__ void condense_solids(const DevParams& P, int ph, cons
                                                 S& w0, S& w1) {
   w0 = S(0);
   w1 = S(0);
-  if (P.react[ph] == 0.0) return;
+  if (P.react[ph] == 0.0 || !(P.active & kSolidsBit)) return;
   using D = Dual<S>;
   D x[9], Sx[9];
 #pragma unroll
@@ -281,7 +281,10 @@ q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict_
   } else {
     constexpr int nout = (Mode == kJvpFull) ? 9 : 7;
 #pragma unroll
-    for (int f = 0; f < nout; ++f) Out[f * FS + e * 8 + n] = deriv_of(r[f]);
+    for (int f = 0; f < nout; ++f) {
+      const bool on = (P.active >> (f < 7 ? f : 7)) & 1;
+      Out[f * FS + e * 8 + n] = on ? deriv_of(r[f]) : S(0);
+    }
   }
 }
 
@@ -290,17 +293,16 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 mass_kernel(const T* __restrict__ U, T* __restrict__ M, const uint8_t* __restrict__ phase,
             DevParams P, int np) {
-  const int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const int64_t FS = P.Ne * np;
-  if (gid >= FS) return;
-  const int64_t e = gid / np;
-  const int ph = phase[e];
-  const T e7 = U[7 * FS + gid], e8 = U[8 * FS + gid];
-  const T eL = liquid_fraction(T(P.epsCBD[ph]), e7, e8, T(P.epsL_min));
+  for (int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x; gid < FS; gid += int64_t(gridDim.x) * 256) {
+    const int ph = phase[gid / np];
+    const T e7 = U[7 * FS + gid], e8 = U[8 * FS + gid];
+    const T eL = liquid_fraction(T(P.epsCBD[ph]), e7, e8, T(P.epsL_min));
 #pragma unroll
-  for (int i = 0; i < 6; ++i) M[i * FS + gid] = eL * U[i * FS + gid];
-  M[6 * FS + gid] = e7;
-  M[7 * FS + gid] = e8;
+    for (int i = 0; i < 6; ++i) M[i * FS + gid] = eL * U[i * FS + gid];
+    M[6 * FS + gid] = e7;
+    M[7 * FS + gid] = e8;
+  }
 }
 
 }  // namespace lsbdg

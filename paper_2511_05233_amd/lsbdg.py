@@ -38,6 +38,8 @@ _SIGNATURES = {
     "dg_solver_opts_default": (None, [C.c_void_p]),
     "dg_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p]),
+    "dg_initial_state": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -261,17 +263,38 @@ class Context:
         _check("dg_blockjacobi_export", self._lib.dg_blockjacobi_export(self._h, _ptr(out), _stream()))
         return out
 
+    def _opts(self, inner, opts):
+        o = DgSolverOpts()
+        self._lib.dg_solver_opts_default(C.byref(o))
+        o.inner_prec = DG_F32 if inner == "f32" else DG_F64
+        for k, v in opts.items():
+            setattr(o, k, v)
+        return o
+
+    def initial_state(self, u=None, t0=0.0, inner="f64", **opts):
+        """Equilibrium concentrations plus the steady potential (FP64, 9 fields)."""
+        import torch
+        if u is None:
+            u = torch.empty(self._shape(9), dtype=torch.float64, device="cuda")
+        self._check_arr(u, 9)
+        if u.dtype != torch.float64:
+            raise ValueError("the state is FP64")
+        o = self._opts(inner, opts)
+        rep = DgStepReport()
+        code = self._lib.dg_initial_state(self._h, float(t0), _ptr(u), C.byref(o), C.byref(rep), _stream())
+        if code != 0:
+            err = DgError("dg_initial_state", code, self._lib.dg_last_error().decode())
+            err.report = rep.as_dict()
+            raise err
+        return u, rep.as_dict()
+
     def step(self, u, t_n, dt, inner="f32", **opts):
         """One backward-Euler step in place on u (FP64, 9 fields); returns the report."""
         import torch
         self._check_arr(u, 9)
         if u.dtype != torch.float64:
             raise ValueError("the step state is FP64")
-        o = DgSolverOpts()
-        self._lib.dg_solver_opts_default(C.byref(o))
-        o.inner_prec = DG_F32 if inner == "f32" else DG_F64
-        for k, v in opts.items():
-            setattr(o, k, v)
+        o = self._opts(inner, opts)
         rep = DgStepReport()
         code = self._lib.dg_step(self._h, float(t_n), float(dt), _ptr(u), C.byref(o), C.byref(rep), _stream())
         if code != 0:

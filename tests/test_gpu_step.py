@@ -32,6 +32,56 @@ def small_case():
     return P, ctx, u0, u1
 
 
+def oracle_charge_noise(P, u0, m_old):
+    """Rounding level of the oracle's charge residual: at uniform
+    concentrations and uniform Phi_L its exact value is zero in every pore
+    voxel off the separator column, so whatever it returns there is the
+    rounding of its evaluation."""
+    uz = osolve.uniform_state(P)
+    uz[6] = u0[6].mean()
+    Rz = odg.residual(P, uz, m_old, 0.0, 1.0)[6]
+    ix = np.arange(P.n_elem) % P.nx
+    sel = (np.asarray(P.phase).reshape(-1) == 0) & (ix < P.nx - 1)
+    R0 = odg.residual(P, u0, m_old, 0.0, 1.0)[6]
+    return max(np.abs(Rz[sel]).max(), np.abs(R0).max())
+
+
+@pytest.fixture(scope="module")
+def phi_bound(small_case):
+    """Rounding-limited accuracy of the steady potential.
+
+    With frozen concentrations the level of Phi_L is fixed only by the
+    exchange currents (1e-3..1e-1 A/m^2 here), so the charge block is badly
+    conditioned (about 1e7): a rounding-level change of the residual moves
+    the root by up to sqrt(n) |dR|_max / sigma_min(J)."""
+    P, ctx, u0, _ = small_case
+    m_old = odg.old_mass(P, osolve.uniform_state(P))
+    J = osolve.sparse_jacobian(P, u0, m_old, 0.0, 1.0, fields=(6,)).toarray()
+    smin = np.linalg.svd(J, compute_uv=False)[-1]
+    noise = oracle_charge_noise(P, u0, m_old)
+    return m_old, noise, np.sqrt(J.shape[0]) * noise / smin
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_initial_state_matches_oracle(small_case, phi_bound, inner):
+    """Equilibrium concentrations and solid fractions exactly; Phi_L solves
+    the charge balance to the rounding level (GPU residual at the GPU root)
+    and lies within the conditioning bound of the oracle's root."""
+    P, ctx, u0, _ = small_case
+    m_old, noise, bound = phi_bound
+    ut, rep = ctx.initial_state(inner=inner, verbose=1)
+    print(f"[init] {inner} report {rep}", flush=True)
+    got = ut.cpu().numpy()
+    assert np.array_equal(got[[0, 1, 2, 3, 4, 5, 7, 8]], u0[[0, 1, 2, 3, 4, 5, 7, 8]])
+    diff = np.linalg.norm(got[6] - u0[6])
+    rel = diff / np.linalg.norm(u0[6])
+    r6 = np.abs(ctx.residual(ut, torch.tensor(m_old, device="cuda:0"), 0.0, 1.0)[6].cpu().numpy()).max()
+    print(f"  Phi_L |diff| {diff:.3e} V (relative {rel:.3e}), bound {bound:.3e}; "
+          f"GPU charge residual at its root {r6:.3e}, oracle rounding level {noise:.3e}", flush=True)
+    assert r6 <= 2 * noise
+    assert diff <= bound
+
+
 @pytest.mark.parametrize("inner,tol", [("f64", 1e-10), ("f32", 1e-8)])
 def test_step_matches_oracle_root(small_case, inner, tol):
     P, ctx, u0, u1 = small_case
@@ -55,6 +105,17 @@ def test_step_invariants_on_cube16():
                                        param_seed=w.param_seed, f_C=w.f_C)
     print("[step] oracle initial state 16^3", flush=True)
     u0, _ = osolve.initial_state(P)
+    ug, rep0 = ctx.initial_state(inner="f32")
+    ug = ug.cpu().numpy()
+    err0 = np.linalg.norm(ug[6] - u0[6]) / np.linalg.norm(u0[6])
+    m_init = odg.old_mass(P, osolve.uniform_state(P))
+    r6_gpu = np.abs(ctx.residual(torch.tensor(ug, device="cuda:0"), torch.tensor(m_init, device="cuda:0"),
+                                 0.0, 1.0)[6].cpu().numpy()).max()
+    noise = oracle_charge_noise(P, u0, m_init)
+    print(f"[step] GPU initial state {rep0}, Phi_L relative L2 {err0:.3e}, "
+          f"GPU charge residual {r6_gpu:.3e} (oracle rounding level {noise:.3e})", flush=True)
+    assert r6_gpu <= 2 * noise
+    assert err0 < 1e-7
     ut = torch.tensor(u0, device="cuda:0")
     rep = ctx.step(ut, 0.0, 0.1, inner="f32", verbose=1)
     print(f"[step] cube16 report {rep}", flush=True)
