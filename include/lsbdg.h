@@ -229,6 +229,72 @@ int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* o
 int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts,
                      dg_step_report* report, dg_stream stream);
 
+/* Battery outputs of a state u (device, FP64, 9 fields) at time t (the
+ * time enters the reaction current through T_H).  Any output pointer may
+ * be NULL.  Host results:
+ *   U_cell      cell voltage [V]: the anode Butler-Volmer law (Eq. 27,
+ *               k_E,Ano = 5e-3 mol/(s m^2), U0_Ano = 0) inverted in closed
+ *               form at each separator-face point, V - Phi_L - (2RT/F) ln y,
+ *               averaged over the separator face (App. A);
+ *   means[10]   volume averages of the nine unknowns and of the dissolved
+ *               sulfur c_S (Eq. A3);
+ *   sums[4]     sulfur atoms, lithium atoms, stored electrons [mol] and the
+ *               reaction current [A], with the nodal quadrature of the time
+ *               terms (at a step root the current equals j_el times the
+ *               separator area, and the atom counts change only by the
+ *               separator flux).
+ * Synchronises the stream. */
+int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* means, double* sums,
+               dg_stream stream);
+
+/* Adaptive time control (Sec. 2.7). */
+typedef enum { DG_CTRL_NAIVE = 0, DG_CTRL_H211B = 1 } dg_controller_kind;
+
+typedef struct {
+  int32_t kind;          /* dg_controller_kind */
+  int32_t max_halvings;  /* consecutive halvings before DG_ENOCONV (30) */
+  int32_t successes;     /* naive: converged steps before the step grows (3) */
+  int32_t sct;           /* naive: success counter (state) */
+  double dt;             /* size of the next trial step [s] (state) */
+  double dt_max;         /* cap on the step size [s] (100) */
+  double grow;           /* naive growth factor (1.2) */
+  double tol;            /* H211b tolerance on the relative step error */
+  double err_prev;       /* H211b history (state): error of the last accepted step */
+  double dt_prev;        /* H211b history (state): its step size */
+} dg_controller;
+
+/* Controller with the paper's settings, first trial step dt0 and (H211b)
+ * tolerance tol; before the first accepted step err_prev = tol and
+ * dt_prev = dt0. */
+void dg_controller_init(dg_controller* c, int32_t kind, double dt0, double tol);
+
+typedef struct {
+  double dt;             /* size of the accepted step [s] */
+  double err;            /* H211b: relative error of the accepted step (0 for naive) */
+  int32_t trials;        /* trial steps (H211b: coarse + two fine solves each) */
+  int32_t halvings;      /* solver failures answered by halving dt */
+  int32_t newton_its;    /* over all solves of this call */
+  int32_t gmres_its;
+} dg_advance_report;
+
+/* One accepted step of the controller c from time *t: on return u holds the
+ * state at *t (advanced by report.dt) and c its updated state.
+ * Naive: backward-Euler step of size c->dt; a failed solve halves dt and
+ * retries (the success counter restarts); after `successes` converged steps
+ * in a row dt grows by `grow`, capped at dt_max.
+ * H211b (Eq. 51-54): one coarse step (dt) and two fine steps (dt/2);
+ * err = ||z_F - z_C||_2 / ||z_F||_2 over all unknowns; rho = (tol/err)^(1/4)
+ * (tol/err_prev)^(1/4) (dt/dt_prev)^(-1/4), lim = 1 + atan(rho - 1); the
+ * trial is repeated with dt <- min(lim, 0.9) dt while err > 1.02 tol or
+ * lim < 0.9; on acceptance u = 2 z_F - z_C and the next dt is
+ * min(lim dt, dt_max).  A failed solve inside a trial halves dt.
+ * Non-convergence and non-finite residuals count as failed solves; after
+ * more than max_halvings in one call: DG_ENOCONV with u and *t unchanged.
+ * Device workspace: up to three extra FP64 states, kept.  Synchronises the
+ * stream. */
+int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u, const dg_solver_opts* opts,
+               dg_advance_report* report, dg_stream stream);
+
 /* Human-readable description of the last error on this thread. */
 const char* dg_last_error(void);
 

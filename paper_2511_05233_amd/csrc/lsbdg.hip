@@ -19,6 +19,7 @@
 #include "resid_q1.hpp"
 #include "blockjacobi.hpp"
 #include "solver.hpp"
+#include "outputs.hpp"
 
 using namespace lsbdg;
 
@@ -544,6 +545,26 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   return DG_OK;
 }
 
+// Checked copy of the solver options with the precision-dependent default
+// coarse space filled in.
+int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) {
+  if (in) o = *in; else dg_solver_opts_default(&o);
+  if (o.gmres_restart < 1 || o.gmres_restart > kMaxDots - 2)
+    return fail(DG_EINVAL, std::string(fn) + ": gmres_restart must be in 1..30");
+  if (o.newton_maxit < 1 || o.gmres_maxit < 1) return fail(DG_EINVAL, std::string(fn) + ": iteration limits");
+  if (o.inner_prec != DG_F32 && o.inner_prec != DG_F64)
+    return fail(DG_EINVAL, std::string(fn) + ": bad inner precision");
+  if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
+  if (o.coarse < 0) o.coarse = 0;
+  return DG_OK;
+}
+
+int solve_once(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_opts& o, dg_step_report* rep,
+               hipStream_t st, int active = kAllFields) {
+  if (o.inner_prec == DG_F32) return newton_solve<float>(ctx, t_n, dt, u, o, rep, st, active);
+  return newton_solve<double>(ctx, t_n, dt, u, o, rep, st, active);
+}
+
 }  // namespace
 
 extern "C" {
@@ -822,19 +843,9 @@ int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* o
     if (!u) return fail(DG_EINVAL, "dg_step: null state");
     if (!(dt > 0)) return fail(DG_EINVAL, "dg_step: dt must be positive");
     dg_solver_opts o;
-    if (opts) o = *opts; else dg_solver_opts_default(&o);
-    if (o.gmres_restart < 1 || o.gmres_restart > kMaxDots - 2)
-      return fail(DG_EINVAL, "dg_step: gmres_restart must be in 1..30");
-    if (o.newton_maxit < 1 || o.gmres_maxit < 1) return fail(DG_EINVAL, "dg_step: iteration limits");
-    if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
-    if (o.coarse < 0) o.coarse = 0;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (int s = normalize_opts(opts, o, "dg_step")) return s;
     if (report) std::memset(report, 0, sizeof(*report));
-    if (o.inner_prec == DG_F32)
-      return newton_solve<float>(ctx, t_n, dt, static_cast<double*>(u), o, report, st);
-    if (o.inner_prec == DG_F64)
-      return newton_solve<double>(ctx, t_n, dt, static_cast<double*>(u), o, report, st);
-    return fail(DG_EINVAL, "dg_step: bad inner precision");
+    return solve_once(ctx, t_n, dt, static_cast<double*>(u), o, report, static_cast<hipStream_t>(stream));
   } catch (const std::bad_alloc&) {
     return fail(DG_ENOMEM, "dg_step: host allocation failed");
   } catch (...) {
@@ -848,12 +859,7 @@ int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts
     if (int s = check_ctx(ctx)) return s;
     if (!u) return fail(DG_EINVAL, "dg_initial_state: null state");
     dg_solver_opts o;
-    if (opts) o = *opts; else dg_solver_opts_default(&o);
-    if (o.gmres_restart < 1 || o.gmres_restart > kMaxDots - 2)
-      return fail(DG_EINVAL, "dg_initial_state: gmres_restart must be in 1..30");
-    if (o.newton_maxit < 1 || o.gmres_maxit < 1) return fail(DG_EINVAL, "dg_initial_state: iteration limits");
-    if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
-    if (o.coarse < 0) o.coarse = 0;
+    if (int s = normalize_opts(opts, o, "dg_initial_state")) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (report) std::memset(report, 0, sizeof(*report));
     const int64_t FS = ctx->Ne * ctx->np;
@@ -867,15 +873,195 @@ int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts
     // charge rows only, at t0 with unit dt (the time terms of the frozen
     // unknowns do not enter)
     constexpr int kPhiOnly = 1 << 6;
-    if (o.inner_prec == DG_F32)
-      return newton_solve<float>(ctx, t0 - 1.0, 1.0, static_cast<double*>(u), o, report, st, kPhiOnly);
-    if (o.inner_prec == DG_F64)
-      return newton_solve<double>(ctx, t0 - 1.0, 1.0, static_cast<double*>(u), o, report, st, kPhiOnly);
-    return fail(DG_EINVAL, "dg_initial_state: bad inner precision");
+    return solve_once(ctx, t0 - 1.0, 1.0, static_cast<double*>(u), o, report, st, kPhiOnly);
   } catch (const std::bad_alloc&) {
     return fail(DG_ENOMEM, "dg_initial_state: host allocation failed");
   } catch (...) {
     return fail(DG_EINVAL, "dg_initial_state: unexpected exception");
+  }
+}
+
+int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* means, double* sums,
+               dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (!u) return fail(DG_EINVAL, "dg_outputs: null state");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    constexpr int nb = 1024;
+    SolverWork& W = ctx->work;
+    hipError_t e = W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double));
+    if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_outputs workspace: ") + hipGetErrorString(e));
+    const DevParams P = make_params(ctx, t, 1.0);
+    const double RT = kGas * ctx->params.T;
+    const double q = ctx->j_el / (kFaraday * kKEanode);
+    hipLaunchKernelGGL(outputs_kernel, dim3(nb), dim3(256), 0, st, static_cast<const double*>(u), ctx->d_phase,
+                       P, q, 2.0 * RT / kFaraday, W.out_partial.as<double>());
+    DG_HIP(hipGetLastError());
+    std::vector<double> part(size_t(kNumSums) * nb);
+    DG_HIP(hipMemcpyAsync(part.data(), W.out_partial.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    double acc[kNumSums];
+    for (int j = 0; j < kNumSums; ++j) {
+      double a = 0.0;
+      for (int b = 0; b < nb; ++b) a += part[size_t(j) * nb + b];
+      acc[j] = a;
+    }
+    const double nodes = double(ctx->Ne) * ctx->np;
+    if (means)
+      for (int f = 0; f < 10; ++f) means[f] = acc[f] / nodes;
+    if (sums)
+      for (int j = 0; j < 4; ++j) sums[j] = acc[10 + j];
+    if (U_cell) *U_cell = acc[14] / (double(ctx->mesh.ny) * ctx->mesh.nz * 4.0);
+    return DG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_outputs: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_outputs: unexpected exception");
+  }
+}
+
+void dg_controller_init(dg_controller* c, int32_t kind, double dt0, double tol) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->kind = kind;
+  c->max_halvings = 30;
+  c->successes = 3;
+  c->sct = 0;
+  c->dt = dt0;
+  c->dt_max = 100.0;
+  c->grow = 1.2;
+  c->tol = tol;
+  c->err_prev = tol;
+  c->dt_prev = dt0;
+}
+
+int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solver_opts* opts,
+               dg_advance_report* report, dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (!c || !t || !u_) return fail(DG_EINVAL, "dg_advance: null argument");
+    if (!(c->dt > 0) || !(c->dt_max > 0)) return fail(DG_EINVAL, "dg_advance: step sizes must be positive");
+    if (c->kind != DG_CTRL_NAIVE && c->kind != DG_CTRL_H211B) return fail(DG_EINVAL, "dg_advance: controller kind");
+    if (c->kind == DG_CTRL_H211B && !(c->tol > 0)) return fail(DG_EINVAL, "dg_advance: H211b needs tol > 0");
+    dg_solver_opts o;
+    if (int s = normalize_opts(opts, o, "dg_advance")) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* u = static_cast<double*>(u_);
+    const int64_t n9 = 9 * ctx->Ne * ctx->np;
+    const size_t bytes = size_t(n9) * sizeof(double);
+    SolverWork& W = ctx->work;
+    for (DevBuf* b : {&W.z0, &W.zC, &W.zF}) {
+      if (b != &W.z0 && c->kind != DG_CTRL_H211B) continue;
+      hipError_t e = b->ensure(bytes);
+      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_advance workspace: ") + hipGetErrorString(e));
+    }
+    double* z0 = W.z0.as<double>();
+    DG_HIP(hipMemcpyAsync(z0, u, bytes, hipMemcpyDeviceToDevice, st));
+    dg_advance_report r{};
+    auto solve = [&](double* z, double tn, double dt) -> int {
+      dg_step_report sr{};
+      const int s = solve_once(ctx, tn, dt, z, o, &sr, st);
+      r.newton_its += sr.newton_its;
+      r.gmres_its += sr.gmres_its;
+      return s;
+    };
+    auto failed_solve = [](int s) { return s == DG_ENOCONV || s == DG_ENAN; };
+    auto restore = [&]() -> int {
+      DG_HIP(hipMemcpyAsync(u, z0, bytes, hipMemcpyDeviceToDevice, st));
+      DG_HIP(hipStreamSynchronize(st));
+      return DG_OK;
+    };
+    int halvings = 0;
+    if (c->kind == DG_CTRL_NAIVE) {
+      for (;;) {
+        const double dt = c->dt;
+        ++r.trials;
+        const int s = solve(u, *t, dt);
+        if (s == DG_OK) {
+          if (++c->sct >= c->successes) {
+            c->dt = std::min(dt * c->grow, c->dt_max);
+            c->sct = 0;
+          }
+          *t += dt;
+          r.dt = dt;
+          break;
+        }
+        if (int e = restore()) return e;
+        if (!failed_solve(s)) return s;
+        ++halvings;
+        ++r.halvings;
+        c->sct = 0;
+        if (halvings > c->max_halvings) {
+          if (report) *report = r;
+          return fail(DG_ENOCONV, "dg_advance: more than max_halvings consecutive halvings");
+        }
+        c->dt = dt / 2;
+      }
+    } else {
+      double* zC = W.zC.as<double>();
+      double* zF = W.zF.as<double>();
+      double lim = 0.0, err = HUGE_VAL, dt = c->dt;
+      constexpr int nb = 1024;
+      hipError_t e = W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double));
+      if (e != hipSuccess) return fail(DG_ENOMEM, "dg_advance workspace");
+      while (lim < 0.9 || err > 1.02 * c->tol) {
+        dt = c->dt;
+        ++r.trials;
+        DG_HIP(hipMemcpyAsync(zC, z0, bytes, hipMemcpyDeviceToDevice, st));
+        int s = solve(zC, *t, dt);
+        if (s == DG_OK) {
+          DG_HIP(hipMemcpyAsync(zF, z0, bytes, hipMemcpyDeviceToDevice, st));
+          s = solve(zF, *t, dt / 2);
+          if (s == DG_OK) s = solve(zF, *t + dt / 2, dt / 2);
+        }
+        if (s != DG_OK) {
+          if (!failed_solve(s)) {
+            (void)restore();
+            return s;
+          }
+          ++halvings;
+          ++r.halvings;
+          if (halvings > c->max_halvings) {
+            if (report) *report = r;
+            return fail(DG_ENOCONV, "dg_advance: more than max_halvings consecutive halvings");
+          }
+          c->dt = dt / 2;
+          lim = 0.0;
+          err = HUGE_VAL;
+          continue;
+        }
+        hipLaunchKernelGGL(diff_norm_kernel, dim3(nb), dim3(256), 0, st, zF, zC, n9, W.out_partial.as<double>());
+        DG_HIP(hipGetLastError());
+        std::vector<double> part(2 * nb);
+        DG_HIP(hipMemcpyAsync(part.data(), W.out_partial.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        DG_HIP(hipStreamSynchronize(st));
+        double d2 = 0.0, f2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          d2 += part[b];
+          f2 += part[nb + b];
+        }
+        err = std::max(std::sqrt(d2) / std::sqrt(f2), 1e-300);
+        const double rho = std::pow(c->tol / err, 0.25) * std::pow(c->tol / c->err_prev, 0.25) *
+                           std::pow(dt / c->dt_prev, -0.25);
+        lim = 1.0 + std::atan(rho - 1.0);
+        if (lim < 0.9 || err > 1.02 * c->tol) c->dt = std::min(lim, 0.9) * dt;
+      }
+      hipLaunchKernelGGL(richardson_kernel, grid1(n9), dim3(256), 0, st, zF, zC, u, n9);
+      DG_HIP(hipGetLastError());
+      DG_HIP(hipStreamSynchronize(st));
+      c->err_prev = err;
+      c->dt_prev = dt;
+      c->dt = std::min(lim * dt, c->dt_max);
+      *t += dt;
+      r.dt = dt;
+      r.err = err;
+    }
+    if (report) *report = r;
+    return DG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_advance: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_advance: unexpected exception");
   }
 }
 

@@ -40,6 +40,11 @@ _SIGNATURES = {
                           C.c_void_p]),
     "dg_initial_state": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]),
+    "dg_outputs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
+    "dg_controller_init": (None, [C.c_void_p, C.c_int32, C.c_double, C.c_double]),
+    "dg_advance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -70,6 +75,34 @@ class DgStepReport(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+DG_CTRL_NAIVE, DG_CTRL_H211B = 0, 1
+
+
+class DgController(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("max_halvings", C.c_int32), ("successes", C.c_int32),
+                ("sct", C.c_int32), ("dt", C.c_double), ("dt_max", C.c_double), ("grow", C.c_double),
+                ("tol", C.c_double), ("err_prev", C.c_double), ("dt_prev", C.c_double)]
+
+
+class DgAdvanceReport(C.Structure):
+    _fields_ = [("dt", C.c_double), ("err", C.c_double), ("trials", C.c_int32), ("halvings", C.c_int32),
+                ("newton_its", C.c_int32), ("gmres_its", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def controller(kind="naive", dt0=0.1, tol=1e-5, dt_max=None):
+    """Time controller state (naive or H211b) with the paper's settings."""
+    lib = load()
+    c = DgController()
+    lib.dg_controller_init(C.byref(c), DG_CTRL_H211B if kind == "h211b" else DG_CTRL_NAIVE,
+                           float(dt0), float(tol))
+    if dt_max is not None:
+        c.dt_max = float(dt_max)
+    return c
 
 
 class DgError(RuntimeError):
@@ -302,3 +335,30 @@ class Context:
             err.report = rep.as_dict()
             raise err
         return rep.as_dict()
+
+    def outputs(self, u, t):
+        """U_cell [V], means (9 unknowns + c_S), sums (S, Li, electrons [mol], current [A])."""
+        self._check_arr(u, 9)
+        U = C.c_double()
+        means = (C.c_double * 10)()
+        sums = (C.c_double * 4)()
+        _check("dg_outputs", self._lib.dg_outputs(self._h, _ptr(u), float(t), C.byref(U), means, sums,
+                                                  _stream()))
+        return {"U_cell": U.value, "means": np.array(means[:]), "sums": np.array(sums[:])}
+
+    def advance(self, ctrl, t, u, inner="f32", **opts):
+        """One accepted controller step from t (u in place); returns (t_new, report)."""
+        import torch
+        self._check_arr(u, 9)
+        if u.dtype != torch.float64:
+            raise ValueError("the state is FP64")
+        o = self._opts(inner, opts)
+        rep = DgAdvanceReport()
+        tt = C.c_double(float(t))
+        code = self._lib.dg_advance(self._h, C.byref(ctrl), C.byref(tt), _ptr(u), C.byref(o), C.byref(rep),
+                                    _stream())
+        if code != 0:
+            err = DgError("dg_advance", code, self._lib.dg_last_error().decode())
+            err.report = rep.as_dict()
+            raise err
+        return tt.value, rep.as_dict()

