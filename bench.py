@@ -1,7 +1,8 @@
 """Benchmark of the DG hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--dt S] [--inner f32|f64]
-                    [--workload slab96_q1] [--compare-f64] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--mode newton|controller] [--dt S]
+                    [--inner f32|f64] [--workload slab96_q1] [--compare-f64]
+                    [--no-cpu-baseline] [--kernels-only] [--copy-probe]
 
 Workload (default): the 96 x 96 x 192 voxel cathode slab (x = transport
 axis, 1 um voxels), DG-Q1, 9 unknowns per node of which 7 are transported
@@ -9,22 +10,24 @@ axis, 1 um voxels), DG-Q1, 9 unknowns per node of which 7 are transported
 synthetic transport and kinetic parameters, constant 1C discharge current.
 All inputs are synthetic, seeded and resident in HBM before timing starts.
 
-Set-up (untimed): the context, the initial state of the discharge on the
+Set-up (untimed): the context and the initial state of the discharge on the
 GPU (equilibrium concentrations and the steady potential).
 
-A step is one accepted step of the discharge under the naive time
-controller (every part of the hot path: FP64 residual and Newton update,
-element block-Jacobi assembly and inversion, condensed JVP, block apply,
-GMRES and coarse correction, halving dt after a failed solve), inner solve
-in FP32 by default.  The K timed steps continue the discharge from the W
-warm-up steps.  ms_per_step is their mean wall time.
+A step (--mode newton, the default) is one Newton iteration of the first
+implicit step of the discharge (dt = 0.1 s): FP64 residual, linearisation,
+element block-Jacobi assembly and inversion, the full GMRES solve (condensed
+JVP, block apply, coarse correction, Gram-Schmidt) and the line-searched
+FP64 update -- every part of the hot path but the time controller.  The W
+warm-up and the K timed iterations each run as one dg_step call limited to
+that many Newton iterations.  --mode controller times K accepted steps of
+the naive controller instead (an implicit step is 10-20 Newton iterations).
 
 value = DG operator GDoF/s: transported DoF / mean duration of one
-application of the Krylov operator (the condensed tangent, in the inner
-precision) at the state the timed steps reached, timed with HIP events on
-the stream it runs on.  roofline = the kernel with the largest share of the
-step (the block apply: one per GMRES iteration) against the HBM peak; the
-other kernels are listed beside it.
+application of the Krylov operator (the condensed tangent at a stored
+linearisation, in the inner precision), timed with HIP events on the stream
+it runs on.  roofline = the kernel with the largest share of a Newton
+iteration (the block apply: one per GMRES iteration) against the HBM peak;
+the other kernels are listed beside it.
 """
 from __future__ import annotations
 
@@ -70,6 +73,17 @@ def cpu_baseline(w, budget_s=12.0):
                       f"of the same workload, {n} applications in {wall:.1f} s"}
 
 
+def copy_probe(dev):
+    """Three plain device copies of 1 GiB (reference for the HBM byte counters)."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return a.numel() * 8
+
+
 def time_launches(fn, stream, reps):
     """Mean duration [ms] of fn() over reps launches, HIP events on `stream`."""
     import torch
@@ -82,6 +96,77 @@ def time_launches(fn, stream, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def random_state(ctx, mask, seed, dev):
+    """Seeded positive state around the equilibrium values (9 fields, FP64), on the device."""
+    import torch
+    g = torch.Generator(device=dev).manual_seed(seed)
+    Ne, npn = ctx.n_elem, ctx.n_nodes
+    typical = [1500.0, 6.0, 6.2e-3, 3.9e-3, 1.9e-3, 3.6e-12, 0.0, 0.2375, 6.9e-6]
+    u = torch.empty((9, Ne, npn), dtype=torch.float64, device=dev)
+    for f in range(9):
+        z = torch.randn((Ne, npn), generator=g, dtype=torch.float64, device=dev)
+        u[f] = 5e-3 * z if f == 6 else typical[f] * torch.exp(0.1 * z)
+    pore = torch.tensor(mask.reshape(-1) == 0, device=dev)
+    u[7:9, pore, :] = 0
+    return u
+
+
+def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
+    """The step's kernels, each timed alone (HIP events) at state u."""
+    import torch
+    S = torch.float32 if inner == "f32" else torch.float64
+    sb = 4 if S == torch.float32 else 8
+    nodes = ctx.n_elem * ctx.n_nodes
+    uS = u.to(S)
+    g = torch.Generator(device=dev).manual_seed(7)
+    v7 = torch.randn((7, ctx.n_elem, ctx.n_nodes), generator=g, dtype=S, device=dev)
+    y7 = torch.empty_like(v7)
+    m8 = ctx.mass(u)
+    r9 = torch.empty_like(u)
+    reps = 20
+    log("[bench] timing kernels")
+    ms_lin = time_launches(lambda: ctx.linearize(uS, t, dt), stream, 5)
+    ms_jvp = time_launches(lambda: ctx.jvp(uS, v7, t, dt, out=y7, linearized=True), stream, reps)
+    ms_res = time_launches(lambda: ctx.residual(u, m8, t, dt, out=r9), stream, reps)
+    ctx.blockjacobi_setup(uS, t, dt)
+    ms_apply = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7), stream, reps)
+    ms_setup = time_launches(lambda: ctx.blockjacobi_setup(uS, t, dt), stream, 3)
+
+    def gbs(nbytes, ms):
+        return nbytes / (ms * 1e-3) / 1e9
+
+    b_jvp = nodes * (9 + 7 + 14 + 7) * sb + ctx.n_elem      # u, v, coefficients in; Jv out; phase
+    b_res = nodes * (9 + 8 + 9) * 8 + ctx.n_elem            # u, old mass in; R out; phase
+    b_apply = ctx.n_elem * (56 * 56 + 2 * 56) * sb          # blocks, x in, y out
+    kernels = {
+        "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp},
+        "residual_f64": {"ms": ms_res, "GB/s": gbs(b_res, ms_res), "bytes": b_res},
+        "block_apply": {"ms": ms_apply, "GB/s": gbs(b_apply, ms_apply), "bytes": b_apply},
+        "block_setup": {"ms": ms_setup},
+        "linearize": {"ms": ms_lin},
+    }
+    for k in kernels.values():
+        if "GB/s" in k:
+            k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 4)
+            k["GB/s"] = round(k["GB/s"], 1)
+        k["ms"] = round(k["ms"], 4)
+    return kernels, (b_apply, ms_apply)
+
+
+def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0):
+    """n Newton iterations of the implicit step from (t, u) (one dg_step call)."""
+    from paper_2511_05233_amd import lsbdg
+    try:
+        rep = ctx.step(u, t, dt, inner=inner, verbose=verbose, newton_maxit=n)
+    except lsbdg.DgError as e:
+        if e.code != -4:                      # DG_ENOCONV: the iteration cap was reached
+            raise
+        rep = e.report
+    log(f"[bench] {rep['newton_its']} Newton iterations, {rep['gmres_its']} GMRES, "
+        f"update {rep['last_update']:.2e}")
+    return rep
 
 
 def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0):
@@ -101,6 +186,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="newton", choices=["newton", "controller"])
     ap.add_argument("--dt", type=float, default=0.1, help="first trial step [s]")
     ap.add_argument("--inner", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="slab96_q1")
@@ -108,6 +194,9 @@ def main(argv=None):
                     help="repeat the timed steps with an FP64 inner solve from the same state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0, help="Newton progress lines on stderr")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling aid: skip the solves and time the kernels alone on a seeded "
+                         "random state (prints the kernel table, not the benchmark line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -132,62 +221,52 @@ def main(argv=None):
     n_dof = ctx.n_elem * ctx.n_nodes * 7
     nodes = ctx.n_elem * ctx.n_nodes
 
+    if args.kernels_only:
+        u = random_state(ctx, mask, 1, dev)
+        t = 0.5
+        kernels, _ = time_kernels(ctx, u, t, args.dt, args.inner, stream, dev, log)
+        out = {"workload": w.name, "inner": args.inner, "kernels": kernels}
+        if args.copy_probe:
+            out["copy_probe_bytes"] = copy_probe(dev)
+        print(json.dumps(out), flush=True)
+        return 0
     u, rep0 = ctx.initial_state(inner=args.inner, verbose=args.verbose)
     log(f"[bench] initial state: {rep0['newton_its']} Newton, {rep0['gmres_its']} GMRES")
     t = 0.0
-    ctrl = lsbdg.controller("naive", dt0=args.dt)
-    t, _ = run_steps(ctx, ctrl, u, t, args.warmup, args.inner, log, args.verbose)
-    u_start = u.clone() if args.compare_f64 else None
-    ctrl_start = lsbdg.DgController.from_buffer_copy(ctrl)
-    t_start = t
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    t, tot = run_steps(ctx, ctrl, u, t, args.steps, args.inner, log, args.verbose)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_step = wall * 1e3 / args.steps
+    if args.mode == "newton":
+        newton_iterations(ctx, u, t, args.dt, args.warmup, args.inner, log, args.verbose)
+        u_start = u.clone() if args.compare_f64 else None
+        t_start = t
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        rep = newton_iterations(ctx, u, t, args.dt, args.steps, args.inner, log, args.verbose)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        done = max(rep["newton_its"], 1)
+        ms_step = wall * 1e3 / done
+        tot = {"newton_its": rep["newton_its"], "gmres_its": rep["gmres_its"]}
+    else:
+        ctrl = lsbdg.controller("naive", dt0=args.dt)
+        t, _ = run_steps(ctx, ctrl, u, t, args.warmup, args.inner, log, args.verbose)
+        u_start = u.clone() if args.compare_f64 else None
+        ctrl_start = lsbdg.DgController.from_buffer_copy(ctrl)
+        t_start = t
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t, tot = run_steps(ctx, ctrl, u, t, args.steps, args.inner, log, args.verbose)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        done = args.steps
+        ms_step = wall * 1e3 / args.steps
 
-    # kernels of the step, each timed alone at the reached state
-    S = torch.float32 if args.inner == "f32" else torch.float64
-    sb = 4 if S == torch.float32 else 8
-    uS = u.to(S)
-    g = torch.Generator(device=dev).manual_seed(7)
-    v7 = torch.randn((7, ctx.n_elem, ctx.n_nodes), generator=g, dtype=S, device=dev)
-    y7 = torch.empty_like(v7)
-    m8 = ctx.mass(u)
-    r9 = torch.empty_like(u)
-    reps = 20
-    ms_jvp = time_launches(lambda: ctx.jvp(uS, v7, t, args.dt, out=y7, condensed=True), stream, reps)
-    ms_res = time_launches(lambda: ctx.residual(u, m8, t, args.dt, out=r9), stream, reps)
-    ctx.blockjacobi_setup(u, t, args.dt, dtype=S)
-    ms_apply = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7), stream, reps)
-    ms_setup = time_launches(lambda: ctx.blockjacobi_setup(u, t, args.dt, dtype=S), stream, 3)
-
-    def gbs(nbytes, ms):
-        return nbytes / (ms * 1e-3) / 1e9
-
-    b_jvp = nodes * (9 + 7 + 7) * sb + ctx.n_elem           # u, v in; Jv out; phase
-    b_res = nodes * (9 + 8 + 9) * 8 + ctx.n_elem            # u, old mass in; R out; phase
-    b_apply = ctx.n_elem * (56 * 56 + 2 * 56) * sb          # blocks, x in, y out
-    kernels = {
-        "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp},
-        "residual_f64": {"ms": ms_res, "GB/s": gbs(b_res, ms_res), "bytes": b_res},
-        "block_apply": {"ms": ms_apply, "GB/s": gbs(b_apply, ms_apply), "bytes": b_apply},
-        "block_setup": {"ms": ms_setup},
-    }
-    for k in kernels.values():
-        if "GB/s" in k:
-            k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 4)
-            k["GB/s"] = round(k["GB/s"], 1)
-        k["ms"] = round(k["ms"], 4)
-
-    achieved = gbs(b_apply, ms_apply)
+    kernels, (b_apply, ms_apply) = time_kernels(ctx, u, t, args.dt, args.inner, stream, dev, log)
+    achieved = b_apply / (ms_apply * 1e-3) / 1e9
     out = {
         "metric": METRIC,
-        "value": round(n_dof / (ms_jvp * 1e-3) / 1e9, 3),
+        "value": round(n_dof / (kernels["jvp_condensed"]["ms"] * 1e-3) / 1e9, 3),
         "unit": "GDoF/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": done,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 2),
         "higher_is_better": True,
@@ -198,13 +277,13 @@ def main(argv=None):
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} voxels of {w.h * 1e6:g} um, "
                                f"DG-Q{w.order}, 7 transported + 2 node-local fields, porosity "
                                f"{w.porosity} (mask seed {w.mask_seed}), {w.f_C}C discharge",
-                   "dof": n_dof, "dt0_s": args.dt, "t_start_s": round(t_start, 6),
-                   "t_end_s": round(t, 6),
-                   "step": "accepted step of the naive time controller: backward-Euler solves "
-                           "(Newton in FP64 + GMRES(30) with element block-Jacobi and coarse "
-                           "correction), halving dt on failed solves",
-                   "trials": tot["trials"], "halvings": tot["halvings"],
-                   "newton_its": tot["newton_its"], "gmres_its": tot["gmres_its"]},
+                   "dof": n_dof, "dt_s": args.dt, "t_start_s": round(t_start, 6),
+                   "step": ("Newton iteration of the first implicit step: FP64 residual, linearisation, "
+                            "block-Jacobi setup, GMRES(30) with block-Jacobi and coarse correction, "
+                            "FP64 update" if args.mode == "newton" else
+                            "accepted step of the naive time controller (backward-Euler Newton-GMRES "
+                            "solves, halving dt on failure)"),
+                   "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "apply_blocks_kernel", "ms": round(ms_apply, 4),
@@ -215,23 +294,23 @@ def main(argv=None):
         u64 = u_start.clone()
         torch.cuda.synchronize()
         w1 = time.perf_counter()
-        ctrl64 = lsbdg.DgController.from_buffer_copy(ctrl_start)
-        _, tot64 = run_steps(ctx, ctrl64, u64, t_start, args.steps, "f64", log, args.verbose)
+        if args.mode == "newton":
+            rep64 = newton_iterations(ctx, u64, t_start, args.dt, args.steps, "f64", log, args.verbose)
+            tot64 = {"newton_its": rep64["newton_its"], "gmres_its": rep64["gmres_its"]}
+        else:
+            ctrl64 = lsbdg.DgController.from_buffer_copy(ctrl_start)
+            _, tot64 = run_steps(ctx, ctrl64, u64, t_start, args.steps, "f64", log, args.verbose)
         torch.cuda.synchronize()
         wall64 = time.perf_counter() - w1
         rel = [float(torch.linalg.norm(u[f] - u64[f]) / torch.clamp(torch.linalg.norm(u64[f]), min=1e-300))
                for f in range(9)]
-        out["f64_inner"] = {"ms_per_step": round(wall64 * 1e3 / args.steps, 2),
+        out["f64_inner"] = {"ms_per_step": round(wall64 * 1e3 / max(tot64["newton_its"] if args.mode == "newton"
+                                                                   else args.steps, 1), 2),
                             "newton_its": tot64["newton_its"], "gmres_its": tot64["gmres_its"],
                             "mixed_speedup": round(wall64 / wall, 3),
                             "rel_l2_mixed_vs_f64": [float(f"{x:.3e}") for x in rel]}
     if args.copy_probe:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = a.numel() * 8
+        out["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -66,8 +66,13 @@ typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_prec;
  *   DG_JVP_FULL9:      v and J v over all 9 fields.
  *   DG_JVP_CONDENSED7: v and J v over the 7 transported fields; the solid
  *     fractions are eliminated node by node (their rows hold no spatial
- *     coupling): J_red v = J_uu v + J_ue w with w = -J_ee^-1 J_eu v. */
-typedef enum { DG_JVP_FULL9 = 0, DG_JVP_CONDENSED7 = 1 } dg_jvp_mode;
+ *     coupling): J_red v = J_uu v + J_ue w with w = -J_ee^-1 J_eu v.  The
+ *     node-local coefficients of w (w = C v, C: 2 x 7 per node) are formed
+ *     first (as dg_linearize does), then applied.
+ *   DG_JVP_LINEARIZED7: as DG_JVP_CONDENSED7 with the coefficients of the
+ *     last dg_linearize call of the same precision, which must have been at
+ *     this u, t_new and dt (the Krylov operator of one Newton iteration). */
+typedef enum { DG_JVP_FULL9 = 0, DG_JVP_CONDENSED7 = 1, DG_JVP_LINEARIZED7 = 2 } dg_jvp_mode;
 
 /* Mesh: voxel counts, voxel edge h [m], polynomial degree per axis. */
 typedef struct {
@@ -138,9 +143,16 @@ int dg_residual(dg_ctx* ctx, dg_prec prec, const void* u, const void* m_old,
  * the exact derivative of the same arithmetic (forward-mode dual numbers),
  * with zero derivative where a clamp is active.  The old mass does not
  * enter.  u: device, 9 fields; v and jv: device, 9 fields (DG_JVP_FULL9) or
- * 7 fields (DG_JVP_CONDENSED7); all in the precision prec. */
+ * 7 fields (condensed modes); all in the precision prec.  DG_ESTATE:
+ * DG_JVP_LINEARIZED7 without a linearisation of that precision. */
 int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const void* v,
            double t_new, double dt, void* jv, dg_stream stream);
+
+/* Linearisation point of the condensed tangent: stores in library-owned
+ * device memory (14 values per node, precision prec) the coefficients C of
+ * the node-local elimination w = -J_ee^-1 J_eu v = C v at (u, t_new, dt),
+ * for later DG_JVP_LINEARIZED7 products.  u: device, 9 fields. */
+int dg_linearize(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt, dg_stream stream);
 
 /* Element block-Jacobi preconditioner (replaces the paper's BoomerAMG
  * preconditioner of Sec. 2.8 inside GMRES).  Builds the exact
@@ -173,7 +185,7 @@ typedef struct {
   double gmres_rtol;     /* relative reduction of the preconditioned, scaled
                             residual per Newton iteration (default 1e-4) */
   double gmres_rtol_final; /* tolerance once the Newton update is below 1e-7
-                            (default 1e-9) */
+                            (default 1e-11; FP32 inner solves stop at 1e-5) */
   double newton_tol;     /* converged when a full step changes no unknown by
                             more than this relative amount (default 1e-11) */
   int32_t coarse;        /* global per-field coarse space: 0 = by precision

@@ -41,10 +41,11 @@ __device__ __forceinline__ double bcast(double x, int lane) {
 
 // Element-diagonal blocks.  Mode kJvpFull (9 fields, nb = 72) or
 // kJvpCondensed (7 fields, nb = 56).  One lane per node, as q1_kernel.
+// Cw: linearisation coefficients at U (kJvpCondensed).
 template <typename S, int Mode>
 __global__ void __launch_bounds__(256)
-q1_block_kernel(const S* __restrict__ U, S* __restrict__ Bout, const uint8_t* __restrict__ phase,
-                DevParams P, int64_t nblocks_padded) {
+q1_block_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict__ Bout,
+                const uint8_t* __restrict__ phase, DevParams P, int64_t nblocks_padded) {
   using N = Dual<S>;
   constexpr int NF = (Mode == kJvpFull) ? 9 : 7;
   constexpr int NB = NF * 8;
@@ -78,10 +79,12 @@ q1_block_kernel(const S* __restrict__ U, S* __restrict__ Bout, const uint8_t* __
 #pragma unroll
       for (int f = 0; f < 9; ++f) vs[f] = (f == fj && n == nj) ? S(1) : S(0);
       if constexpr (Mode == kJvpCondensed) {
-        S w0, w1;
-        condense_solids(P, ph, us, vs, w0, w1);
-        vs[7] = w0;
-        vs[8] = w1;
+        // w = C e_col: column fj of this node's C on the seeded node only
+        const bool seeded = (n == nj);
+        const S c0 = seeded ? Cw[fj * FS + e * 8 + n] : S(0);
+        const S cs = seeded ? Cw[(7 + fj) * FS + e * 8 + n] : S(0);
+        vs[7] = c0;
+        vs[8] = cs - c0;
       }
 #pragma unroll
       for (int f = 0; f < 9; ++f) u[f] = N(us[f], vs[f]);

@@ -24,6 +24,14 @@ __global__ void __launch_bounds__(256) cast_kernel(const A* __restrict__ x, B* _
     y[i] = B(x[i]);
 }
 
+// y = B(scale * x), the product taken in double (scale: a power of two)
+template <typename A, typename B>
+__global__ void __launch_bounds__(256) scaled_cast_kernel(const A* __restrict__ x, double scale,
+                                                          B* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    y[i] = B(scale * double(x[i]));
+}
+
 // y = a * x (elementwise) or y = x / a
 template <typename S, bool kDiv>
 __global__ void __launch_bounds__(256) emul_kernel(const S* __restrict__ a, const S* __restrict__ x,
@@ -158,10 +166,10 @@ field_select_kernel(const S* __restrict__ sc, int f, S* __restrict__ t, int64_t 
 // rhs = -(R_u - y_u) on the 7 transported fields (R in FP64)
 template <typename S>
 __global__ void __launch_bounds__(256)
-condensed_rhs_kernel(const double* __restrict__ R, const S* __restrict__ y9, S* __restrict__ rhs, int64_t FS,
-                     int active) {
+condensed_rhs_kernel(const double* __restrict__ R, double scale, const S* __restrict__ y9, S* __restrict__ rhs,
+                     int64_t FS, int active) {
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256)
-    rhs[k] = ((active >> int(k / FS)) & 1) ? -(S(R[k]) - y9[k]) : S(0);
+    rhs[k] = ((active >> int(k / FS)) & 1) ? -(S(scale * R[k]) - y9[k]) : S(0);
 }
 
 // Zero the inactive fields of a 7-field vector.
@@ -188,12 +196,12 @@ uniform_state_kernel(double* __restrict__ U, const uint8_t* __restrict__ phase, 
   }
 }
 
-// v9 = (0 on the 7 transported fields, w_R on the solid fractions)
+// v9 = scale (0 on the 7 transported fields, w_R on the solid fractions)
 template <typename S>
 __global__ void __launch_bounds__(256)
-solid_direction_kernel(const double* __restrict__ wR, S* __restrict__ v9, int64_t FS) {
+solid_direction_kernel(const double* __restrict__ wR, double scale, S* __restrict__ v9, int64_t FS) {
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 9 * FS; k += int64_t(gridDim.x) * 256)
-    v9[k] = (k < 7 * FS) ? S(0) : S(wR[k - 7 * FS]);
+    v9[k] = (k < 7 * FS) ? S(0) : S(scale * wR[k - 7 * FS]);
 }
 
 // Unknown scales of the 7 transported fields: max(|u_f|, floor_f).
@@ -316,12 +324,14 @@ newton_update_kernel(const double* __restrict__ U, const double* __restrict__ dU
 // Merit contributions: sum of squares of x (n entries) into block partials.
 template <typename S>
 __global__ void __launch_bounds__(256)
-sumsq_kernel(const S* __restrict__ x, int64_t n, S* __restrict__ partial) {
-  __shared__ S sh[4];
-  S acc = S(0);
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256)
-    acc += x[k] * x[k];
-  const S s = block_sum(acc, sh);
+sumsq_kernel(const S* __restrict__ x, int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;                          // FP64: no overflow of FP32 squares
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) {
+    const double v = double(x[k]);
+    acc += v * v;
+  }
+  const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 

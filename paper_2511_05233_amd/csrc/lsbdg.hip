@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lsbdg.h"
@@ -38,6 +39,9 @@ struct dg_ctx {
   void* d_blocks = nullptr;
   size_t blocks_bytes = 0;
   int blocks_prec = -1;
+  // linearisation coefficients of the condensed tangent (14 x nodes)
+  DevBuf lin;
+  int lin_prec = -1;
   int* d_status = nullptr;
   SolverWork work;
 };
@@ -120,9 +124,29 @@ void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void*
   int64_t nb = (threads + 255) / 256;
   nb = (nb + 7) / 8 * 8;
   const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
-  hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
-                     static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
-                     ctx->d_phase, P, nb);
+  if constexpr (std::is_same<S, float>::value && Mode != kResidual)
+    hipLaunchKernelGGL((q1_kernel_w2<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
+                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
+                       ctx->d_phase, P, nb);
+  else
+    hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
+                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
+                       ctx->d_phase, P, nb);
+}
+
+// Linearisation coefficients of the condensed tangent at u (precision S).
+template <typename S>
+int linearize(dg_ctx* ctx, const DevParams& P, const S* u, hipStream_t st) {
+  const int64_t FS = ctx->Ne * ctx->np;
+  hipError_t e = ctx->lin.ensure(size_t(14) * FS * sizeof(S));
+  if (e != hipSuccess) return fail(DG_ENOMEM, std::string("linearisation storage: ") + hipGetErrorString(e));
+  int64_t nb = (FS + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(solid_tangent_kernel<S>, dim3(unsigned(nb)), dim3(256), 0, st, u, ctx->lin.as<S>(),
+                     ctx->d_phase, P);
+  DG_HIP(hipGetLastError());
+  ctx->lin_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  return DG_OK;
 }
 
 }  // namespace
@@ -130,7 +154,8 @@ void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void*
 
 namespace {
 
-// Build and invert the condensed element blocks of precision S at uS.
+// Build and invert the condensed element blocks of precision S at uS
+// (needs the linearisation at uS).
 template <typename S>
 int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
   const size_t need = size_t(ctx->Ne) * 56 * 56 * sizeof(S);
@@ -152,7 +177,7 @@ int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
   nb = (nb + 7) / 8 * 8;
   const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
   const dim3 grid_w{unsigned((ctx->Ne + 3) / 4), 1, 1};
-  hipLaunchKernelGGL((q1_block_kernel<S, kJvpCondensed>), grid, block, 0, st, uS,
+  hipLaunchKernelGGL((q1_block_kernel<S, kJvpCondensed>), grid, block, 0, st, uS, ctx->lin.as<S>(),
                      static_cast<S*>(ctx->d_blocks), ctx->d_phase, P, nb);
   hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), grid_w, block, 0, st, static_cast<S*>(ctx->d_blocks),
                      ctx->Ne, ctx->d_status);
@@ -191,6 +216,11 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   DevParams P = make_params(ctx, t_n + dt, dt);
   P.active = active;
   const double phi_floor = kGas * ctx->params.T / kFaraday;
+  // The linear system of the inner solve is J du = rhs multiplied by rs (a
+  // power of two): raw residual rows span ~1e-42 (trace species near the
+  // root) to ~1e-10, below the FP32 normal range at the small end, and the
+  // scaled ones sit well inside it.  The correction is divided by rs in FP64.
+  const double rs = std::is_same<S, float>::value ? 0x1p40 : 1.0;
   double* m_old = W.m_old.as<double>();
   double* R = W.R.as<double>();
   double* Rtry = W.Rtry.as<double>();
@@ -212,7 +242,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     launch_q1<double, double, kResidual>(ctx, P, uu, nullptr, m_old, out, st);
   };
   auto jvp_cond = [&](const S* v7, S* out) {
-    launch_q1<S, Dual<S>, kJvpCondensed>(ctx, P, uS, v7, nullptr, out, st);
+    launch_q1<S, Dual<S>, kJvpCondensed>(ctx, P, uS, v7, ctx->lin.p, out, st);
   };
   // coarse coefficients yc = E^-1 Z^T r (E = Z^T J Z, Z_f = sc on field f)
   auto coarse_coeffs = [&](const S* r) {
@@ -253,12 +283,13 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     return DG_OK;
   };
   auto sumsq = [&](const S* a, int64_t n, double& out) -> int {
-    hipLaunchKernelGGL(sumsq_kernel<S>, gred, blk, 0, st, a, n, partial);
-    hipLaunchKernelGGL(finish_sum_kernel<S>, g1, blk, 0, st, partial, kRedBlocks, dots);
-    S hs = 0;
-    DG_HIP(hipMemcpyAsync(&hs, dots, sizeof(S), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(sumsq_kernel<S>, gred, blk, 0, st, a, n, partial64);
+    hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, kRedBlocks,
+                       reinterpret_cast<double*>(hbuf));
+    double hs = 0;
+    DG_HIP(hipMemcpyAsync(&hs, hbuf, sizeof(double), hipMemcpyDeviceToHost, st));
     DG_HIP(hipStreamSynchronize(st));
-    out = double(hs);
+    out = hs;
     return DG_OK;
   };
   // merit(Rv)^2 = ||sc^-1 M^-1 R_u||^2 (+ ||E^-1 Z^T R_u||^2 when deflated)
@@ -267,7 +298,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // norm in which GMRES reduced the linearised residual (the deflated coarse
   // part of it vanishes exactly), so the Newton direction descends it.
   auto merit = [&](const double* Rv, double& out) -> int {
-    hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n7), blk, 0, st, Rv, t, n7);
+    hipLaunchKernelGGL((scaled_cast_kernel<double, S>), grid1(n7), blk, 0, st, Rv, rs, t, n7);
     if (active != kAllFields) hipLaunchKernelGGL(mask_fields_kernel<S>, grid1(n7), blk, 0, st, t, FS, active);
     double cpart = 0.0;
     precond(t, pJ);
@@ -286,7 +317,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     double bsum = 0.0;
     DG_HIP(hipMemcpyAsync(&bsum, hbuf, sizeof(double), hipMemcpyDeviceToHost, st));
     DG_HIP(hipStreamSynchronize(st));
-    out = a + cpart + bsum;
+    out = (a + cpart) / (rs * rs) + bsum;
     return DG_OK;
   };
 
@@ -305,6 +336,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   for (int it = 1; it <= o.newton_maxit; ++it) {
     r.newton_its = it;
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
+    if (int s = linearize<S>(ctx, P, uS, st)) return s;
     if (int s = blocks_setup<S>(ctx, P, uS, st)) return s;
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
     // coarse operator Ac[g][f] = sum_g sc_g (J Z_f)_g
@@ -345,9 +377,9 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     }
     // condensed right side
     hipLaunchKernelGGL(solid_rhs_kernel, grid1(FS), blk, 0, st, u, R, wR, ctx->d_phase, P, ctx->np);
-    hipLaunchKernelGGL(solid_direction_kernel<S>, grid1(n9), blk, 0, st, wR, v9, FS);
+    hipLaunchKernelGGL(solid_direction_kernel<S>, grid1(n9), blk, 0, st, wR, rs, v9, FS);
     launch_q1<S, Dual<S>, kJvpFull>(ctx, P, uS, v9, nullptr, y9, st);
-    hipLaunchKernelGGL(condensed_rhs_kernel<S>, grid1(n7), blk, 0, st, R, y9, rhs, FS, active);
+    hipLaunchKernelGGL(condensed_rhs_kernel<S>, grid1(n7), blk, 0, st, R, rs, y9, rhs, FS, active);
     hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), rhs, S(0), w, n7);
     precond(w, b);
     hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, b, b, n7);
@@ -451,7 +483,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       coarse_coeffs(pJ);
       hipLaunchKernelGGL(coarse_add_kernel<S>, grid1(n7), blk, 0, st, sc, yc, t, FS);
     }
-    hipLaunchKernelGGL((cast_kernel<S, double>), grid1(n7), blk, 0, st, t, du, n7);
+    hipLaunchKernelGGL((scaled_cast_kernel<S, double>), grid1(n7), blk, 0, st, t, 1.0 / rs, du, n7);
     hipLaunchKernelGGL(solid_delta_kernel, grid1(FS), blk, 0, st, u, du, wR, du + n7, ctx->d_phase, P,
                        ctx->np);
     if (o.verbose >= 2) {
@@ -484,7 +516,10 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       resid64(u_try, Rtry);
       if (int s = merit(Rtry, mt)) return s;
       upd = *std::max_element(pm.begin(), pm.end());
-      if (std::isfinite(mt) && (mt < merit0 || (lam == 1.0 && upd < 1e-8))) {
+      // near the root the merit (preconditioned in the inner precision)
+      // cannot rank steps any more: full steps are then taken as iterative
+      // refinement and the update-based stall test ends the iteration
+      if (std::isfinite(mt) && (mt < merit0 || (lam == 1.0 && (upd < 1e-8 || near_root)))) {
         found = true;
         break;
       }
@@ -657,6 +692,7 @@ int dg_destroy(dg_ctx* ctx) {
   if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   ctx->work.release_all();
+  ctx->lin.release();
   delete ctx;
   return DG_OK;
 }
@@ -723,13 +759,19 @@ int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const voi
       launch_q1<float, Dual<float>, kJvpFull>(ctx, P, u, v, nullptr, jv, st);
     else
       return fail(DG_EINVAL, "dg_jvp: bad precision");
-  } else if (mode == DG_JVP_CONDENSED7) {
+  } else if (mode == DG_JVP_CONDENSED7 || mode == DG_JVP_LINEARIZED7) {
+    if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_jvp: bad precision");
+    if (mode == DG_JVP_CONDENSED7) {
+      const int s = prec == DG_F64 ? linearize<double>(ctx, P, static_cast<const double*>(u), st)
+                                   : linearize<float>(ctx, P, static_cast<const float*>(u), st);
+      if (s) return s;
+    } else if (ctx->lin_prec != int(prec)) {
+      return fail(DG_ESTATE, "dg_jvp: no linearisation of this precision (dg_linearize)");
+    }
     if (prec == DG_F64)
-      launch_q1<double, Dual<double>, kJvpCondensed>(ctx, P, u, v, nullptr, jv, st);
-    else if (prec == DG_F32)
-      launch_q1<float, Dual<float>, kJvpCondensed>(ctx, P, u, v, nullptr, jv, st);
+      launch_q1<double, Dual<double>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
     else
-      return fail(DG_EINVAL, "dg_jvp: bad precision");
+      launch_q1<float, Dual<float>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
   } else {
     return fail(DG_EINVAL, "dg_jvp: bad mode");
   }
@@ -737,6 +779,17 @@ int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const voi
   return DG_OK;
 }
 
+
+int dg_linearize(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!u) return fail(DG_EINVAL, "dg_linearize: null array");
+  if (!(dt > 0)) return fail(DG_EINVAL, "dg_linearize: dt must be positive");
+  const DevParams P = make_params(ctx, t_new, dt);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (prec == DG_F64) return linearize<double>(ctx, P, static_cast<const double*>(u), st);
+  if (prec == DG_F32) return linearize<float>(ctx, P, static_cast<const float*>(u), st);
+  return fail(DG_EINVAL, "dg_linearize: bad precision");
+}
 
 constexpr int kNB = 56;   // condensed Q1 block size: 7 fields x 8 nodes
 
@@ -769,15 +822,18 @@ int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new,
   nb = (nb + 7) / 8 * 8;
   const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
   const dim3 grid_w{unsigned((ctx->Ne + 3) / 4), 1, 1};
+  if (int s = prec == DG_F64 ? linearize<double>(ctx, P, static_cast<const double*>(u), st)
+                             : linearize<float>(ctx, P, static_cast<const float*>(u), st))
+    return s;
   if (prec == DG_F64) {
     hipLaunchKernelGGL((q1_block_kernel<double, kJvpCondensed>), grid, block, 0, st,
-                       static_cast<const double*>(u), static_cast<double*>(ctx->d_blocks),
+                       static_cast<const double*>(u), ctx->lin.as<double>(), static_cast<double*>(ctx->d_blocks),
                        ctx->d_phase, P, nb);
     hipLaunchKernelGGL((invert_blocks_kernel<double, kNB>), grid_w, block, 0, st,
                        static_cast<double*>(ctx->d_blocks), ctx->Ne, ctx->d_status);
   } else {
     hipLaunchKernelGGL((q1_block_kernel<float, kJvpCondensed>), grid, block, 0, st,
-                       static_cast<const float*>(u), static_cast<float*>(ctx->d_blocks),
+                       static_cast<const float*>(u), ctx->lin.as<float>(), static_cast<float*>(ctx->d_blocks),
                        ctx->d_phase, P, nb);
     hipLaunchKernelGGL((invert_blocks_kernel<float, kNB>), grid_w, block, 0, st,
                        static_cast<float*>(ctx->d_blocks), ctx->Ne, ctx->d_status);
@@ -830,7 +886,7 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->gmres_maxit = 1500;
   o->newton_maxit = 60;
   o->gmres_rtol = 1e-4;
-  o->gmres_rtol_final = 1e-9;
+  o->gmres_rtol_final = 1e-11;
   o->newton_tol = 1e-11;
   o->coarse = 0;           // 0: per precision (additive for FP32, deflation for FP64)
   o->verbose = 0;

@@ -46,6 +46,20 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblocks_padded) {
 
 template <typename T>
 __device__ __forceinline__ T xlane(T v, int mask) { return __shfl_xor(v, mask); }
+
+// Trace at the near face of a Q1 line, lam1 u_near + lam0 u_far, with one
+// explicitly fused rounding: both elements of a face form every trace with
+// the same operation sequence, so their copies agree bit for bit.
+__device__ __forceinline__ double face_trace(double near, double far) {
+  return __builtin_fma(kLam1, near, kLam0 * far);
+}
+__device__ __forceinline__ float face_trace(float near, float far) {
+  return __builtin_fmaf(float(kLam1), near, float(kLam0) * far);
+}
+template <typename S>
+__device__ __forceinline__ Dual<S> face_trace(Dual<S> near, Dual<S> far) {
+  return {face_trace(near.v, far.v), face_trace(near.d, far.d)};
+}
 template <typename S>
 __device__ __forceinline__ Dual<S> xlane(Dual<S> v, int mask) {
   return {__shfl_xor(v.v, mask), __shfl_xor(v.d, mask)};
@@ -67,6 +81,8 @@ __device__ __forceinline__ void axis_flux(const DevParams& P, T f, const T* u, c
 }
 
 // Operator modes of the Q1 kernel.
+// kJvpCondensed reads the solid-fraction tangent coefficients C of every
+// node it touches from the linearisation array (see solid_tangent_kernel).
 enum Q1Mode { kResidual = 0, kJvpFull = 1, kJvpCondensed = 2 };
 
 // Node-local elimination of the solid fractions for a direction v on the
@@ -104,10 +120,73 @@ __device__ __forceinline__ void condense_solids(const DevParams& P, int ph, cons
   w1 = (a00 * t8 - a10 * t7) / det;
 }
 
-// Load the nine unknowns of one node as operator numbers.
-template <typename S, typename N, int Mode>
-__device__ __forceinline__ void load_node(const S* __restrict__ U, const S* __restrict__ V, int64_t FS,
-                                          int64_t idx, int ph, const DevParams& P, N* x) {
+// Solid-fraction tangent of one node for the transported-field direction v,
+// w = C v with the node's 2 x 7 coefficients C.  Stored as 14 field-major
+// arrays: Cw[j] = C[0][j] and Cw[7 + j] = C[0][j] + C[1][j] (j < 7), so that
+// the tangent of eps_S8 + eps_Li2S -- all a face neighbour's solid fractions
+// enter through, via the liquid fraction -- costs seven loads.
+template <typename S>
+__device__ __forceinline__ S solid_tangent_row(const S* __restrict__ Cw, int row, int64_t FS, int64_t idx,
+                                               const S* v7) {
+  S a = S(0);
+#pragma unroll
+  for (int j = 0; j < 7; ++j) a += Cw[(row * 7 + j) * FS + idx] * v7[j];
+  return a;
+}
+
+// Per-node coefficients C of the condensation (condense_solids applied to
+// the seven unit directions); nodes without reactions, or with frozen solid
+// fractions, get C = 0.  Once per linearisation point; every condensed
+// tangent at that point then costs at most two 7-term products per node.
+template <typename S>
+__global__ void __launch_bounds__(256)
+solid_tangent_kernel(const S* __restrict__ U, S* __restrict__ Cw, const uint8_t* __restrict__ phase,
+                     DevParams P) {
+  const int64_t FS = P.Ne * 8;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
+    const int ph = phase[k >> 3];
+    if (P.react[ph] == 0.0 || !(P.active & kSolidsBit)) {
+#pragma unroll
+      for (int j = 0; j < 14; ++j) Cw[j * FS + k] = S(0);
+      continue;
+    }
+    using D = Dual<S>;
+    D x[9], Sx[9];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) x[f] = D(U[f * FS + k], S(0));
+    x[7].d = S(1);
+    node_sources(P, ph, x, Sx);
+    const S c70 = Sx[7].d, c80 = Sx[8].d;
+    x[7].d = S(0);
+    x[8].d = S(1);
+    node_sources(P, ph, x, Sx);
+    const S c71 = Sx[7].d, c81 = Sx[8].d;
+    x[8].d = S(0);
+    const S idt = S(P.inv_dt);
+    const S a00 = S(P.rhoM[0]) * idt - c70, a01 = -c71;
+    const S a10 = -c80, a11 = S(P.rhoM[1]) * idt - c81;
+    const S det = a00 * a11 - a01 * a10;
+#pragma unroll 1
+    for (int j = 0; j < 7; ++j) {
+      x[j].d = S(1);
+      node_sources(P, ph, x, Sx);
+      x[j].d = S(0);
+      const S t7 = Sx[7].d, t8 = Sx[8].d;
+      const S w0 = (a11 * t7 - a01 * t8) / det;
+      const S w1 = (a00 * t8 - a10 * t7) / det;
+      Cw[j * FS + k] = w0;
+      Cw[(7 + j) * FS + k] = w0 + w1;
+    }
+  }
+}
+
+// Load the nine unknowns of one node as operator numbers (Cw: the
+// linearisation coefficients, read in kJvpCondensed only).  kFace: a face
+// neighbour, whose solid fractions enter through their sum only (the
+// tangent of eps_S8 carries that sum, eps_Li2S none).
+template <typename S, typename N, int Mode, bool kFace = false>
+__device__ __forceinline__ void load_node(const S* __restrict__ U, const S* __restrict__ V,
+                                          const S* __restrict__ Cw, int64_t FS, int64_t idx, N* x) {
   if constexpr (Mode == kResidual) {
 #pragma unroll
     for (int f = 0; f < 9; ++f) x[f] = U[f * FS + idx];
@@ -115,17 +194,19 @@ __device__ __forceinline__ void load_node(const S* __restrict__ U, const S* __re
 #pragma unroll
     for (int f = 0; f < 9; ++f) x[f] = N(U[f * FS + idx], V[f * FS + idx]);
   } else {
-    S us[9], vs[7];
-#pragma unroll
-    for (int f = 0; f < 9; ++f) us[f] = U[f * FS + idx];
+    S vs[7];
 #pragma unroll
     for (int f = 0; f < 7; ++f) vs[f] = V[f * FS + idx];
-    S w0, w1;
-    condense_solids(P, ph, us, vs, w0, w1);
+    const S ws = solid_tangent_row(Cw, 1, FS, idx, vs);
+    S w0 = ws, w1 = S(0);
+    if constexpr (!kFace) {
+      w0 = solid_tangent_row(Cw, 0, FS, idx, vs);
+      w1 = ws - w0;
+    }
 #pragma unroll
-    for (int f = 0; f < 7; ++f) x[f] = N(us[f], vs[f]);
-    x[7] = N(us[7], w0);
-    x[8] = N(us[8], w1);
+    for (int f = 0; f < 7; ++f) x[f] = N(U[f * FS + idx], vs[f]);
+    x[7] = N(U[7 * FS + idx], w0);
+    x[8] = N(U[8 * FS + idx], w1);
   }
 }
 
@@ -191,7 +272,12 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
     if (cn >= 0 && cn < ncell[d]) {
       const int64_t e2 = e + (hi ? stride[d] : -stride[d]);
       const int ph2 = phase[e2];
-      T tm[9], tp[9], gp[7];
+      // Canonical orientation: A = the lower element of the face (outward
+      // normal +e_d), B = the upper one.  Both elements evaluate the flux
+      // from A to B with the same operation sequence on the same operands
+      // and take +-1 times it, so a face's two contributions cancel exactly
+      // in any sum over elements (discrete conservation to the last bit).
+      T ta[9], tb[9], ga[7], gb[7];
       {
         T vn[9], vf[9];
         const int64_t in_ = e2 * 8 + (n ^ mask), if_ = e2 * 8 + n;   // nearest the face, far side
@@ -202,41 +288,50 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
             vf[f] = T(U[f * FS + if_]);
           }
         } else {
-          load_node<S, N, Mode>(U, V, FS, in_, ph2, P, vn);
-          load_node<S, N, Mode>(U, V, FS, if_, ph2, P, vf);
+          load_node<S, N, Mode, true>(U, V, M, FS, in_, vn);
+          load_node<S, N, Mode, true>(U, V, M, FS, if_, vf);
         }
 #pragma unroll
         for (int f = 0; f < 9; ++f) {
-          tm[f] = lam1 * u[f] + lam0 * up[f];
-          tp[f] = lam1 * vn[f] + lam0 * vf[f];
-          if (f < 7) gp[f] = sq3h * (hi ? vf[f] - vn[f] : vn[f] - vf[f]);
+          const T tm = face_trace(u[f], up[f]);
+          const T tp = face_trace(vn[f], vf[f]);
+          ta[f] = hi ? tm : tp;
+          tb[f] = hi ? tp : tm;
+          if (f < 7) {
+            const T gp = sq3h * (hi ? vf[f] - vn[f] : vn[f] - vf[f]);
+            ga[f] = hi ? g[f] : gp;
+            gb[f] = hi ? gp : g[f];
+          }
         }
       }
-      const T fm = transport_factor(tm, liquid_fraction(epsCBD, tm[7], tm[8], T(P.epsL_min)));
-      const T fp = transport_factor(tp, liquid_fraction(T(P.epsCBD[ph2]), tp[7], tp[8], T(P.epsL_min)));
-      const T Hf = harm(fm, fp);
+      const int phA = hi ? ph : ph2, phB = hi ? ph2 : ph;
+      const T fa = transport_factor(ta, liquid_fraction(T(P.epsCBD[phA]), ta[7], ta[8], T(P.epsL_min)));
+      const T fb = transport_factor(tb, liquid_fraction(T(P.epsCBD[phB]), tb[7], tb[8], T(P.epsL_min)));
+      const T Hf = harm(fa, fb);
       const T frt = T(P.frt);
-      const T dphi = tm[6] - tp[6];
-      T lamm = T(0), lamp = T(0), sdm = T(0), sdp = T(0), pen6 = T(0);
+      const T dphi = ta[6] - tb[6];
+      const T side = hi ? T(1) : T(-1);          // +flux for A, -flux for B
+      T lama = T(0), lamb = T(0), sda = T(0), sdb = T(0), pen6 = T(0);
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         const T D0 = T(P.D0[i]);
         const T z = T(kZ[i]);
-        const T Fm = fm * (g[i] + z * frt * tm[i] * g[6]);
-        const T Fp = fp * (gp[i] + z * frt * tp[i] * gp[6]);
-        q[i] = -T(0.5) * sgn * D0 * (Fm + Fp) +
-               sigh * D0 * (Hf * (tm[i] - tp[i]) + z * frt * harm(fm * tm[i], fp * tp[i]) * dphi);
-        lamm += T(P.wL[i]) * tm[i];
-        lamp += T(P.wL[i]) * tp[i];
-        sdm += T(P.zDA[i]) * g[i];
-        sdp += T(P.zDA[i]) * gp[i];
-        pen6 += T(P.zDA[i]) * (tm[i] - tp[i]);
+        const T Fa = fa * (ga[i] + z * frt * ta[i] * ga[6]);
+        const T Fb = fb * (gb[i] + z * frt * tb[i] * gb[6]);
+        const T flux = -T(0.5) * D0 * (Fa + Fb) +
+                       sigh * D0 * (Hf * (ta[i] - tb[i]) + z * frt * harm(fa * ta[i], fb * tb[i]) * dphi);
+        q[i] = side * flux;
+        lama += T(P.wL[i]) * ta[i];
+        lamb += T(P.wL[i]) * tb[i];
+        sda += T(P.zDA[i]) * ga[i];
+        sdb += T(P.zDA[i]) * gb[i];
+        pen6 += T(P.zDA[i]) * (ta[i] - tb[i]);
       }
       const T Fq = T(P.F);
-      const T Gm = fm * Fq * (sdm + frt * lamm * g[6]);
-      const T Gp = fp * Fq * (sdp + frt * lamp * gp[6]);
-      q[6] = -T(0.5) * sgn * (Gm + Gp) +
-             sigh * Fq * (Hf * pen6 + frt * harm(fm * lamm, fp * lamp) * dphi);
+      const T Ga = fa * Fq * (sda + frt * lama * ga[6]);
+      const T Gb = fb * Fq * (sdb + frt * lamb * gb[6]);
+      const T flux6 = -T(0.5) * (Ga + Gb) + sigh * Fq * (Hf * pen6 + frt * harm(fa * lama, fb * lamb) * dphi);
+      q[6] = side * flux6;
     } else if (d == 0 && hi) {
       // separator face x = L_x: inward Li+ flux j_el/F and ionic current j_el
       q[0] = -T(P.jel) / T(P.F);
@@ -255,12 +350,14 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
 }
 
 // Q1 operator: residual (Mode 0, N = S) or Jacobian-vector product (Modes 1
-// and 2, N = Dual<S>, output = derivative part).
+// and 2, N = Dual<S>, output = derivative part).  M: the old mass
+// (residual) or the linearisation coefficients of solid_tangent_kernel
+// (condensed tangent); unused otherwise.
 template <typename S, typename N, int Mode>
-__global__ void __launch_bounds__(256)
-q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
-          S* __restrict__ Out, const uint8_t* __restrict__ phase, DevParams P,
-          int64_t nblocks_padded) {
+__device__ __forceinline__ void q1_body(const S* __restrict__ U, const S* __restrict__ V,
+                                        const S* __restrict__ M, S* __restrict__ Out,
+                                        const uint8_t* __restrict__ phase, const DevParams& P,
+                                        int64_t nblocks_padded) {
   const int64_t blk = xcd_block(nblocks_padded);
   const int64_t gid = blk * 256 + threadIdx.x;
   const int64_t Ne = P.Ne;
@@ -273,7 +370,7 @@ q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict_
   const int iz = int(e / (int64_t(P.nx) * P.ny));
   const int ph = phase[e];
   N u[9], r[9];
-  load_node<S, N, Mode>(U, V, FS, e * 8 + n, ph, P, u);
+  load_node<S, N, Mode>(U, V, M, FS, e * 8 + n, u);
   q1_rows<S, N, Mode, false>(U, V, M, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
   if constexpr (Mode == kResidual) {
 #pragma unroll
@@ -286,6 +383,25 @@ q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict_
       Out[f * FS + e * 8 + n] = on ? deriv_of(r[f]) : S(0);
     }
   }
+}
+
+template <typename S, typename N, int Mode>
+__global__ void __launch_bounds__(256)
+q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
+          S* __restrict__ Out, const uint8_t* __restrict__ phase, DevParams P,
+          int64_t nblocks_padded) {
+  q1_body<S, N, Mode>(U, V, M, Out, phase, P, nblocks_padded);
+}
+
+// The same operator held to 256 registers per lane (two waves per SIMD):
+// the FP32 tangent otherwise takes a few accumulation registers beyond 256
+// and drops to one wave per SIMD.
+template <typename S, typename N, int Mode>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+q1_kernel_w2(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
+             S* __restrict__ Out, const uint8_t* __restrict__ phase, DevParams P,
+             int64_t nblocks_padded) {
+  q1_body<S, N, Mode>(U, V, M, Out, phase, P, nblocks_padded);
 }
 
 // Old mass: m[i] = eps_L c_i (i < 6), m[6 + s] = eps_s.

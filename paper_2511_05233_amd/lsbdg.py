@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblsbdg.so")
 
 DG_F64, DG_F32 = 0, 1
-DG_JVP_FULL9, DG_JVP_CONDENSED7 = 0, 1
+DG_JVP_FULL9, DG_JVP_CONDENSED7, DG_JVP_LINEARIZED7 = 0, 1, 2
 
 _STATUS = {0: "DG_OK", -1: "DG_EINVAL", -2: "DG_ENOMEM", -3: "DG_EHIP", -4: "DG_ENOCONV",
            -5: "DG_ENAN", -6: "DG_ESTATE", -7: "DG_EUNSUPPORTED"}
@@ -31,6 +31,7 @@ _SIGNATURES = {
                               C.c_double, C.c_void_p, C.c_void_p]),
     "dg_jvp": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                          C.c_double, C.c_void_p, C.c_void_p]),
+    "dg_linearize": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
     "dg_blockjacobi_setup": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double,
                                        C.c_void_p]),
     "dg_blockjacobi_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -256,9 +257,17 @@ class Context:
                                                     float(t_new), float(dt), _ptr(out), _stream()))
         return out
 
-    def jvp(self, u, v, t_new, dt, out=None, condensed=False):
-        """J(u) v: 9 fields, or 7 with the solid fractions condensed out."""
+    def linearize(self, u, t_new, dt):
+        """Store the condensation coefficients at u (precision of u)."""
+        self._check_arr(u, 9)
+        _check("dg_linearize", self._lib.dg_linearize(self._h, _prec(u), _ptr(u), float(t_new), float(dt),
+                                                      _stream()))
+
+    def jvp(self, u, v, t_new, dt, out=None, condensed=False, linearized=False):
+        """J(u) v: 9 fields, or 7 with the solid fractions condensed out
+        (linearized: with the coefficients of the last linearize call)."""
         import torch
+        condensed = condensed or linearized
         nf = 7 if condensed else 9
         self._check_arr(u, 9)
         self._check_arr(v, nf)
@@ -267,7 +276,7 @@ class Context:
         if out is None:
             out = torch.empty(self._shape(nf), dtype=u.dtype, device=u.device)
         self._check_arr(out, nf)
-        mode = DG_JVP_CONDENSED7 if condensed else DG_JVP_FULL9
+        mode = DG_JVP_LINEARIZED7 if linearized else (DG_JVP_CONDENSED7 if condensed else DG_JVP_FULL9)
         _check("dg_jvp", self._lib.dg_jvp(self._h, _prec(u), mode, _ptr(u), _ptr(v), float(t_new),
                                           float(dt), _ptr(out), _stream()))
         return out

@@ -58,3 +58,24 @@ def test_jvp_fp32(condensed):
 def test_jvp_paper_parameters_condensed():
     err = _case((6, 5, 4), 4, torch.float64, True, paper_params=True)
     assert np.all(err < TOL64), err
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_linearized_jvp_equals_condensed(dtype):
+    """The Krylov operator with a stored linearisation gives the condensed
+    product bit for bit; without a linearisation of its precision it is an
+    error."""
+    from paper_2511_05233_amd import lsbdg
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    P, ctx, mask = problem_and_context(7, 6, 5, mask_seed=5, param_seed=5)
+    u = torch.tensor(synth.random_state(P.n_elem, P.n_nodes, 5, phase=mask), device="cuda:0", dtype=dt)
+    v = torch.tensor(synth.random_vector(7, P.n_elem, P.n_nodes, 6), device="cuda:0", dtype=dt)
+    other = torch.float32 if dt == torch.float64 else torch.float64
+    ctx.linearize(u.to(other), 0.7, 0.02)
+    with pytest.raises(lsbdg.DgError) as ei:
+        ctx.jvp(u, v, 0.7, 0.02, linearized=True)
+    assert ei.value.code == -6
+    a = ctx.jvp(u, v, 0.7, 0.02, condensed=True)
+    ctx.linearize(u, 0.7, 0.02)
+    b = ctx.jvp(u, v, 0.7, 0.02, linearized=True)
+    assert torch.equal(a, b)
