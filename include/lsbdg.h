@@ -188,10 +188,20 @@ typedef struct {
                             (default 1e-11; FP32 inner solves stop at 1e-5) */
   double newton_tol;     /* converged when a full step changes no unknown by
                             more than this relative amount (default 1e-11) */
-  int32_t coarse;        /* global per-field coarse space: 0 = by precision
-                            (1 for DG_F32, 2 for DG_F64), 1 = additive
-                            correction, 2 = deflation (exact coarse solve),
-                            -1 = none */
+  int32_t coarse;        /* coarse space of the preconditioner: 0 = by
+                            precision (1 for DG_F32, 2 for DG_F64), 1 =
+                            global per-field constants,
+                            additive, 2 = global per-field constants with
+                            deflation (exact coarse solve), 3 = per-field
+                            constants on voxel aggregates, additive (a
+                            two-level method; LU of the coarse operator in
+                            FP64), -1 = none */
+  int32_t coarse_agg;    /* aggregate edge in voxels for coarse = 3 (0: the
+                            smallest edge >= 4 with at most 16384 coarse
+                            unknowns) */
+  int32_t block_bf16;    /* DG_F32 inner solves: 1 streams the element block
+                            inverses as bfloat16 in the preconditioner apply
+                            (half the bytes; the solution is unchanged) */
   int32_t verbose;       /* 1: one line per Newton iteration on stderr */
 } dg_solver_opts;
 

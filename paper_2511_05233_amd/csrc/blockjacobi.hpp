@@ -18,8 +18,12 @@
 //     A^{-1}[k][p_m] = B[p_k][m],
 // which the write-out applies.
 //
-// Apply: y_e = B_e^{-1} x_e, one wavefront per element, lane r = row r,
-// columns streamed with one coalesced load each.
+// Storage of the inverse: column quads per row, element block e at
+// e * NB * NB, entry (row, col) at ((col / 4) * NB + row) * 4 + col % 4, so
+// that lane r of the apply reads four columns of its row with one 16-byte
+// (FP32) load and a wavefront's load covers a contiguous 56 x 16 bytes.
+//
+// Apply: y_e = B_e^{-1} x_e, one wavefront per element, lane r = row r.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -97,6 +101,12 @@ q1_block_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict
   }
 }
 
+// Entry (row, col) of a block in the column-quad storage.
+template <int NB>
+__host__ __device__ __forceinline__ int quad_index(int row, int col) {
+  return ((col >> 2) * NB + row) * 4 + (col & 3);
+}
+
 // Wave-wide argmax of a non-negative key (-1 = excluded); returns the lane.
 __device__ __forceinline__ int wave_argmax(float key, int lane) {
   float k = key;
@@ -155,7 +165,20 @@ invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status) {
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
     const int pm = __builtin_amdgcn_readlane(mypiv, m);
-    if (act) Be[pm * NB + kk] = r[m];
+    if (act) Be[quad_index<NB>(kk, pm)] = r[m];
+  }
+}
+
+// Column-major copy of the stored inverses: out[e][col][row].
+template <typename S, int NB>
+__global__ void __launch_bounds__(256)
+export_blocks_kernel(const S* __restrict__ B, S* __restrict__ out, int64_t Ne) {
+  const int64_t total = Ne * NB * NB;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < total; k += int64_t(gridDim.x) * 256) {
+    const int64_t e = k / (NB * NB);
+    const int w = int(k - e * NB * NB);
+    const int col = w / NB, row = w - col * NB;
+    out[k] = B[e * NB * NB + quad_index<NB>(row, col)];
   }
 }
 
@@ -173,11 +196,67 @@ apply_blocks_kernel(const S* __restrict__ B, const S* __restrict__ X, S* __restr
   const int fl = lane >> 3, nl = lane & 7;
   const S xl = act ? X[fl * FS + e * 8 + nl] : S(0);
   const S* Be = B + e * int64_t(NB) * NB;
+  struct alignas(4 * sizeof(S)) Quad { S a, b, c, d; };
   S acc = S(0);
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    const S bc = act ? Be[c * NB + lane] : S(0);
-    acc += bc * bcast(xl, c);
+  for (int c4 = 0; c4 < NB / 4; ++c4) {
+    Quad q{S(0), S(0), S(0), S(0)};
+    if (act) q = *reinterpret_cast<const Quad*>(Be + (c4 * NB + lane) * 4);
+    acc += q.a * bcast(xl, 4 * c4);
+    acc += q.b * bcast(xl, 4 * c4 + 1);
+    acc += q.c * bcast(xl, 4 * c4 + 2);
+    acc += q.d * bcast(xl, 4 * c4 + 3);
+  }
+  if (act) Y[fl * FS + e * 8 + nl] = acc;
+}
+
+// bfloat16 copy of FP32 inverses for the apply (half the bytes; only the
+// preconditioner changes, not the solution): entry (row, col) at
+// ((col / 8) * NB + row) * 8 + col % 8, rounded to nearest even.
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256)
+blocks_to_bf16_kernel(const float* __restrict__ B, uint16_t* __restrict__ H, int64_t Ne) {
+  const int64_t total = Ne * NB * NB;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < total; k += int64_t(gridDim.x) * 256) {
+    const int64_t e = k / (NB * NB);
+    const int w = int(k - e * NB * NB);
+    const int i = w & 7, row = (w >> 3) % NB, c8 = (w >> 3) / NB;
+    H[k] = to_bf16(B[e * NB * NB + quad_index<NB>(row, 8 * c8 + i)]);
+  }
+}
+
+template <int NF>
+__global__ void __launch_bounds__(256)
+apply_blocks_bf16_kernel(const uint16_t* __restrict__ H, const float* __restrict__ X, float* __restrict__ Y,
+                         int64_t Ne) {
+  constexpr int NB = NF * 8;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t e = int64_t(blockIdx.x) * 4 + w;
+  if (e >= Ne) return;
+  const int64_t FS = Ne * 8;
+  const bool act = lane < NB;
+  const int fl = lane >> 3, nl = lane & 7;
+  const float xl = act ? X[fl * FS + e * 8 + nl] : 0.0f;
+  const uint16_t* He = H + e * int64_t(NB) * NB;
+  float acc = 0.0f;
+#pragma unroll
+  for (int c8 = 0; c8 < NB / 8; ++c8) {
+    uint4 q = make_uint4(0u, 0u, 0u, 0u);
+    if (act) q = *reinterpret_cast<const uint4*>(He + (c8 * NB + lane) * 8);
+    const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc += __uint_as_float(wd[t] << 16) * bcast(xl, 8 * c8 + 2 * t);
+      acc += __uint_as_float(wd[t] & 0xffff0000u) * bcast(xl, 8 * c8 + 2 * t + 1);
+    }
   }
   if (act) Y[fl * FS + e * 8 + nl] = acc;
 }

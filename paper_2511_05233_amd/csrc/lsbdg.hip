@@ -21,6 +21,10 @@
 #include "blockjacobi.hpp"
 #include "solver.hpp"
 #include "outputs.hpp"
+#include "coarse.hpp"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 using namespace lsbdg;
 
@@ -41,6 +45,12 @@ struct dg_ctx {
   int blocks_prec = -1;
   // linearisation coefficients of the condensed tangent (14 x nodes)
   DevBuf lin;
+  // aggregation coarse space: LU of the equilibrated coarse operator,
+  // equilibration, pivots, a coarse vector, LAPACK status
+  DevBuf cE, cd, crc, cipiv, cinfo;
+  // bfloat16 copy of FP32 block inverses (block_bf16)
+  DevBuf bh;
+  rocblas_handle blas = nullptr;
   int lin_prec = -1;
   int* d_status = nullptr;
   SolverWork work;
@@ -238,6 +248,41 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   const dim3 gw{unsigned((ctx->Ne + 3) / 4), 1, 1};
   const dim3 g1{1, 1, 1}, g7{7, 1, 1};
 
+  // aggregation coarse space (coarse = 3)
+  AggGrid G{};
+  int64_t nc = 0;
+  if (o.coarse == 3) {
+    const int nx = ctx->mesh.nx, ny = ctx->mesh.ny, nz = ctx->mesh.nz;
+    int A = o.coarse_agg;
+    auto naggs = [&](int a) {
+      return int64_t((nx + a - 1) / a) * ((ny + a - 1) / a) * ((nz + a - 1) / a);
+    };
+    if (A <= 0) {
+      A = 4;
+      while (7 * naggs(A) > 16384) ++A;
+    }
+    G.nx = nx; G.ny = ny; G.nz = nz; G.A = A;
+    G.nax = (nx + A - 1) / A; G.nay = (ny + A - 1) / A; G.naz = (nz + A - 1) / A;
+    G.na = naggs(A);
+    nc = 7 * G.na;
+    if (nc > (int64_t(1) << 20)) return fail(DG_EINVAL, "dg_step: coarse space too large (raise coarse_agg)");
+    for (auto pr : {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cd, size_t(nc) * 8),
+                    std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->cipiv, size_t(nc) * 4),
+                    std::make_pair(&ctx->cinfo, size_t(4))}) {
+      hipError_t e = pr.first->ensure(pr.second);
+      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("coarse space: ") + hipGetErrorString(e));
+    }
+    if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success)
+      return fail(DG_EHIP, "rocblas_create_handle failed");
+    if (rocblas_set_stream(ctx->blas, st) != rocblas_status_success) return fail(DG_EHIP, "rocblas_set_stream failed");
+  }
+  double* cE = ctx->cE.as<double>();
+  double* cd = ctx->cd.as<double>();
+  double* crc = ctx->crc.as<double>();
+  rocblas_int* cipiv = ctx->cipiv.as<rocblas_int>();
+  rocblas_int* cinfo = ctx->cinfo.as<rocblas_int>();
+  const dim3 gagg{unsigned(G.na > 0 ? G.na : 1), 1, 1};
+
   auto resid64 = [&](const double* uu, double* out) {
     launch_q1<double, double, kResidual>(ctx, P, uu, nullptr, m_old, out, st);
   };
@@ -259,11 +304,28 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // space; the deflated variant has already removed that part from r)
   auto precond = [&](S* r, S* out) {
     deflate(r);
-    hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), r,
-                       out, ctx->Ne);
+    if constexpr (std::is_same<S, float>::value) {
+      if (o.block_bf16)
+        hipLaunchKernelGGL((apply_blocks_bf16_kernel<7>), gw, blk, 0, st, ctx->bh.as<const uint16_t>(), r, out,
+                           ctx->Ne);
+      else
+        hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), r,
+                           out, ctx->Ne);
+    } else {
+      hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), r,
+                         out, ctx->Ne);
+    }
     if (o.coarse == 1) {
       coarse_coeffs(r);
       hipLaunchKernelGGL(coarse_add_kernel<S>, grid1(n7), blk, 0, st, sc, yc, out, FS);
+    } else if (o.coarse == 3) {
+      // out += Z E^-1 Z^T r with E = D^-1 LU D^-1 (equilibrated)
+      hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, sc, r, G, FS, crc);
+      hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
+      rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), 1, cE, rocblas_int(nc), cipiv, crc,
+                       rocblas_int(nc));
+      hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
+      hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(n7), blk, 0, st, sc, crc, G, FS, out);
     }
   };
   auto opA = [&](const S* v, S* out) {           // out = sc^-1 M^-1 J (sc v)
@@ -338,9 +400,37 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
     if (int s = linearize<S>(ctx, P, uS, st)) return s;
     if (int s = blocks_setup<S>(ctx, P, uS, st)) return s;
+    if (std::is_same<S, float>::value && o.block_bf16) {
+      hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * 56 * 56 * 2);
+      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("bf16 blocks: ") + hipGetErrorString(e));
+      hipLaunchKernelGGL((blocks_to_bf16_kernel<56>), dim3(8192), blk, 0, st,
+                         static_cast<const float*>(ctx->d_blocks), ctx->bh.as<uint16_t>(), ctx->Ne);
+    }
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
+    if (o.coarse == 3) {
+      // aggregation coarse operator E = Z^T J Z by coloured probes, then LU
+      DG_HIP(hipMemsetAsync(cE, 0, size_t(nc) * nc * 8, st));
+      for (int f = 0; f < 7; ++f) {
+        if (!((active >> f) & 1)) continue;
+        for (int c = 0; c < 7; ++c) {
+          hipLaunchKernelGGL(agg_probe_kernel<S>, grid1(n7), blk, 0, st, sc, f, c, G, FS, t);
+          jvp_cond(t, pJ);
+          hipLaunchKernelGGL(agg_probe_reduce_kernel<S>, gagg, blk, 0, st, sc, pJ, f, c, G, FS, cE, nc);
+        }
+      }
+      hipLaunchKernelGGL(coarse_diag_kernel, grid1(nc), blk, 0, st, cE, nc, nc, cd);
+      hipLaunchKernelGGL(coarse_scale_kernel, dim3(8192), blk, 0, st, cE, nc, nc, cd);
+      DG_HIP(hipGetLastError());
+      if (rocsolver_dgetrf(ctx->blas, rocblas_int(nc), rocblas_int(nc), cE, rocblas_int(nc), cipiv, cinfo) !=
+          rocblas_status_success)
+        return fail(DG_EHIP, "dg_step: rocsolver_dgetrf failed");
+      rocblas_int hinfo = 0;
+      DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+      DG_HIP(hipStreamSynchronize(st));
+      if (hinfo != 0) return fail(DG_ENAN, "dg_step: singular aggregation coarse operator");
+    }
     // coarse operator Ac[g][f] = sum_g sc_g (J Z_f)_g
-    if (o.coarse) {
+    if (o.coarse == 1 || o.coarse == 2) {
       std::vector<double> Ac(49), col(7);
       for (int f = 0; f < 7; ++f) {
         S* JZf = JZ + int64_t(f) * n7;
@@ -424,13 +514,21 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
         for (; j < m && its < maxit; ++j) {
           S* Vj1 = V + int64_t(j + 1) * n7;
           opA(V + int64_t(j) * n7, w);
+          // classical Gram-Schmidt, repeated only when the projection removed
+          // more than half of ||w||^2 (Daniel-Gragg-Kaufman-Stewart test;
+          // ||w_before||^2 = sum h^2 + ||w_after||^2)
           if (int s = mdot(V, j + 1, w, h)) return s;
           hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
-          if (int s = mdot(V, j + 1, w, h2)) return s;
-          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
-          for (int i = 0; i <= j; ++i) h[i] += h2[i];
           double hn = 0.0;
           if (int s = sumsq(w, n7, hn)) return s;
+          double hh = 0.0;
+          for (int i = 0; i <= j; ++i) hh += h[i] * h[i];
+          if (hn < hh) {
+            if (int s = mdot(V, j + 1, w, h2)) return s;
+            hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
+            for (int i = 0; i <= j; ++i) h[i] += h2[i];
+            if (int s = sumsq(w, n7, hn)) return s;
+          }
           hn = std::sqrt(hn);
           ++its;
           for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
@@ -591,6 +689,7 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
     return fail(DG_EINVAL, std::string(fn) + ": bad inner precision");
   if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
   if (o.coarse < 0) o.coarse = 0;
+  if (o.coarse > 3) return fail(DG_EINVAL, std::string(fn) + ": coarse must be -1..3");
   return DG_OK;
 }
 
@@ -693,6 +792,8 @@ int dg_destroy(dg_ctx* ctx) {
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   ctx->work.release_all();
   ctx->lin.release();
+  for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->cipiv, &ctx->cinfo, &ctx->bh}) b->release();
+  if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   delete ctx;
   return DG_OK;
 }
@@ -871,9 +972,14 @@ int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
   if (!out) return fail(DG_EINVAL, "dg_blockjacobi_export: null array");
   if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_export: no setup yet");
-  const size_t esz = ctx->blocks_prec == DG_F64 ? sizeof(double) : sizeof(float);
-  DG_HIP(hipMemcpyAsync(out, ctx->d_blocks, size_t(ctx->Ne) * kNB * kNB * esz,
-                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->blocks_prec == DG_F64)
+    hipLaunchKernelGGL((export_blocks_kernel<double, kNB>), dim3(4096), dim3(256), 0, st,
+                       static_cast<const double*>(ctx->d_blocks), static_cast<double*>(out), ctx->Ne);
+  else
+    hipLaunchKernelGGL((export_blocks_kernel<float, kNB>), dim3(4096), dim3(256), 0, st,
+                       static_cast<const float*>(ctx->d_blocks), static_cast<float*>(out), ctx->Ne);
+  DG_HIP(hipGetLastError());
   return DG_OK;
 }
 

@@ -140,3 +140,49 @@ def test_step_invariants_on_cube16():
         ratio = np.max(np.abs(R[f])) / scale
         print(f"[step] field {f} residual / scale {ratio:.3e}", flush=True)
         assert ratio <= 1e-6, f
+
+
+@pytest.mark.parametrize("inner,tol", [("f64", 1e-10), ("f32", 1e-8)])
+def test_step_with_aggregation_coarse_space(small_case, inner, tol):
+    """The two-level preconditioner (per-field constants on 2x2x2-voxel
+    aggregates, coarse operator by coloured probes, LU) reaches the same
+    root."""
+    P, ctx, u0, u1 = small_case
+    ut = torch.tensor(u0, device="cuda:0")
+    rep = ctx.step(ut, 0.0, 0.1, inner=inner, coarse=3, coarse_agg=2, verbose=1)
+    print(f"[step] coarse=3 {inner} report {rep}", flush=True)
+    err = rel_l2(ut.cpu().numpy(), u1)
+    print("  relative L2 per field", err, flush=True)
+    assert np.all(err < tol), err
+
+
+def test_aggregation_coarse_space_cuts_gmres_on_cube16():
+    """16^3 cube, first implicit step from the GPU initial state: the
+    aggregation coarse space needs fewer GMRES iterations than the global
+    per-field constants, for the same root."""
+    w = synth.WORKLOADS["cube16_q1"]
+    P, ctx, mask = problem_and_context(w.nx, w.ny, w.nz, porosity=w.porosity, mask_seed=w.mask_seed,
+                                       param_seed=w.param_seed, f_C=w.f_C)
+    u0, _ = ctx.initial_state(inner="f32")
+    reps, roots = {}, {}
+    for coarse in (1, 3):
+        ut = u0.clone()
+        reps[coarse] = ctx.step(ut, 0.0, 0.1, inner="f32", coarse=coarse)
+        roots[coarse] = ut.cpu().numpy()
+        print(f"[step] cube16 coarse={coarse}: {reps[coarse]}", flush=True)
+    err = rel_l2(roots[3], roots[1])
+    print("  relative L2 between the roots", err, flush=True)
+    assert np.all(err[:7] < 1e-8), err
+    assert reps[3]["gmres_its"] < reps[1]["gmres_its"]
+
+
+def test_step_with_bf16_block_inverses(small_case):
+    """Streaming the FP32 block inverses as bfloat16 changes only the
+    preconditioner: the mixed-precision step reaches the same root."""
+    P, ctx, u0, u1 = small_case
+    ut = torch.tensor(u0, device="cuda:0")
+    rep = ctx.step(ut, 0.0, 0.1, inner="f32", block_bf16=1, verbose=1)
+    print(f"[step] bf16 blocks report {rep}", flush=True)
+    err = rel_l2(ut.cpu().numpy(), u1)
+    print("  relative L2 per field", err, flush=True)
+    assert np.all(err < 1e-8), err
