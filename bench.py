@@ -73,6 +73,34 @@ def cpu_baseline(w, budget_s=12.0):
                       f"of the same workload, {n} applications in {wall:.1f} s"}
 
 
+def source_hash():
+    """Hash of the HIP sources (the recorded counters hold for this version only)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2511_05233_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
+    or None when absent or taken on other kernel sources."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    want = source_hash()
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"\s*traffic\s+(\S+)\s+bytes_per_launch=(\d+)\s+source=(\w+)", line)
+            if m and m.group(1) == kernel and m.group(3) == want:
+                return int(m.group(2))
+    return None
+
+
 def copy_probe(dev):
     """Three plain device copies of 1 GiB (reference for the HBM byte counters)."""
     import torch
@@ -169,6 +197,39 @@ def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0):
     return rep
 
 
+def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
+    """Row C3: 5 backward-Euler steps on the 16^3 cube with FP64 and with
+    mixed (FP32 inner) solves from the same GPU initial state."""
+    import torch
+    import synth
+    from paper_2511_05233_amd import lsbdg
+    w = synth.WORKLOADS["cube16_q1"]
+    D0, i0 = synth.sample_transport_kinetics(w.param_seed)
+    ctx = lsbdg.Context(w.nx, w.ny, w.nz, w.h, w.order, w.mask(), D0=D0, kE=i0 / FARADAY, f_C=w.f_C)
+    u0, _ = ctx.initial_state(inner="f64", coarse=coarse)
+    res = {}
+    for inner in ("f64", "f32"):
+        u = u0.clone()
+        its = [0, 0]
+        ctx.step(u.clone(), 0.0, dt, inner=inner, coarse=coarse)      # warm-up (allocations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            rep = ctx.step(u, k * dt, dt, inner=inner, coarse=coarse)
+            its[0] += rep["newton_its"]
+            its[1] += rep["gmres_its"]
+        torch.cuda.synchronize()
+        res[inner] = (time.perf_counter() - t0, u, its)
+    rel = [float(torch.linalg.norm(res["f32"][1][f] - res["f64"][1][f]) /
+                 torch.clamp(torch.linalg.norm(res["f64"][1][f]), min=1e-300)) for f in range(9)]
+    log(f"[bench] C3: f64 {res['f64'][0]:.3f} s, mixed {res['f32'][0]:.3f} s")
+    return {"workload": "cube16_q1: 16^3 voxels, 0.1C, 5 backward-Euler steps of 0.1 s from the initial state",
+            "s_f64": round(res["f64"][0], 4), "s_mixed": round(res["f32"][0], 4),
+            "mixed_speedup": round(res["f64"][0] / res["f32"][0], 3),
+            "newton_gmres_f64": res["f64"][2], "newton_gmres_mixed": res["f32"][2],
+            "rel_l2_mixed_vs_f64": [float(f"{x:.2e}") for x in rel]}
+
+
 def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0):
     """n accepted steps of the naive controller (halving on failed solves)."""
     tot = {"newton_its": 0, "gmres_its": 0, "trials": 0, "halvings": 0}
@@ -196,6 +257,7 @@ def main(argv=None):
     ap.add_argument("--compare-f64", action="store_true",
                     help="repeat the timed steps with an FP64 inner solve from the same state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the mixed-vs-FP64 comparison on the 16^3 cube")
     ap.add_argument("--verbose", type=int, default=0, help="Newton progress lines on stderr")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: skip the solves and time the kernels alone on a seeded "
@@ -288,7 +350,8 @@ def main(argv=None):
                             "solves, halving dt on failure)"),
                    "coarse": args.coarse, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(w.name, "apply_blocks_kernel"),
                      "kernel": "apply_blocks_kernel", "ms": round(ms_apply, 4),
                      "bytes_per_launch": b_apply},
         "kernels": kernels,
@@ -312,6 +375,8 @@ def main(argv=None):
                             "newton_its": tot64["newton_its"], "gmres_its": tot64["gmres_its"],
                             "mixed_speedup": round(wall64 / wall, 3),
                             "rel_l2_mixed_vs_f64": [float(f"{x:.3e}") for x in rel]}
+    if not args.no_c3:
+        out["mixed_vs_f64"] = mixed_vs_f64(args.coarse, log)
     if args.copy_probe:
         out["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu_baseline:

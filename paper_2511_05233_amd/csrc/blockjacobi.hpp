@@ -68,36 +68,59 @@ q1_block_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict
 #pragma unroll
   for (int f = 0; f < 9; ++f) us[f] = U[f * FS + e * 8 + n];
   S* Be = Bout + e * int64_t(NB) * NB;
+  const S W3 = S(P.W3);
 
+  // Columns in the order (field fj, node nj).  The sources are node-local:
+  // a column seeded at node nj reaches this lane's source rows only when
+  // nj == n, through the tangent ks of the lane's own unknown fj (with the
+  // condensed solid-fraction tangent), formed once per field; the column
+  // loop evaluates the spatial terms only.
 #pragma unroll 1
-  for (int col = 0; col < NB; ++col) {
-    const int fj = col >> 3, nj = col & 7;
-    if (!((P.active >> (fj < 7 ? fj : 7)) & 1)) {   // inactive unknown: identity column
+  for (int fj = 0; fj < NF; ++fj) {
+    if (!((P.active >> (fj < 7 ? fj : 7)) & 1)) {   // inactive unknown: identity columns
+#pragma unroll 1
+      for (int nj = 0; nj < 8; ++nj) {
+        const int col = fj * 8 + nj;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) Be[col * NB + f * 8 + n] = (f == fj && n == nj) ? S(1) : S(0);
+        for (int f = 0; f < NF; ++f) Be[col * NB + f * 8 + n] = (f == fj && n == nj) ? S(1) : S(0);
+      }
       continue;
     }
-    N u[9];
-    {
-      S vs[9];
+    S vo[9];                                     // direction at the seeded node
 #pragma unroll
-      for (int f = 0; f < 9; ++f) vs[f] = (f == fj && n == nj) ? S(1) : S(0);
-      if constexpr (Mode == kJvpCondensed) {
-        // w = C e_col: column fj of this node's C on the seeded node only
-        const bool seeded = (n == nj);
-        const S c0 = seeded ? Cw[fj * FS + e * 8 + n] : S(0);
-        const S cs = seeded ? Cw[(7 + fj) * FS + e * 8 + n] : S(0);
-        vs[7] = c0;
-        vs[8] = cs - c0;
-      }
-#pragma unroll
-      for (int f = 0; f < 9; ++f) u[f] = N(us[f], vs[f]);
+    for (int f = 0; f < 9; ++f) vo[f] = (f == fj) ? S(1) : S(0);
+    if constexpr (Mode == kJvpCondensed) {
+      const S c0 = Cw[fj * FS + e * 8 + n];
+      const S cs = Cw[(7 + fj) * FS + e * 8 + n];
+      vo[7] = c0;
+      vo[8] = cs - c0;
     }
-    N r[9];
-    q1_rows<S, N, kJvpFull, true>(U, nullptr, nullptr, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
+    S ks[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-      Be[col * NB + f * 8 + n] = ((P.active >> (f < 7 ? f : 7)) & 1) ? r[f].d : S(0);
+    for (int f = 0; f < NF; ++f) ks[f] = S(0);
+    if (P.react[ph] != 0.0) {
+      N x[9], Sx[9];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) x[f] = N(us[f], vo[f]);
+      node_sources(P, ph, x, Sx);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) ks[f] = Sx[f].d;
+    }
+#pragma unroll 1
+    for (int nj = 0; nj < 8; ++nj) {
+      const int col = fj * 8 + nj;
+      const bool seeded = (n == nj);
+      N u[9];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) u[f] = N(us[f], seeded ? vo[f] : S(0));
+      N r[9];
+      q1_rows<S, N, kJvpFull, true, false>(U, nullptr, nullptr, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const S val = r[f].d - (seeded ? W3 * ks[f] : S(0));
+        Be[col * NB + f * 8 + n] = ((P.active >> (f < 7 ? f : 7)) & 1) ? val : S(0);
+      }
+    }
   }
 }
 

@@ -514,21 +514,16 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
         for (; j < m && its < maxit; ++j) {
           S* Vj1 = V + int64_t(j + 1) * n7;
           opA(V + int64_t(j) * n7, w);
-          // classical Gram-Schmidt, repeated only when the projection removed
-          // more than half of ||w||^2 (Daniel-Gragg-Kaufman-Stewart test;
-          // ||w_before||^2 = sum h^2 + ||w_after||^2)
+          // classical Gram-Schmidt applied twice: with FP32 basis vectors a
+          // single pass (even with a reorthogonalisation test) loses enough
+          // orthogonality to slow the two-level preconditioned iteration
           if (int s = mdot(V, j + 1, w, h)) return s;
           hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
+          if (int s = mdot(V, j + 1, w, h2)) return s;
+          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
+          for (int i = 0; i <= j; ++i) h[i] += h2[i];
           double hn = 0.0;
           if (int s = sumsq(w, n7, hn)) return s;
-          double hh = 0.0;
-          for (int i = 0; i <= j; ++i) hh += h[i] * h[i];
-          if (hn < hh) {
-            if (int s = mdot(V, j + 1, w, h2)) return s;
-            hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
-            for (int i = 0; i <= j; ++i) h[i] += h2[i];
-            if (int s = sumsq(w, n7, hn)) return s;
-          }
           hn = std::sqrt(hn);
           ++its;
           for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];

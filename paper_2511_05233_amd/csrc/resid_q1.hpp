@@ -214,7 +214,7 @@ __device__ __forceinline__ void load_node(const S* __restrict__ U, const S* __re
 // tangents (N = Dual<S>).  u holds the lane's own nine unknowns as N.
 // Neighbour nodes are read from U (and from V in the JVP modes); with
 // kNbrZero their direction is zero (element-diagonal Jacobian blocks).
-template <typename S, typename N, int Mode, bool kNbrZero>
+template <typename S, typename N, int Mode, bool kNbrZero, bool kSources = true>
 __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __restrict__ V,
                                         const S* __restrict__ M, const uint8_t* __restrict__ phase,
                                         const DevParams& P, int64_t e, int n, int ph, int ix, int iy,
@@ -341,11 +341,13 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
     for (int f = 0; f < 7; ++f) r[f] += W2 * (lam1 * q[f] + lam0 * xlane(q[f], mask));
   }
 
-  if (P.react[ph] != 0.0) {
-    T Sx[9];
-    node_sources(P, ph, u, Sx);
+  if constexpr (kSources) {
+    if (P.react[ph] != 0.0) {
+      T Sx[9];
+      node_sources(P, ph, u, Sx);
 #pragma unroll
-    for (int f = 0; f < 9; ++f) r[f] -= W3 * Sx[f];
+      for (int f = 0; f < 9; ++f) r[f] -= W3 * Sx[f];
+    }
   }
 }
 
