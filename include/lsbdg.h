@@ -195,8 +195,10 @@ typedef struct {
                             deflation (exact coarse solve), 3 = per-field
                             constants on voxel aggregates, additive (a
                             two-level method; LU of the coarse operator in
-                            FP64), -1 = none */
-  int32_t coarse_agg;    /* aggregate edge in voxels for coarse = 3 (0: the
+                            FP64), 4 = the same space applied
+                            multiplicatively (coarse solve, then the element
+                            blocks on the remaining residual), -1 = none */
+  int32_t coarse_agg;    /* aggregate edge in voxels for coarse = 3, 4 (0: the
                             smallest edge >= 4 with at most 16384 coarse
                             unknowns) */
   int32_t block_bf16;    /* DG_F32 inner solves: 1 streams the element block
@@ -226,7 +228,8 @@ typedef struct {
  * solve is GMRES(m) on the condensed 7-field Jacobian, scaled by the unknown
  * magnitudes and preconditioned by the element blocks plus a global
  * per-field coarse correction, in the inner precision of opts (NULL:
- * defaults).  Device workspace is allocated on first use and kept.
+ * defaults).  Operator and preconditioner are rebuilt at every Newton
+ * iterate.  Device workspace is allocated on first use and kept.
  * Converged when a full step changes no unknown by more than newton_tol,
  * or, once an update below 1e-7 has been reached (the attainable accuracy
  * of the iterative solve; report.stalled = 1), when three full steps in a

@@ -219,7 +219,9 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
                   std::make_pair(&W.partial, size_t(kMaxDots) * kRedBlocks * sS),
                   std::make_pair(&W.partial64, size_t(kRedBlocks) * 8),
                   std::make_pair(&W.dots, size_t(kMaxDots) * 8), std::make_pair(&W.yc, size_t(8) * 8),
-                  std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8)}) {
+                  std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8),
+                  std::make_pair(&W.pc, size_t(n7) * sS), std::make_pair(&W.pc2, size_t(n7) * sS),
+                  std::make_pair(&W.scc, size_t(n7) * sS)}) {
     hipError_t e = pr.first->ensure(pr.second);
     if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_step workspace: ") + hipGetErrorString(e));
   }
@@ -241,6 +243,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   S *pJ = W.pJ.as<S>(), *rhs = W.rhs.as<S>(), *b = W.b.as<S>(), *x = W.x.as<S>();
   S *y9 = W.y9.as<S>(), *v9 = W.v9.as<S>(), *partial = W.partial.as<S>(), *dots = W.dots.as<S>();
   S *yc = W.yc.as<S>(), *hbuf = W.hbuf.as<S>(), *JZ = W.JZ.as<S>();
+  S *pc = W.pc.as<S>(), *pc2 = W.pc2.as<S>(), *scc = W.scc.as<S>();
   double* partial64 = W.partial64.as<double>();
   double* Ainv = W.Ainv.as<double>();
   const dim3 blk{256, 1, 1};
@@ -251,7 +254,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // aggregation coarse space (coarse = 3)
   AggGrid G{};
   int64_t nc = 0;
-  if (o.coarse == 3) {
+  const bool agg = (o.coarse == 3 || o.coarse == 4);
+  if (agg) {
     const int nx = ctx->mesh.nx, ny = ctx->mesh.ny, nz = ctx->mesh.nz;
     int A = o.coarse_agg;
     auto naggs = [&](int a) {
@@ -302,7 +306,37 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   };
   // preconditioner: out = B^-1 r (+ Z E^-1 Z^T r for the additive coarse
   // space; the deflated variant has already removed that part from r)
+  // out = Z E^-1 Z^T r (aggregation coarse space; E = D^-1 LU D^-1)
+  auto coarse_solve_into = [&](const S* r, S* out, bool add) {
+    hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
+    hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
+    rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), 1, cE, rocblas_int(nc), cipiv, crc,
+                     rocblas_int(nc));
+    hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
+    if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
+    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(n7), blk, 0, st, scc, crc, G, FS, out);
+  };
   auto precond = [&](S* r, S* out) {
+    if (o.coarse == 4) {
+      // multiplicative two-level: coarse solve, then the element blocks on
+      // the remaining residual: out = c + B^-1 (r - J c), c = Z E^-1 Z^T r
+      coarse_solve_into(r, pc, false);
+      jvp_cond(pc, pc2);
+      hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), r, S(-1), pc2, n7);
+      if constexpr (std::is_same<S, float>::value) {
+        if (o.block_bf16)
+          hipLaunchKernelGGL((apply_blocks_bf16_kernel<7>), gw, blk, 0, st, ctx->bh.as<const uint16_t>(), pc2,
+                             out, ctx->Ne);
+        else
+          hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks),
+                             pc2, out, ctx->Ne);
+      } else {
+        hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), pc2,
+                           out, ctx->Ne);
+      }
+      hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), pc, S(1), out, n7);
+      return;
+    }
     deflate(r);
     if constexpr (std::is_same<S, float>::value) {
       if (o.block_bf16)
@@ -319,13 +353,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       coarse_coeffs(r);
       hipLaunchKernelGGL(coarse_add_kernel<S>, grid1(n7), blk, 0, st, sc, yc, out, FS);
     } else if (o.coarse == 3) {
-      // out += Z E^-1 Z^T r with E = D^-1 LU D^-1 (equilibrated)
-      hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, sc, r, G, FS, crc);
-      hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
-      rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), 1, cE, rocblas_int(nc), cipiv, crc,
-                       rocblas_int(nc));
-      hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
-      hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(n7), blk, 0, st, sc, crc, G, FS, out);
+      coarse_solve_into(r, out, true);      // additive: out += Z E^-1 Z^T r
     }
   };
   auto opA = [&](const S* v, S* out) {           // out = sc^-1 M^-1 J (sc v)
@@ -395,6 +423,9 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   double gm_rtol = o.gmres_rtol;
   double best_upd = 1e300;
   int stall = 0, prev_its = 0;
+  // Operator and preconditioner are rebuilt at every Newton iterate: a
+  // preconditioner kept from an earlier iterate cost more GMRES iterations
+  // than its rebuild on the 16^3 cube.
   for (int it = 1; it <= o.newton_maxit; ++it) {
     r.newton_its = it;
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
@@ -407,15 +438,17 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
                          static_cast<const float*>(ctx->d_blocks), ctx->bh.as<uint16_t>(), ctx->Ne);
     }
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
-    if (o.coarse == 3) {
-      // aggregation coarse operator E = Z^T J Z by coloured probes, then LU
+    if (agg) {
+      // aggregation coarse operator E = Z^T J Z by coloured probes, then LU;
+      // Z keeps the unknown scales of this rebuild (scc)
+      hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), sc, S(0), scc, n7);
       DG_HIP(hipMemsetAsync(cE, 0, size_t(nc) * nc * 8, st));
       for (int f = 0; f < 7; ++f) {
         if (!((active >> f) & 1)) continue;
         for (int c = 0; c < 7; ++c) {
-          hipLaunchKernelGGL(agg_probe_kernel<S>, grid1(n7), blk, 0, st, sc, f, c, G, FS, t);
+          hipLaunchKernelGGL(agg_probe_kernel<S>, grid1(n7), blk, 0, st, scc, f, c, G, FS, t);
           jvp_cond(t, pJ);
-          hipLaunchKernelGGL(agg_probe_reduce_kernel<S>, gagg, blk, 0, st, sc, pJ, f, c, G, FS, cE, nc);
+          hipLaunchKernelGGL(agg_probe_reduce_kernel<S>, gagg, blk, 0, st, scc, pJ, f, c, G, FS, cE, nc);
         }
       }
       hipLaunchKernelGGL(coarse_diag_kernel, grid1(nc), blk, 0, st, cE, nc, nc, cd);
@@ -684,7 +717,7 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
     return fail(DG_EINVAL, std::string(fn) + ": bad inner precision");
   if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
   if (o.coarse < 0) o.coarse = 0;
-  if (o.coarse > 3) return fail(DG_EINVAL, std::string(fn) + ": coarse must be -1..3");
+  if (o.coarse > 4) return fail(DG_EINVAL, std::string(fn) + ": coarse must be -1..4");
   return DG_OK;
 }
 

@@ -142,15 +142,16 @@ def test_step_invariants_on_cube16():
         assert ratio <= 1e-6, f
 
 
+@pytest.mark.parametrize("coarse", [3, 4])
 @pytest.mark.parametrize("inner,tol", [("f64", 1e-10), ("f32", 1e-8)])
-def test_step_with_aggregation_coarse_space(small_case, inner, tol):
+def test_step_with_aggregation_coarse_space(small_case, inner, tol, coarse):
     """The two-level preconditioner (per-field constants on 2x2x2-voxel
     aggregates, coarse operator by coloured probes, LU) reaches the same
     root."""
     P, ctx, u0, u1 = small_case
     ut = torch.tensor(u0, device="cuda:0")
-    rep = ctx.step(ut, 0.0, 0.1, inner=inner, coarse=3, coarse_agg=2, verbose=1)
-    print(f"[step] coarse=3 {inner} report {rep}", flush=True)
+    rep = ctx.step(ut, 0.0, 0.1, inner=inner, coarse=coarse, coarse_agg=2, verbose=1)
+    print(f"[step] coarse={coarse} {inner} report {rep}", flush=True)
     err = rel_l2(ut.cpu().numpy(), u1)
     print("  relative L2 per field", err, flush=True)
     assert np.all(err < tol), err
@@ -165,14 +166,15 @@ def test_aggregation_coarse_space_cuts_gmres_on_cube16():
                                        param_seed=w.param_seed, f_C=w.f_C)
     u0, _ = ctx.initial_state(inner="f32")
     reps, roots = {}, {}
-    for coarse in (1, 3):
+    for coarse in (1, 3, 4):
         ut = u0.clone()
         reps[coarse] = ctx.step(ut, 0.0, 0.1, inner="f32", coarse=coarse)
         roots[coarse] = ut.cpu().numpy()
         print(f"[step] cube16 coarse={coarse}: {reps[coarse]}", flush=True)
-    err = rel_l2(roots[3], roots[1])
-    print("  relative L2 between the roots", err, flush=True)
-    assert np.all(err[:7] < 1e-8), err
+    for c in (3, 4):
+        err = rel_l2(roots[c], roots[1])
+        print(f"  relative L2 between the roots (coarse {c} vs 1)", err, flush=True)
+        assert np.all(err[:7] < 1e-8), err
     assert reps[3]["gmres_its"] < reps[1]["gmres_its"]
 
 
