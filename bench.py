@@ -89,7 +89,7 @@ def recorded_traffic(workload, kernel):
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings),
     or None when absent or taken on other kernel sources."""
     import re
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
     want = source_hash()
@@ -183,11 +183,14 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     return kernels, (b_apply, ms_apply)
 
 
-def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0):
+def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
     """n Newton iterations of the implicit step from (t, u) (one dg_step call)."""
     from paper_2511_05233_amd import lsbdg
+    if n < 1:
+        return {"newton_its": 0, "gmres_its": 0, "last_update": float("nan")}
     try:
-        rep = ctx.step(u, t, dt, inner=inner, verbose=verbose, newton_maxit=n, coarse=coarse)
+        rep = ctx.step(u, t, dt, inner=inner, verbose=verbose, newton_maxit=n, coarse=coarse,
+                       coarse_agg=coarse_agg)
     except lsbdg.DgError as e:
         if e.code != -4:                      # DG_ENOCONV: the iteration cap was reached
             raise
@@ -230,11 +233,11 @@ def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
             "rel_l2_mixed_vs_f64": [float(f"{x:.2e}") for x in rel]}
 
 
-def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0):
+def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
     """n accepted steps of the naive controller (halving on failed solves)."""
     tot = {"newton_its": 0, "gmres_its": 0, "trials": 0, "halvings": 0}
     for _ in range(n):
-        t, rep = ctx.advance(ctrl, t, u, inner=inner, verbose=verbose, coarse=coarse)
+        t, rep = ctx.advance(ctrl, t, u, inner=inner, verbose=verbose, coarse=coarse, coarse_agg=coarse_agg)
         for k in tot:
             tot[k] += rep[k]
         log(f"[bench] step of {rep['dt']:.4g} s to t = {t:.4f} s: {rep['trials']} trials, "
@@ -251,8 +254,9 @@ def main(argv=None):
     ap.add_argument("--dt", type=float, default=0.1, help="first trial step [s]")
     ap.add_argument("--inner", default="f32", choices=["f32", "f64"])
     ap.add_argument("--coarse", type=int, default=0,
-                    help="preconditioner coarse space (0: library default, 1: global constants, "
-                         "3: voxel aggregates)")
+                    help="preconditioner coarse space (0: library default = 3, 1: global constants, "
+                         "3: voxel aggregates, additive, 4: multiplicative)")
+    ap.add_argument("--coarse-agg", type=int, default=0, help="aggregate edge in voxels (0: automatic)")
     ap.add_argument("--workload", default="slab96_q1")
     ap.add_argument("--compare-f64", action="store_true",
                     help="repeat the timed steps with an FP64 inner solve from the same state")
@@ -295,16 +299,17 @@ def main(argv=None):
             out["copy_probe_bytes"] = copy_probe(dev)
         print(json.dumps(out), flush=True)
         return 0
-    u, rep0 = ctx.initial_state(inner=args.inner, verbose=args.verbose, coarse=args.coarse)
+    u, rep0 = ctx.initial_state(inner=args.inner, verbose=args.verbose, coarse=args.coarse,
+                                coarse_agg=args.coarse_agg)
     log(f"[bench] initial state: {rep0['newton_its']} Newton, {rep0['gmres_its']} GMRES")
     t = 0.0
     if args.mode == "newton":
-        newton_iterations(ctx, u, t, args.dt, args.warmup, args.inner, log, args.verbose, args.coarse)
+        newton_iterations(ctx, u, t, args.dt, args.warmup, args.inner, log, args.verbose, args.coarse, args.coarse_agg)
         u_start = u.clone() if args.compare_f64 else None
         t_start = t
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        rep = newton_iterations(ctx, u, t, args.dt, args.steps, args.inner, log, args.verbose, args.coarse)
+        rep = newton_iterations(ctx, u, t, args.dt, args.steps, args.inner, log, args.verbose, args.coarse, args.coarse_agg)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         done = max(rep["newton_its"], 1)
@@ -312,13 +317,13 @@ def main(argv=None):
         tot = {"newton_its": rep["newton_its"], "gmres_its": rep["gmres_its"]}
     else:
         ctrl = lsbdg.controller("naive", dt0=args.dt)
-        t, _ = run_steps(ctx, ctrl, u, t, args.warmup, args.inner, log, args.verbose, args.coarse)
+        t, _ = run_steps(ctx, ctrl, u, t, args.warmup, args.inner, log, args.verbose, args.coarse, args.coarse_agg)
         u_start = u.clone() if args.compare_f64 else None
         ctrl_start = lsbdg.DgController.from_buffer_copy(ctrl)
         t_start = t
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        t, tot = run_steps(ctx, ctrl, u, t, args.steps, args.inner, log, args.verbose, args.coarse)
+        t, tot = run_steps(ctx, ctrl, u, t, args.steps, args.inner, log, args.verbose, args.coarse, args.coarse_agg)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         done = args.steps
@@ -348,7 +353,7 @@ def main(argv=None):
                             "FP64 update" if args.mode == "newton" else
                             "accepted step of the naive time controller (backward-Euler Newton-GMRES "
                             "solves, halving dt on failure)"),
-                   "coarse": args.coarse, "timed_steps": done, **{k: v for k, v in tot.items()}},
+                   "coarse": args.coarse, "coarse_agg": args.coarse_agg, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(w.name, "apply_blocks_kernel"),
@@ -361,11 +366,11 @@ def main(argv=None):
         torch.cuda.synchronize()
         w1 = time.perf_counter()
         if args.mode == "newton":
-            rep64 = newton_iterations(ctx, u64, t_start, args.dt, args.steps, "f64", log, args.verbose, args.coarse)
+            rep64 = newton_iterations(ctx, u64, t_start, args.dt, args.steps, "f64", log, args.verbose, args.coarse, args.coarse_agg)
             tot64 = {"newton_its": rep64["newton_its"], "gmres_its": rep64["gmres_its"]}
         else:
             ctrl64 = lsbdg.DgController.from_buffer_copy(ctrl_start)
-            _, tot64 = run_steps(ctx, ctrl64, u64, t_start, args.steps, "f64", log, args.verbose, args.coarse)
+            _, tot64 = run_steps(ctx, ctrl64, u64, t_start, args.steps, "f64", log, args.verbose, args.coarse, args.coarse_agg)
         torch.cuda.synchronize()
         wall64 = time.perf_counter() - w1
         rel = [float(torch.linalg.norm(u[f] - u64[f]) / torch.clamp(torch.linalg.norm(u64[f]), min=1e-300))

@@ -188,9 +188,8 @@ typedef struct {
                             (default 1e-11; FP32 inner solves stop at 1e-5) */
   double newton_tol;     /* converged when a full step changes no unknown by
                             more than this relative amount (default 1e-11) */
-  int32_t coarse;        /* coarse space of the preconditioner: 0 = by
-                            precision (1 for DG_F32, 2 for DG_F64), 1 =
-                            global per-field constants,
+  int32_t coarse;        /* coarse space of the preconditioner: 0 = default
+                            (3), 1 = global per-field constants,
                             additive, 2 = global per-field constants with
                             deflation (exact coarse solve), 3 = per-field
                             constants on voxel aggregates, additive (a

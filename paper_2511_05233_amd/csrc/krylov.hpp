@@ -15,7 +15,7 @@
 
 namespace lsbdg {
 
-constexpr int kRedBlocks = 1024;   // partial sums per reduction
+constexpr int kRedBlocks = 4096;   // partial sums per reduction
 constexpr int kMaxDots = 32;       // vectors per multi-dot (restart + 2)
 
 template <typename A, typename B>
@@ -65,15 +65,22 @@ template <typename S>
 __global__ void __launch_bounds__(256)
 multi_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ w, int64_t n,
                  S* __restrict__ partial) {
+  // four consecutive entries per thread (n and ldv are multiples of 4:
+  // Krylov vectors hold 7 fields x 8 nodes per voxel)
+  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
   __shared__ S sh[4];
   S acc[kMaxDots];
 #pragma unroll
   for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) {
-    const S wk = w[k];
+  const int64_t n4 = n >> 2;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    const Q wk = reinterpret_cast<const Q*>(w)[k];
 #pragma unroll
     for (int i = 0; i < kMaxDots; ++i)
-      if (i < nv) acc[i] += V[i * ldv + k] * wk;
+      if (i < nv) {
+        const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
+        acc[i] += v.a * wk.a + v.b * wk.b + v.c * wk.c + v.d * wk.d;
+      }
   }
 #pragma unroll
   for (int i = 0; i < kMaxDots; ++i) {
@@ -100,10 +107,24 @@ template <typename S>
 __global__ void __launch_bounds__(256)
 multi_axpy_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h, S sign,
                   S* __restrict__ w, int64_t n) {
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) {
-    S acc = S(0);
-    for (int i = 0; i < nv; ++i) acc += h[i] * V[i * ldv + k];
-    w[k] += sign * acc;
+  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
+  const int64_t n4 = n >> 2;                 // n, ldv: multiples of 4
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    Q acc{S(0), S(0), S(0), S(0)};
+    for (int i = 0; i < nv; ++i) {
+      const S hi = h[i];
+      const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
+      acc.a += hi * v.a;
+      acc.b += hi * v.b;
+      acc.c += hi * v.c;
+      acc.d += hi * v.d;
+    }
+    Q wk = reinterpret_cast<Q*>(w)[k];
+    wk.a += sign * acc.a;
+    wk.b += sign * acc.b;
+    wk.c += sign * acc.c;
+    wk.d += sign * acc.d;
+    reinterpret_cast<Q*>(w)[k] = wk;
   }
 }
 

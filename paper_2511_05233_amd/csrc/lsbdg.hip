@@ -47,7 +47,7 @@ struct dg_ctx {
   DevBuf lin;
   // aggregation coarse space: LU of the equilibrated coarse operator,
   // equilibration, pivots, a coarse vector, LAPACK status
-  DevBuf cE, cd, crc, cipiv, cinfo;
+  DevBuf cE, cd, crc, crc2, cipiv, cinfo;
   // bfloat16 copy of FP32 block inverses (block_bf16)
   DevBuf bh;
   rocblas_handle blas = nullptr;
@@ -271,7 +271,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     nc = 7 * G.na;
     if (nc > (int64_t(1) << 20)) return fail(DG_EINVAL, "dg_step: coarse space too large (raise coarse_agg)");
     for (auto pr : {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cd, size_t(nc) * 8),
-                    std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->cipiv, size_t(nc) * 4),
+                    std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->crc2, size_t(nc) * 8),
+                    std::make_pair(&ctx->cipiv, size_t(nc) * 4),
                     std::make_pair(&ctx->cinfo, size_t(4))}) {
       hipError_t e = pr.first->ensure(pr.second);
       if (e != hipSuccess) return fail(DG_ENOMEM, std::string("coarse space: ") + hipGetErrorString(e));
@@ -283,6 +284,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   double* cE = ctx->cE.as<double>();
   double* cd = ctx->cd.as<double>();
   double* crc = ctx->crc.as<double>();
+  double* crc2 = ctx->crc2.as<double>();
   rocblas_int* cipiv = ctx->cipiv.as<rocblas_int>();
   rocblas_int* cinfo = ctx->cinfo.as<rocblas_int>();
   const dim3 gagg{unsigned(G.na > 0 ? G.na : 1), 1, 1};
@@ -306,15 +308,18 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   };
   // preconditioner: out = B^-1 r (+ Z E^-1 Z^T r for the additive coarse
   // space; the deflated variant has already removed that part from r)
-  // out = Z E^-1 Z^T r (aggregation coarse space; E = D^-1 LU D^-1)
+  // out = Z E^-1 Z^T r (aggregation coarse space): E^-1 = D Einv D with the
+  // explicit inverse Einv of the equilibrated operator, applied as one dense
+  // GEMV (triangular solves with the LU factors run far below HBM speed)
   auto coarse_solve_into = [&](const S* r, S* out, bool add) {
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
     hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
-    rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), 1, cE, rocblas_int(nc), cipiv, crc,
-                     rocblas_int(nc));
-    hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
+    const double one = 1.0, zero = 0.0;
+    rocblas_dgemv(ctx->blas, rocblas_operation_none, rocblas_int(nc), rocblas_int(nc), &one, cE, rocblas_int(nc),
+                  crc, 1, &zero, crc2, 1);
+    hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc2, cd, nc);
     if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
-    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(n7), blk, 0, st, scc, crc, G, FS, out);
+    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(n7), blk, 0, st, scc, crc2, G, FS, out);
   };
   auto precond = [&](S* r, S* out) {
     if (o.coarse == 4) {
@@ -458,6 +463,11 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
           rocblas_status_success)
         return fail(DG_EHIP, "dg_step: rocsolver_dgetrf failed");
       rocblas_int hinfo = 0;
+      DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+      DG_HIP(hipStreamSynchronize(st));
+      if (hinfo != 0) return fail(DG_ENAN, "dg_step: singular aggregation coarse operator");
+      if (rocsolver_dgetri(ctx->blas, rocblas_int(nc), cE, rocblas_int(nc), cipiv, cinfo) != rocblas_status_success)
+        return fail(DG_EHIP, "dg_step: rocsolver_dgetri failed");
       DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
       DG_HIP(hipStreamSynchronize(st));
       if (hinfo != 0) return fail(DG_ENAN, "dg_step: singular aggregation coarse operator");
@@ -715,7 +725,7 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
   if (o.newton_maxit < 1 || o.gmres_maxit < 1) return fail(DG_EINVAL, std::string(fn) + ": iteration limits");
   if (o.inner_prec != DG_F32 && o.inner_prec != DG_F64)
     return fail(DG_EINVAL, std::string(fn) + ": bad inner precision");
-  if (o.coarse == 0) o.coarse = (o.inner_prec == DG_F64) ? 2 : 1;
+  if (o.coarse == 0) o.coarse = 3;
   if (o.coarse < 0) o.coarse = 0;
   if (o.coarse > 4) return fail(DG_EINVAL, std::string(fn) + ": coarse must be -1..4");
   return DG_OK;
@@ -820,7 +830,7 @@ int dg_destroy(dg_ctx* ctx) {
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   ctx->work.release_all();
   ctx->lin.release();
-  for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->cipiv, &ctx->cinfo, &ctx->bh}) b->release();
+  for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->crc2, &ctx->cipiv, &ctx->cinfo, &ctx->bh}) b->release();
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   delete ctx;
   return DG_OK;
@@ -1022,7 +1032,7 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->gmres_rtol = 1e-4;
   o->gmres_rtol_final = 1e-11;
   o->newton_tol = 1e-11;
-  o->coarse = 0;           // 0: per precision (additive for FP32, deflation for FP64)
+  o->coarse = 0;           // 0: the aggregation coarse space (3)
   o->verbose = 0;
 }
 
