@@ -233,6 +233,41 @@ def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
             "rel_l2_mixed_vs_f64": [float(f"{x:.2e}") for x in rel]}
 
 
+def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9, max_steps=5000):
+    """Full galvanostatic discharge under the naive controller (Sec. 2.7):
+    from the initial state until U_cell <= cutoff or t >= 3600 / f_C."""
+    import torch
+    import synth
+    from paper_2511_05233_amd import lsbdg
+    w = synth.WORKLOADS[workload]
+    D0, i0 = synth.sample_transport_kinetics(w.param_seed)
+    ctx = lsbdg.Context(w.nx, w.ny, w.nz, w.h, w.order, w.mask(), D0=D0, kE=i0 / FARADAY, f_C=f_C)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    u, _ = ctx.initial_state(inner=inner, coarse=coarse, coarse_agg=coarse_agg)
+    ctrl = lsbdg.controller("naive", dt0=dt0)
+    t, t_end = 0.0, 3600.0 / f_C
+    tot = {"steps": 0, "trials": 0, "halvings": 0, "newton_its": 0, "gmres_its": 0}
+    U = ctx.outputs(u, t)["U_cell"]
+    curve = [(0.0, U)]
+    while t < t_end and U > cutoff and tot["steps"] < max_steps:
+        t, rep = ctx.advance(ctrl, t, u, inner=inner, coarse=coarse, coarse_agg=coarse_agg)
+        for k in ("trials", "halvings", "newton_its", "gmres_its"):
+            tot[k] += rep[k]
+        tot["steps"] += 1
+        U = ctx.outputs(u, t)["U_cell"]
+        curve.append((t, U))
+        log(f"[discharge] step {tot['steps']}: t = {t:.4g} s, dt = {rep['dt']:.3g} s, U_cell = {U:.5f} V, "
+            f"{rep['newton_its']} Newton, {rep['gmres_its']} GMRES")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    soc = 1.0 - t / t_end
+    return {"workload": f"{workload} at {f_C}C", "s_per_discharge": round(wall, 2), "t_end_s": round(t, 3),
+            "U_end_V": round(U, 5), "soc_end": round(soc, 4), **tot,
+            "ended_by": "cutoff" if U <= cutoff else ("time" if t >= t_end else "step limit"),
+            "curve_tU": [(round(a, 3), round(b, 6)) for a, b in curve[:: max(1, len(curve) // 40)]]}
+
+
 def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
     """n accepted steps of the naive controller (halving on failed solves)."""
     tot = {"newton_its": 0, "gmres_its": 0, "trials": 0, "halvings": 0}
@@ -266,6 +301,10 @@ def main(argv=None):
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: skip the solves and time the kernels alone on a seeded "
                          "random state (prints the kernel table, not the benchmark line)")
+    ap.add_argument("--discharge", default=None, metavar="WORKLOAD",
+                    help="run one full discharge of WORKLOAD (naive controller, cutoff 1.9 V) and print "
+                         "its wall time instead of the benchmark line")
+    ap.add_argument("--discharge-rate", type=float, default=1.0, help="C-rate of --discharge")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -281,6 +320,10 @@ def main(argv=None):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if args.discharge:
+        out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log)
+        print(json.dumps(out), flush=True)
+        return 0
     w = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     mask = w.mask()

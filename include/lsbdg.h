@@ -198,7 +198,7 @@ typedef struct {
                             multiplicatively (coarse solve, then the element
                             blocks on the remaining residual), -1 = none */
   int32_t coarse_agg;    /* aggregate edge in voxels for coarse = 3, 4 (0: the
-                            smallest edge >= 4 with at most 16384 coarse
+                            smallest edge >= 4 with at most 8192 coarse
                             unknowns) */
   int32_t block_bf16;    /* DG_F32 inner solves: 1 streams the element block
                             inverses as bfloat16 in the preconditioner apply

@@ -263,7 +263,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     };
     if (A <= 0) {
       A = 4;
-      while (7 * naggs(A) > 16384) ++A;
+      while (7 * naggs(A) > 8192) ++A;
     }
     G.nx = nx; G.ny = ny; G.nz = nz; G.A = A;
     G.nax = (nx + A - 1) / A; G.nay = (ny + A - 1) / A; G.naz = (nz + A - 1) / A;
