@@ -2,7 +2,8 @@
 
     python bench.py [--steps K] [--warmup W] [--mode newton|controller] [--dt S]
                     [--inner f32|f64] [--workload slab96_q1] [--compare-f64]
-                    [--no-cpu-baseline] [--kernels-only] [--copy-probe]
+                    [--no-cpu-baseline] [--no-c3] [--kernels-only] [--copy-probe]
+                    [--discharge WORKLOAD [--discharge-rate C]]
 
 Workload (default): the 96 x 96 x 192 voxel cathode slab (x = transport
 axis, 1 um voxels), DG-Q1, 9 unknowns per node of which 7 are transported
@@ -28,6 +29,10 @@ linearisation, in the inner precision), timed with HIP events on the stream
 it runs on.  roofline = the kernel with the largest share of a Newton
 iteration (the block apply: one per GMRES iteration) against the HBM peak;
 the other kernels are listed beside it.
+
+Beside the line (skipped with --no-c3): five steps on the 16^3 cube and a
+full 1C discharge of it to the 1.9 V cutoff, each with FP64 and with mixed
+(FP32 inner) solves -- wall times, speedup and the difference of the results.
 """
 from __future__ import annotations
 
@@ -265,7 +270,29 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
     return {"workload": f"{workload} at {f_C}C", "s_per_discharge": round(wall, 2), "t_end_s": round(t, 3),
             "U_end_V": round(U, 5), "soc_end": round(soc, 4), **tot,
             "ended_by": "cutoff" if U <= cutoff else ("time" if t >= t_end else "step limit"),
-            "curve_tU": [(round(a, 3), round(b, 6)) for a, b in curve[:: max(1, len(curve) // 40)]]}
+            "curve_tU": [(round(a, 3), round(b, 6)) for a, b in curve[:: max(1, len(curve) // 40)]],
+            "_curve": curve}
+
+
+def discharge_mixed_vs_f64(workload, f_C, coarse, coarse_agg, log):
+    """The same full discharge with FP64 and with mixed (FP32 inner) solves:
+    wall time of each and the largest cell-voltage difference between the
+    two discharge curves (at the accepted step times of the FP64 run)."""
+    runs = {}
+    for inner in ("f64", "f32"):
+        runs[inner] = discharge(workload, f_C, inner, coarse, coarse_agg, log)
+        log(f"[bench] discharge {workload} {inner}: {runs[inner]['s_per_discharge']} s")
+    c64 = np.array(runs["f64"]["_curve"])
+    c32 = np.array(runs["f32"]["_curve"])
+    t_hi = min(c64[-1, 0], c32[-1, 0])
+    sel = c64[:, 0] <= t_hi
+    dU = np.abs(np.interp(c64[sel, 0], c32[:, 0], c32[:, 1]) - c64[sel, 1])
+    strip = lambda r: {k: v for k, v in r.items() if k not in ("_curve", "curve_tU")}
+    return {"workload": f"{workload} at {f_C}C, naive controller from the initial state to the 1.9 V cutoff",
+            "s_f64": runs["f64"]["s_per_discharge"], "s_mixed": runs["f32"]["s_per_discharge"],
+            "mixed_speedup": round(runs["f64"]["s_per_discharge"] / runs["f32"]["s_per_discharge"], 3),
+            "max_abs_dU_cell_V": float(f"{dU.max():.3e}"),
+            "f64": strip(runs["f64"]), "mixed": strip(runs["f32"])}
 
 
 def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
@@ -296,7 +323,8 @@ def main(argv=None):
     ap.add_argument("--compare-f64", action="store_true",
                     help="repeat the timed steps with an FP64 inner solve from the same state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-c3", action="store_true", help="skip the mixed-vs-FP64 comparison on the 16^3 cube")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the mixed-vs-FP64 comparisons on the 16^3 cube (5 steps and a full 1C discharge)")
     ap.add_argument("--verbose", type=int, default=0, help="Newton progress lines on stderr")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling aid: skip the solves and time the kernels alone on a seeded "
@@ -322,6 +350,7 @@ def main(argv=None):
 
     if args.discharge:
         out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log)
+        out.pop("_curve")
         print(json.dumps(out), flush=True)
         return 0
     w = synth.WORKLOADS[args.workload]
@@ -425,6 +454,7 @@ def main(argv=None):
                             "rel_l2_mixed_vs_f64": [float(f"{x:.3e}") for x in rel]}
     if not args.no_c3:
         out["mixed_vs_f64"] = mixed_vs_f64(args.coarse, log)
+        out["discharge_mixed_vs_f64"] = discharge_mixed_vs_f64("cube16_q1", 1.0, args.coarse, 0, log)
     if args.copy_probe:
         out["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu_baseline:
