@@ -295,6 +295,168 @@ def discharge_mixed_vs_f64(workload, f_C, coarse, coarse_agg, log):
             "f64": strip(runs["f64"]), "mixed": strip(runs["f32"])}
 
 
+def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
+    """Row a13 (batching) on the batch workload: n cubic structures with
+    edges ~ U{24..64} voxels and porosities ~ U(0.4, 0.75) (seeded), each
+    with its own kinetics draw.  Every operator runs as one launch over all
+    structures; the same work as one launch per structure is timed beside
+    it, eagerly and replayed from a captured graph."""
+    import torch
+    import synth
+    from paper_2511_05233_amd import lsbdg
+    specs = synth.batch_structures(n)
+    structs, ctxs, parts = [], [], []
+    for b, (edge, por, mseed) in enumerate(specs):
+        mask = synth.porosity_mask((edge, edge, edge), por, mseed)
+        D0, i0 = synth.sample_transport_kinetics(b)
+        kw = dict(D0=D0, kE=i0 / FARADAY, f_C=0.1)
+        structs.append(dict(nx=edge, ny=edge, nz=edge, h=1e-6, phase=mask, **kw))
+        ctx = lsbdg.Context(edge, edge, edge, 1e-6, 1, mask, **kw)
+        ctxs.append(ctx)
+        parts.append(random_state(ctx, mask, 100 + b, dev))
+    B = lsbdg.Batch(structs)
+    E = B.n_elem
+    log(f"[bench] batch: {n} structures, {E} voxels, {B.n_tiles} tiles")
+    u64 = torch.cat(parts, dim=1)
+    del parts
+    u32 = u64.float()
+    g = torch.Generator(device=dev).manual_seed(11)
+    v7 = torch.randn((7, E, 8), generator=g, dtype=torch.float32, device=dev)
+    y7 = torch.empty_like(v7)
+    m8 = B.mass(u64)
+    r9 = torch.empty_like(u64)
+    tt = [t] * n
+    dd = [dt] * n
+    stream = torch.cuda.current_stream()
+    # one launch over the whole batch
+    B.linearize(u32, tt, dd)
+    ms_jvp_b = time_launches(lambda: B.jvp(u32, v7, tt, dd, out=y7, linearized=True), stream, reps)
+    ms_res_b = time_launches(lambda: B.residual(u64, m8, tt, dd, out=r9), stream, reps)
+    # the same work, one launch per structure (contiguous per-structure copies)
+    us32 = [B.part(u32, s).contiguous() for s in range(n)]
+    us64 = [B.part(u64, s).contiguous() for s in range(n)]
+    vs = [B.part(v7, s).contiguous() for s in range(n)]
+    ys = [torch.empty_like(x) for x in vs]
+    ms8 = [B.part(m8, s).contiguous() for s in range(n)]
+    rs = [torch.empty_like(x) for x in us64]
+    for s, c in enumerate(ctxs):
+        c.linearize(us32[s], t, dt)
+
+    def seq_jvp():
+        for s, c in enumerate(ctxs):
+            c.jvp(us32[s], vs[s], t, dt, out=ys[s], linearized=True)
+
+    def seq_res():
+        for s, c in enumerate(ctxs):
+            c.residual(us64[s], ms8[s], t, dt, out=rs[s])
+
+    ms_jvp_s = time_launches(seq_jvp, stream, reps)
+    ms_res_s = time_launches(seq_res, stream, reps)
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+
+    diff_jvp = max(rel(B.part(y7, s), ys[s]) for s in range(n))
+    diff_res = max(rel(B.part(r9, s), rs[s]) for s in range(n))
+    # the per-structure launches replayed from a captured graph (the
+    # product's outputs are compared with the eager ones after the replays)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        seq_jvp()
+    stream.wait_stream(side)
+    with torch.cuda.graph(graph):
+        seq_jvp()
+    ref = [y.clone() for y in ys]
+    ms_jvp_g = time_launches(graph.replay, stream, reps)
+    graph_same = all(torch.equal(ys[s], ref[s]) for s in range(n))
+    del graph
+    dof = E * 56
+    b_apply = E * (56 * 56 + 2 * 56) * 4
+    ms_setup_b = ms_apply_b = None
+    if full:
+        # batched block preconditioner (E blocks of 56 x 56 in FP32)
+        ms_setup_b = time_launches(lambda: B.blockjacobi_setup(u32, tt, dd), stream, 1)
+        ms_apply_b = time_launches(lambda: B.blockjacobi_apply(v7, out=y7), stream, reps)
+    for c in ctxs:
+        c.close()
+    B.close()
+    del u32, v7, y7, m8, r9, us32, us64, vs, ys, ms8, rs, ref
+    torch.cuda.empty_cache()
+    del u64
+    torch.cuda.empty_cache()
+    solve = batch_solves(structs, dof, log) if full else None
+    res = {
+        "workload": f"{n} cubic structures, edges U{{24..64}} voxels, porosity U(0.4, 0.75), DG-Q1, "
+                    f"{E} voxels, {dof} DoF, {B.n_tiles} work items of 32 voxels",
+        "jvp_f32_ms": {"batched": round(ms_jvp_b, 3), "per_structure": round(ms_jvp_s, 3),
+                       "per_structure_graph": round(ms_jvp_g, 3)},
+        "jvp_f32_gdofs": {"batched": round(dof / ms_jvp_b / 1e6, 2),
+                          "per_structure": round(dof / ms_jvp_s / 1e6, 2),
+                          "per_structure_graph": round(dof / ms_jvp_g / 1e6, 2)},
+        "residual_f64_ms": {"batched": round(ms_res_b, 3), "per_structure": round(ms_res_s, 3)},
+        "batched_speedup_jvp": round(ms_jvp_s / ms_jvp_b, 3),
+        "batched_speedup_residual": round(ms_res_s / ms_res_b, 3),
+        "block_setup_f32_ms": round(ms_setup_b, 1) if full else None,
+        "block_apply_f32": {"ms": round(ms_apply_b, 3), "GB/s": round(b_apply / ms_apply_b / 1e6, 1),
+                            "frac": round(b_apply / ms_apply_b / 1e6 / HBM_PEAK_GBS, 4)} if full else None,
+        "max_rel_diff_batched_vs_per_structure": {"jvp_f32": float(f"{diff_jvp:.3e}"),
+                                                  "residual_f64": float(f"{diff_res:.3e}")},
+        "graph_replay_equals_eager": bool(graph_same),
+        "implicit_step": solve,
+    }
+    if not full:
+        for k in ("block_setup_f32_ms", "block_apply_f32", "implicit_step"):
+            res.pop(k)
+    log(f"[bench] batch: JVP {ms_jvp_b:.3f} ms batched, {ms_jvp_s:.3f} ms per structure, "
+        f"{ms_jvp_g:.3f} ms per structure from a graph")
+    return res
+
+
+def batch_solves(structs, dof, log, dt=0.1, iters=2):
+    """The solver on the batch, FP32 inner solves: initial states of every
+    structure, then `iters` Newton iterations of the first implicit step
+    (dt) of every structure (the step definition of the main benchmark),
+    with the structures' solves one after another (one worker: the
+    sequential solves) and side by side (four workers, one HIP stream
+    each), from the same initial states."""
+    import torch
+    from paper_2511_05233_amd import lsbdg
+    B = lsbdg.Batch(structs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, reps0 = B.initial_state(inner="f32", workers=4)
+    torch.cuda.synchronize()
+    s_init = time.perf_counter() - t0
+    log(f"[bench] batch: initial states in {s_init:.2f} s (four workers)")
+    runs = {}
+    for workers in (4, 1):
+        uw = u.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            reps = B.step(uw, 0.0, dt, inner="f32", workers=workers, newton_maxit=iters)
+        except lsbdg.DgError as e:      # capped at `iters` iterations: not converged, by design
+            reps = e.reports
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs[workers] = (wall, uw, reps)
+        log(f"[bench] batch: {iters} Newton iterations of every structure in {wall:.2f} s with {workers} worker(s)")
+    same = torch.equal(runs[1][1], runs[4][1])
+    reps = runs[4][2]
+    B.close()
+    its = sum(r["newton_its"] for r in reps)
+    return {"dt_s": dt, "inner": "f32", "newton_iterations_per_structure": iters,
+            "initial_states_s": round(s_init, 2),
+            "initial_state_newton_its": sum(r["newton_its"] for r in reps0),
+            "s_sequential": round(runs[1][0], 2), "s_side_by_side_4": round(runs[4][0], 2),
+            "speedup": round(runs[1][0] / runs[4][0], 3),
+            "gdof_newton_its_per_s": {"sequential": round(dof * iters / runs[1][0] / 1e9, 3),
+                                      "side_by_side_4": round(dof * iters / runs[4][0] / 1e9, 3)},
+            "newton_its": its, "gmres_its": sum(r["gmres_its"] for r in reps),
+            "side_by_side_equals_sequential": bool(same)}
+
+
 def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
     """n accepted steps of the naive controller (halving on failed solves)."""
     tot = {"newton_its": 0, "gmres_its": 0, "trials": 0, "halvings": 0}
@@ -333,6 +495,11 @@ def main(argv=None):
                     help="run one full discharge of WORKLOAD (naive controller, cutoff 1.9 V) and print "
                          "its wall time instead of the benchmark line")
     ap.add_argument("--discharge-rate", type=float, default=1.0, help="C-rate of --discharge")
+    ap.add_argument("--batch", action="store_true",
+                    help="the 64-structure batch workload in full (operators, block preconditioner, "
+                         "side-by-side solves) and print that record only")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-operator record of the default line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -348,6 +515,9 @@ def main(argv=None):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if args.batch:
+        print(json.dumps(batch_throughput(torch.device("cuda:0"), log)), flush=True)
+        return 0
     if args.discharge:
         out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log)
         out.pop("_curve")
@@ -455,6 +625,10 @@ def main(argv=None):
     if not args.no_c3:
         out["mixed_vs_f64"] = mixed_vs_f64(args.coarse, log)
         out["discharge_mixed_vs_f64"] = discharge_mixed_vs_f64("cube16_q1", 1.0, args.coarse, 0, log)
+    if not args.no_batch:
+        ctx.close()
+        torch.cuda.empty_cache()
+        out["batch_operators"] = batch_throughput(dev, log, full=False)
     if args.copy_probe:
         out["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu_baseline:

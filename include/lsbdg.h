@@ -104,7 +104,7 @@ typedef struct {
 void dg_params_default(dg_params* p);
 
 /* Create a context for one voxel structure.
- *   mesh   mesh and degree (order 0 or 1)
+ *   mesh   mesh and degree (the kernels are Q1: order 1)
  *   phase  HOST array of nx*ny*nz bytes, x fastest: 0 = pore voxel
  *          (electrolyte only, no reactions), 1 = cathode structure voxel
  *          (Eq. 57 localisation); copied, may be freed after the call
@@ -318,6 +318,87 @@ typedef struct {
  * stream. */
 int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u, const dg_solver_opts* opts,
                dg_advance_report* report, dg_stream stream);
+
+/* ---- Batches: many structures of uneven size, one launch per operator ----
+ *
+ * A batch holds n independent voxel structures (each set up as by dg_setup
+ * with its own mesh, phase map and parameters, so its own applied current,
+ * Eq. 57 localisation and App. C loading).  Batch arrays concatenate the
+ * structures voxel by voxel in the field-major layout a[f][E][n]: E is the
+ * total voxel count, structure s owns voxels [off[s], off[s+1]) in its own
+ * x-fastest order, n = 0..7 the Q1 node.  Every operator runs as one launch
+ * over work items of 32 voxels of one structure and gives, structure by
+ * structure, the values of the single-structure call (dg_mass, dg_residual,
+ * dg_jvp, dg_linearize, dg_blockjacobi_*) on that structure's slice.
+ * t_new and dt are HOST arrays of n values (each structure steps on its own
+ * clock).  Parameter blocks are staged through library-owned pinned memory;
+ * calls on one batch must not overlap (they share that staging, the
+ * linearisation and the block storage).  The batch workload these serve is
+ * the configuration of many microstructures solved side by side; the
+ * operators are those of Eq. 43-47 and 50 as for one structure. */
+typedef struct dg_batch dg_batch;
+
+/* n >= 1 structures: meshes[n], phases[n] (HOST arrays of nx*ny*nz bytes,
+ * copied), params[n] (copied).  Errors as dg_setup, for the first structure
+ * that fails (named in dg_last_error). */
+int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phases,
+                   const dg_params* params, dg_batch** out);
+
+/* Free the batch and its device storage. */
+int dg_batch_destroy(dg_batch* b);
+
+/* Voxel offsets off[0..n] (HOST array of n + 1 values; off[n] = E) and the
+ * number of work items (may be null). */
+int dg_batch_layout(const dg_batch* b, int64_t* offsets, int64_t* n_tiles);
+
+/* dg_mass of every structure.  u: device, 9 x E x 8; m: device, 8 x E x 8. */
+int dg_batch_mass(dg_batch* b, dg_prec prec, const void* u, void* m, dg_stream stream);
+
+/* dg_residual of every structure (t_new[s], dt[s] > 0).  u, r: 9 x E x 8;
+ * m_old: 8 x E x 8 (dg_batch_mass of the old states). */
+int dg_batch_residual(dg_batch* b, dg_prec prec, const void* u, const void* m_old, const double* t_new,
+                      const double* dt, void* r, dg_stream stream);
+
+/* dg_linearize of every structure into the batch's own storage. */
+int dg_batch_linearize(dg_batch* b, dg_prec prec, const void* u, const double* t_new, const double* dt,
+                       dg_stream stream);
+
+/* dg_jvp of every structure; modes and shapes as dg_jvp with E voxels.
+ * DG_ESTATE: DG_JVP_LINEARIZED7 without a batch linearisation of that
+ * precision. */
+int dg_batch_jvp(dg_batch* b, dg_prec prec, dg_jvp_mode mode, const void* u, const void* v,
+                 const double* t_new, const double* dt, void* jv, dg_stream stream);
+
+/* dg_blockjacobi_setup of every structure: E condensed 56 x 56 inverses in
+ * batch-owned device memory (also stores the linearisation at u).
+ * Synchronises the stream; DG_ENAN if any block is singular or not finite. */
+int dg_batch_blockjacobi_setup(dg_batch* b, dg_prec prec, const void* u, const double* t_new,
+                               const double* dt, dg_stream stream);
+
+/* y = B^-1 x for every voxel of the batch (7 x E x 8, precision of the
+ * setup).  DG_ESTATE before a setup. */
+int dg_batch_blockjacobi_apply(dg_batch* b, dg_prec prec, const void* x, void* y, dg_stream stream);
+
+/* Initial state (as dg_initial_state, at t0[s]) of every structure into the
+ * batch state u (device, FP64, 9 x E x 8).  The structures' solves run side
+ * by side on `workers` host threads (<= 0: 4), each with a HIP stream of its
+ * own and a library-owned contiguous state of the largest structure; each
+ * structure's result is that of dg_initial_state on it.  reports: HOST array
+ * of n (may be null).  Synchronises `stream` first (u may be written on it)
+ * and returns when every structure is done.  The first failing structure
+ * (in structure order) gives the status, named in dg_last_error; the other
+ * structures are still solved. */
+int dg_batch_initial_state(dg_batch* b, const double* t0, void* u, const dg_solver_opts* opts,
+                           dg_step_report* reports, int32_t workers, dg_stream stream);
+
+/* One backward-Euler step of every structure, from t_n[s] by dt[s] (HOST
+ * arrays of n): dg_step on each structure's slice of u (device, FP64,
+ * 9 x E x 8), the solves side by side as in dg_batch_initial_state.  Each
+ * structure's slice ends as dg_step leaves its state (the root, or the last
+ * iterate on DG_ENOCONV); reports[s] is its dg_step report.  Errors: as
+ * dg_step, for the first failing structure; DG_EINVAL for dt[s] <= 0. */
+int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, const dg_solver_opts* opts,
+                  dg_step_report* reports, int32_t workers, dg_stream stream);
 
 /* Human-readable description of the last error on this thread. */
 const char* dg_last_error(void);

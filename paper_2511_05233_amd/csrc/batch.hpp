@@ -1,0 +1,132 @@
+// Batched operators: many voxel structures of uneven size in one launch.
+//
+// The structures are concatenated voxel by voxel in the field-major layout
+// a[f][E][n] (E = total voxels; structure s owns voxels [base_s, base_s +
+// Ne_s)).  The work items are tiles of 32 consecutive voxels of one
+// structure -- 256 lanes, one per node, as in the single-structure kernels
+// -- so a workgroup never straddles two structures.  Each lane offsets the
+// array bases by its structure's first voxel and runs the same node code as
+// the single-structure kernels with the batch's field stride; the results
+// therefore equal those of one launch per structure.  Per-structure
+// parameters (time step, regularisation time, applied current, phase
+// table) are read from a device array indexed by the tile's structure.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "model.hpp"
+#include "resid_q1.hpp"
+#include "blockjacobi.hpp"
+
+namespace lsbdg {
+
+struct BatchTile {
+  int32_t s;       // structure
+  int32_t v0;      // first voxel of the tile within the structure
+  int64_t base;    // first voxel of the structure in the concatenation
+};
+
+constexpr int kTileVoxels = 32;   // 256 lanes / 8 nodes
+
+// The tile of this workgroup (XCD-aware order) and the lane's voxel within
+// its structure; false for lanes past the structure's last voxel and for
+// the padding workgroups of the grid.
+__device__ __forceinline__ bool batch_lane(const BatchTile* __restrict__ tiles, int64_t ntiles,
+                                           int64_t nblocks_padded, const DevParams* __restrict__ Ps,
+                                           BatchTile& t, const DevParams*& P, int64_t& e) {
+  const int64_t blk = xcd_block(nblocks_padded);
+  if (blk >= ntiles) return false;
+  t = tiles[blk];
+  P = Ps + t.s;
+  e = int64_t(t.v0) + (threadIdx.x >> 3);
+  return e < P->Ne;
+}
+
+template <typename S>
+__device__ __forceinline__ const S* shift(const S* p, int64_t o) { return p ? p + o : p; }
+
+template <typename S, typename N, int Mode>
+__device__ __forceinline__ void q1_batch_body(const S* __restrict__ U, const S* __restrict__ V,
+                                              const S* __restrict__ M, S* __restrict__ Out,
+                                              const uint8_t* __restrict__ phase,
+                                              const DevParams* __restrict__ Ps,
+                                              const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS,
+                                              int64_t nblocks_padded) {
+  BatchTile t;
+  const DevParams* P;
+  int64_t e;
+  if (!batch_lane(tiles, ntiles, nblocks_padded, Ps, t, P, e)) return;
+  const int64_t o = t.base * 8;
+  q1_node<S, N, Mode>(U + o, shift(V, o), shift(M, o), Out + o, phase + t.base, *P, e, int(threadIdx.x & 7), FS);
+}
+
+template <typename S, typename N, int Mode>
+__global__ void __launch_bounds__(256)
+q1_batch_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M, S* __restrict__ Out,
+                const uint8_t* __restrict__ phase, const DevParams* __restrict__ Ps,
+                const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS, int64_t nblocks_padded) {
+  q1_batch_body<S, N, Mode>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded);
+}
+
+// As q1_kernel_w2: the FP32 tangent held to two waves per SIMD.
+template <typename S, typename N, int Mode>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+q1_batch_kernel_w2(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
+                   S* __restrict__ Out, const uint8_t* __restrict__ phase, const DevParams* __restrict__ Ps,
+                   const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS, int64_t nblocks_padded) {
+  q1_batch_body<S, N, Mode>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded);
+}
+
+// Element blocks of every structure (Bout: E blocks of nb x nb).
+template <typename S, int Mode>
+__global__ void __launch_bounds__(256)
+q1_block_batch_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict__ Bout,
+                      const uint8_t* __restrict__ phase, const DevParams* __restrict__ Ps,
+                      const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS, int64_t nblocks_padded) {
+  constexpr int NB = (Mode == kJvpFull) ? 72 : 56;
+  BatchTile t;
+  const DevParams* P;
+  int64_t e;
+  if (!batch_lane(tiles, ntiles, nblocks_padded, Ps, t, P, e)) return;
+  const int64_t o = t.base * 8;
+  q1_block_node<S, Mode>(U + o, Cw + o, Bout + t.base * int64_t(NB) * NB, phase + t.base, *P, e,
+                         int(threadIdx.x & 7), FS);
+}
+
+// Linearisation coefficients of the condensed tangent (14 x E x 8).
+template <typename S>
+__global__ void __launch_bounds__(256)
+solid_tangent_batch_kernel(const S* __restrict__ U, S* __restrict__ Cw, const uint8_t* __restrict__ phase,
+                           const DevParams* __restrict__ Ps, const BatchTile* __restrict__ tiles,
+                           int64_t ntiles, int64_t FS, int64_t nblocks_padded) {
+  BatchTile t;
+  const DevParams* P;
+  int64_t e;
+  if (!batch_lane(tiles, ntiles, nblocks_padded, Ps, t, P, e)) return;
+  const int64_t o = t.base * 8;
+  solid_tangent_node(U + o, Cw + o, int(phase[t.base + e]), *P, e * 8 + (threadIdx.x & 7), FS);
+}
+
+// Old mass of every structure: m[i] = eps_L c_i (i < 6), m[6 + s] = eps_s.
+template <typename T>
+__global__ void __launch_bounds__(256)
+mass_batch_kernel(const T* __restrict__ U, T* __restrict__ M, const uint8_t* __restrict__ phase,
+                  const DevParams* __restrict__ Ps, const BatchTile* __restrict__ tiles, int64_t ntiles,
+                  int64_t FS, int64_t nblocks_padded) {
+  BatchTile t;
+  const DevParams* P;
+  int64_t e;
+  if (!batch_lane(tiles, ntiles, nblocks_padded, Ps, t, P, e)) return;
+  const int64_t g = (t.base + e) * 8 + (threadIdx.x & 7);
+  const int ph = phase[t.base + e];
+  const T e7 = U[7 * FS + g], e8 = U[8 * FS + g];
+  const T eL = liquid_fraction(T(P->epsCBD[ph]), e7, e8, T(P->epsL_min));
+#pragma unroll
+  for (int i = 0; i < 6; ++i) M[i * FS + g] = eL * U[i * FS + g];
+  M[6 * FS + g] = e7;
+  M[7 * FS + g] = e8;
+}
+
+}  // namespace lsbdg

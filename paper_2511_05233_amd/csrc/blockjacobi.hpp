@@ -46,20 +46,15 @@ __device__ __forceinline__ double bcast(double x, int lane) {
 // Element-diagonal blocks.  Mode kJvpFull (9 fields, nb = 72) or
 // kJvpCondensed (7 fields, nb = 56).  One lane per node, as q1_kernel.
 // Cw: linearisation coefficients at U (kJvpCondensed).
+// Node n's rows of voxel e's block (e < P.Ne; field stride FS; the arrays,
+// the phase map and Bout start at the structure's first voxel).
 template <typename S, int Mode>
-__global__ void __launch_bounds__(256)
-q1_block_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict__ Bout,
-                const uint8_t* __restrict__ phase, DevParams P, int64_t nblocks_padded) {
+__device__ __forceinline__ void q1_block_node(const S* __restrict__ U, const S* __restrict__ Cw,
+                                              S* __restrict__ Bout, const uint8_t* __restrict__ phase,
+                                              const DevParams& P, int64_t e, int n, int64_t FS) {
   using N = Dual<S>;
   constexpr int NF = (Mode == kJvpFull) ? 9 : 7;
   constexpr int NB = NF * 8;
-  const int64_t blk = xcd_block(nblocks_padded);
-  const int64_t gid = blk * 256 + threadIdx.x;
-  const int64_t Ne = P.Ne;
-  const int64_t e = gid >> 3;
-  if (e >= Ne) return;
-  const int n = int(gid & 7);
-  const int64_t FS = Ne * 8;
   const int ix = int(e % P.nx);
   const int iy = int((e / P.nx) % P.ny);
   const int iz = int(e / (int64_t(P.nx) * P.ny));
@@ -122,6 +117,17 @@ q1_block_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict
       }
     }
   }
+}
+
+template <typename S, int Mode>
+__global__ void __launch_bounds__(256)
+q1_block_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __restrict__ Bout,
+                const uint8_t* __restrict__ phase, DevParams P, int64_t nblocks_padded) {
+  const int64_t blk = xcd_block(nblocks_padded);
+  const int64_t gid = blk * 256 + threadIdx.x;
+  const int64_t e = gid >> 3;
+  if (e >= P.Ne) return;
+  q1_block_node<S, Mode>(U, Cw, Bout, phase, P, e, int(gid & 7), P.Ne * 8);
 }
 
 // Entry (row, col) of a block in the column-quad storage.

@@ -9,8 +9,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <atomic>
 #include <new>
+#include <numeric>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -22,6 +26,7 @@
 #include "solver.hpp"
 #include "outputs.hpp"
 #include "coarse.hpp"
+#include "batch.hpp"
 
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -739,6 +744,99 @@ int solve_once(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_op
 
 }  // namespace
 
+// A batch of independent structures: one context per structure for its
+// derived parameters, plus the concatenated device tables of the batch.
+struct dg_batch {
+  std::vector<dg_ctx*> subs;
+  std::vector<int64_t> off;            // voxel offsets, n + 1 values
+  int64_t E = 0;                       // total voxels
+  int64_t ntiles = 0;
+  uint8_t* d_phase = nullptr;
+  BatchTile* d_tiles = nullptr;
+  DevParams* d_params = nullptr;
+  DevParams* h_params = nullptr;       // pinned staging of d_params
+  hipEvent_t staged = nullptr;         // recorded after each upload of h_params
+  DevBuf lin, blocks, status;
+  int lin_prec = -1, blocks_prec = -1;
+  std::vector<DevBuf> wstate;          // per-worker contiguous states (batched solves)
+};
+
+namespace {
+
+// Per-structure parameter blocks at (t_new[s], dt[s]) (mass: at t = 0,
+// without a step) to the device, on the stream of the call that reads them.
+int batch_params(dg_batch* b, const double* t_new, const double* dt, bool step, hipStream_t st,
+                 const char* fn) {
+  const int n = int(b->subs.size());
+  if (step) {
+    if (!t_new || !dt) return fail(DG_EINVAL, std::string(fn) + ": null t_new or dt");
+    for (int s = 0; s < n; ++s)
+      if (!(dt[s] > 0)) return fail(DG_EINVAL, std::string(fn) + ": dt[" + std::to_string(s) + "] must be positive");
+  }
+  DG_HIP(hipEventSynchronize(b->staged));   // the previous upload has left the staging buffer
+  for (int s = 0; s < n; ++s)
+    b->h_params[s] = make_params(b->subs[s], step ? t_new[s] : 0.0, step ? dt[s] : 0.0);
+  DG_HIP(hipMemcpyAsync(b->d_params, b->h_params, size_t(n) * sizeof(DevParams), hipMemcpyHostToDevice, st));
+  DG_HIP(hipEventRecord(b->staged, st));
+  return DG_OK;
+}
+
+int64_t batch_grid(const dg_batch* b) { return (b->ntiles + 7) / 8 * 8; }
+
+template <typename S, typename N, int Mode>
+void launch_q1_batch(const dg_batch* b, const void* u, const void* v, const void* m, void* out, hipStream_t st) {
+  const int64_t nb = batch_grid(b);
+  const int64_t FS = b->E * 8;
+  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
+  if constexpr (std::is_same<S, float>::value && Mode != kResidual)
+    hipLaunchKernelGGL((q1_batch_kernel_w2<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
+                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), b->d_phase,
+                       b->d_params, b->d_tiles, b->ntiles, FS, nb);
+  else
+    hipLaunchKernelGGL((q1_batch_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
+                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), b->d_phase,
+                       b->d_params, b->d_tiles, b->ntiles, FS, nb);
+}
+
+template <typename S>
+int batch_linearize(dg_batch* b, const S* u, hipStream_t st) {
+  const int64_t FS = b->E * 8;
+  hipError_t e = b->lin.ensure(size_t(14) * FS * sizeof(S));
+  if (e != hipSuccess) return fail(DG_ENOMEM, std::string("batch linearisation storage: ") + hipGetErrorString(e));
+  const int64_t nb = batch_grid(b);
+  hipLaunchKernelGGL(solid_tangent_batch_kernel<S>, dim3(unsigned(nb)), dim3(256), 0, st, u, b->lin.as<S>(),
+                     b->d_phase, b->d_params, b->d_tiles, b->ntiles, FS, nb);
+  DG_HIP(hipGetLastError());
+  b->lin_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  return DG_OK;
+}
+
+template <typename S>
+int batch_blocks(dg_batch* b, const S* u, hipStream_t st) {
+  if (int s = batch_linearize<S>(b, u, st)) return s;
+  const size_t need = size_t(b->E) * 56 * 56 * sizeof(S);
+  hipError_t e = b->blocks.ensure(need);
+  if (e != hipSuccess) return fail(DG_ENOMEM, std::string("batch block storage: ") + hipGetErrorString(e));
+  e = b->status.ensure(sizeof(int));
+  if (e != hipSuccess) return fail(DG_ENOMEM, "batch status allocation");
+  DG_HIP(hipMemsetAsync(b->status.p, 0, sizeof(int), st));
+  const int64_t nb = batch_grid(b);
+  hipLaunchKernelGGL((q1_block_batch_kernel<S, kJvpCondensed>), dim3(unsigned(nb)), dim3(256), 0, st, u,
+                     b->lin.as<S>(), b->blocks.as<S>(), b->d_phase, b->d_params, b->d_tiles, b->ntiles,
+                     b->E * 8, nb);
+  hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), dim3(unsigned((b->E + 3) / 4)), dim3(256), 0, st,
+                     b->blocks.as<S>(), b->E, b->status.as<int>());
+  DG_HIP(hipGetLastError());
+  int h_status = 0;
+  DG_HIP(hipMemcpyAsync(&h_status, b->status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipStreamSynchronize(st));
+  b->blocks_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  if (h_status) return fail(DG_ENAN, "dg_batch_blockjacobi_setup: singular or non-finite element block");
+  return DG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void dg_params_default(dg_params* p) {
@@ -1262,6 +1360,337 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
     return fail(DG_ENOMEM, "dg_advance: host allocation failed");
   } catch (...) {
     return fail(DG_EINVAL, "dg_advance: unexpected exception");
+  }
+}
+
+int dg_batch_destroy(dg_batch* b) {
+  if (!b) return DG_OK;
+  for (dg_ctx* c : b->subs) dg_destroy(c);
+  if (b->d_phase) (void)hipFree(b->d_phase);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_params) (void)hipFree(b->d_params);
+  if (b->staged) {
+    (void)hipEventSynchronize(b->staged);
+    (void)hipEventDestroy(b->staged);
+  }
+  if (b->h_params) (void)hipHostFree(b->h_params);
+  b->lin.release();
+  b->blocks.release();
+  b->status.release();
+  for (DevBuf& w : b->wstate) w.release();
+  delete b;
+  return DG_OK;
+}
+
+int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phases, const dg_params* params,
+                   dg_batch** out) {
+  try {
+    if (!out) return fail(DG_EINVAL, "dg_batch_setup: null argument");
+    *out = nullptr;
+    if (n < 1 || !meshes || !phases || !params)
+      return fail(DG_EINVAL, "dg_batch_setup: null argument or fewer than one structure");
+    dg_batch* b = new dg_batch;
+    auto abandon = [&](int code) {
+      dg_batch_destroy(b);
+      return code;
+    };
+    b->off.push_back(0);
+    for (int s = 0; s < n; ++s) {
+      if (!phases[s])
+        return abandon(fail(DG_EINVAL, "dg_batch_setup: null phase map of structure " + std::to_string(s)));
+      dg_ctx* c = nullptr;
+      if (int code = dg_setup(&meshes[s], phases[s], &params[s], &c)) {
+        const std::string why = g_last_error;
+        return abandon(fail(code, "dg_batch_setup: structure " + std::to_string(s) + ": " + why));
+      }
+      b->subs.push_back(c);
+      if (c->Ne > int64_t(INT32_MAX))
+        return abandon(fail(DG_EINVAL, "dg_batch_setup: structure " + std::to_string(s) + " has more than 2^31 voxels"));
+      b->off.push_back(b->off.back() + c->Ne);
+    }
+    b->E = b->off.back();
+    std::vector<BatchTile> tiles;
+    for (int s = 0; s < n; ++s)
+      for (int64_t v0 = 0; v0 < b->subs[s]->Ne; v0 += kTileVoxels)
+        tiles.push_back(BatchTile{int32_t(s), int32_t(v0), b->off[s]});
+    b->ntiles = int64_t(tiles.size());
+    hipError_t e = hipMalloc(&b->d_phase, size_t(b->E));
+    if (e == hipSuccess) e = hipMalloc(&b->d_tiles, tiles.size() * sizeof(BatchTile));
+    if (e == hipSuccess) e = hipMalloc(&b->d_params, size_t(n) * sizeof(DevParams));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_params, size_t(n) * sizeof(DevParams));
+    if (e != hipSuccess) return abandon(fail(DG_ENOMEM, std::string("dg_batch_setup: ") + hipGetErrorString(e)));
+    e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    for (int s = 0; s < n && e == hipSuccess; ++s)
+      e = hipMemcpy(b->d_phase + b->off[s], phases[s], size_t(b->subs[s]->Ne), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return abandon(fail(DG_EHIP, std::string("dg_batch_setup: ") + hipGetErrorString(e)));
+    *out = b;
+    return DG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_batch_setup: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_batch_setup: unexpected exception");
+  }
+}
+
+int dg_batch_layout(const dg_batch* b, int64_t* offsets, int64_t* n_tiles) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_layout: null batch");
+  if (offsets)
+    for (size_t i = 0; i < b->off.size(); ++i) offsets[i] = b->off[i];
+  if (n_tiles) *n_tiles = b->ntiles;
+  return DG_OK;
+}
+
+int dg_batch_mass(dg_batch* b, dg_prec prec, const void* u, void* m, dg_stream stream) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_mass: null batch");
+  if (!u || !m) return fail(DG_EINVAL, "dg_batch_mass: null array");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_mass: bad precision");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = batch_params(b, nullptr, nullptr, false, st, "dg_batch_mass")) return s;
+  const int64_t nb = batch_grid(b);
+  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
+  if (prec == DG_F64)
+    hipLaunchKernelGGL(mass_batch_kernel<double>, grid, block, 0, st, static_cast<const double*>(u),
+                       static_cast<double*>(m), b->d_phase, b->d_params, b->d_tiles, b->ntiles, b->E * 8, nb);
+  else
+    hipLaunchKernelGGL(mass_batch_kernel<float>, grid, block, 0, st, static_cast<const float*>(u),
+                       static_cast<float*>(m), b->d_phase, b->d_params, b->d_tiles, b->ntiles, b->E * 8, nb);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_batch_residual(dg_batch* b, dg_prec prec, const void* u, const void* m_old, const double* t_new,
+                      const double* dt, void* r, dg_stream stream) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_residual: null batch");
+  if (!u || !m_old || !r) return fail(DG_EINVAL, "dg_batch_residual: null array");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_residual: bad precision");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_residual")) return s;
+  if (prec == DG_F64)
+    launch_q1_batch<double, double, kResidual>(b, u, nullptr, m_old, r, st);
+  else
+    launch_q1_batch<float, float, kResidual>(b, u, nullptr, m_old, r, st);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_batch_linearize(dg_batch* b, dg_prec prec, const void* u, const double* t_new, const double* dt,
+                       dg_stream stream) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_linearize: null batch");
+  if (!u) return fail(DG_EINVAL, "dg_batch_linearize: null array");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_linearize: bad precision");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_linearize")) return s;
+  return prec == DG_F64 ? batch_linearize<double>(b, static_cast<const double*>(u), st)
+                        : batch_linearize<float>(b, static_cast<const float*>(u), st);
+}
+
+int dg_batch_jvp(dg_batch* b, dg_prec prec, dg_jvp_mode mode, const void* u, const void* v,
+                 const double* t_new, const double* dt, void* jv, dg_stream stream) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_jvp: null batch");
+  if (!u || !v || !jv) return fail(DG_EINVAL, "dg_batch_jvp: null array");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_jvp: bad precision");
+  if (mode != DG_JVP_FULL9 && mode != DG_JVP_CONDENSED7 && mode != DG_JVP_LINEARIZED7)
+    return fail(DG_EINVAL, "dg_batch_jvp: bad mode");
+  if (mode == DG_JVP_LINEARIZED7 && b->lin_prec != int(prec))
+    return fail(DG_ESTATE, "dg_batch_jvp: no batch linearisation of this precision (dg_batch_linearize)");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_jvp")) return s;
+  if (mode == DG_JVP_FULL9) {
+    if (prec == DG_F64)
+      launch_q1_batch<double, Dual<double>, kJvpFull>(b, u, v, nullptr, jv, st);
+    else
+      launch_q1_batch<float, Dual<float>, kJvpFull>(b, u, v, nullptr, jv, st);
+  } else {
+    if (mode == DG_JVP_CONDENSED7) {
+      const int s = prec == DG_F64 ? batch_linearize<double>(b, static_cast<const double*>(u), st)
+                                   : batch_linearize<float>(b, static_cast<const float*>(u), st);
+      if (s) return s;
+    }
+    if (prec == DG_F64)
+      launch_q1_batch<double, Dual<double>, kJvpCondensed>(b, u, v, b->lin.p, jv, st);
+    else
+      launch_q1_batch<float, Dual<float>, kJvpCondensed>(b, u, v, b->lin.p, jv, st);
+  }
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_batch_blockjacobi_setup(dg_batch* b, dg_prec prec, const void* u, const double* t_new,
+                               const double* dt, dg_stream stream) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_blockjacobi_setup: null batch");
+  if (!u) return fail(DG_EINVAL, "dg_batch_blockjacobi_setup: null array");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_blockjacobi_setup: bad precision");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_blockjacobi_setup")) return s;
+  return prec == DG_F64 ? batch_blocks<double>(b, static_cast<const double*>(u), st)
+                        : batch_blocks<float>(b, static_cast<const float*>(u), st);
+}
+
+int dg_batch_blockjacobi_apply(dg_batch* b, dg_prec prec, const void* x, void* y, dg_stream stream) {
+  if (!b) return fail(DG_EINVAL, "dg_batch_blockjacobi_apply: null batch");
+  if (!x || !y) return fail(DG_EINVAL, "dg_batch_blockjacobi_apply: null array");
+  if (b->blocks_prec < 0) return fail(DG_ESTATE, "dg_batch_blockjacobi_apply: no setup yet");
+  if (int(prec) != b->blocks_prec)
+    return fail(DG_EINVAL, "dg_batch_blockjacobi_apply: precision differs from the setup");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid{unsigned((b->E + 3) / 4), 1, 1}, block{256, 1, 1};
+  if (prec == DG_F64)
+    hipLaunchKernelGGL((apply_blocks_kernel<double, 7>), grid, block, 0, st, b->blocks.as<const double>(),
+                       static_cast<const double*>(x), static_cast<double*>(y), b->E);
+  else
+    hipLaunchKernelGGL((apply_blocks_kernel<float, 7>), grid, block, 0, st, b->blocks.as<const float>(),
+                       static_cast<const float*>(x), static_cast<float*>(y), b->E);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Run job(s, worker, stream) for every structure of the batch on `workers`
+// host threads, each with a HIP stream of its own and default priority:
+// the structures' Newton solves are independent, and their host-driven
+// control flow (convergence tests, line searches, restarts) diverges, so
+// they proceed side by side rather than in lock step.  Structures are
+// taken largest first.  Every job runs; the first failing structure (in
+// structure order) gives the return status and message.
+template <typename Job>
+int batch_run(dg_batch* b, int workers, const char* fn, Job job) {
+  const int n = int(b->subs.size());
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->subs[x]->Ne > b->subs[y]->Ne; });
+  int dev = 0;
+  DG_HIP(hipGetDevice(&dev));
+  std::vector<hipStream_t> streams(workers, nullptr);
+  for (int w = 0; w < workers; ++w) {
+    hipError_t e = hipStreamCreate(&streams[w]);
+    if (e != hipSuccess) {
+      for (int v = 0; v < w; ++v) (void)hipStreamDestroy(streams[v]);
+      return fail(DG_EHIP, std::string(fn) + ": hipStreamCreate: " + hipGetErrorString(e));
+    }
+  }
+  std::vector<int> status(n, DG_OK);
+  std::vector<std::string> msg(n);
+  std::atomic<int> next{0};
+  auto work = [&](int w) {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      const int s = order[k];
+      try {
+        status[s] = job(s, w, streams[w]);
+      } catch (...) {
+        status[s] = fail(DG_EINVAL, "unexpected exception");
+      }
+      if (status[s]) msg[s] = g_last_error;   // this worker's thread-local message
+    }
+    (void)hipStreamSynchronize(streams[w]);
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < workers; ++w) {
+    try {
+      pool.emplace_back(work, w);
+    } catch (...) {
+      break;   // fewer threads: the shared counter hands their structures to the others
+    }
+  }
+  work(0);
+  for (auto& t : pool) t.join();
+  for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+  for (int s = 0; s < n; ++s)
+    if (status[s]) return fail(status[s], std::string(fn) + ": structure " + std::to_string(s) + ": " + msg[s]);
+  return DG_OK;
+}
+
+// Per-worker contiguous state of the largest structure (9 fields, FP64).
+int batch_state_buffers(dg_batch* b, int workers, const char* fn) {
+  int64_t max_ne = 0;
+  for (dg_ctx* c : b->subs) max_ne = std::max(max_ne, c->Ne);
+  if (int(b->wstate.size()) < workers) b->wstate.resize(workers);
+  for (int w = 0; w < workers; ++w) {
+    hipError_t e = b->wstate[w].ensure(size_t(9) * max_ne * 8 * sizeof(double));
+    if (e != hipSuccess) return fail(DG_ENOMEM, std::string(fn) + ": state buffers: " + hipGetErrorString(e));
+  }
+  return DG_OK;
+}
+
+// Structure s's slice of a batch state (field stride E * 8) to or from a
+// contiguous 9 x Ne_s x 8 state.
+hipError_t batch_copy(const dg_batch* b, int s, double* batch_u, double* own, bool to_own, hipStream_t st) {
+  const size_t row = size_t(b->subs[s]->Ne) * 8 * sizeof(double);
+  const size_t pitch = size_t(b->E) * 8 * sizeof(double);
+  double* slice = batch_u + b->off[s] * 8;
+  return to_own ? hipMemcpy2DAsync(own, row, slice, pitch, row, 9, hipMemcpyDeviceToDevice, st)
+                : hipMemcpy2DAsync(slice, pitch, own, row, row, 9, hipMemcpyDeviceToDevice, st);
+}
+
+int batch_workers(const dg_batch* b, int32_t workers) {
+  const int n = int(b->subs.size());
+  int w = workers > 0 ? workers : 4;
+  return std::max(1, std::min(w, n));
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_batch_initial_state(dg_batch* b, const double* t0, void* u, const dg_solver_opts* opts,
+                           dg_step_report* reports, int32_t workers, dg_stream stream) {
+  try {
+    if (!b) return fail(DG_EINVAL, "dg_batch_initial_state: null batch");
+    if (!t0 || !u) return fail(DG_EINVAL, "dg_batch_initial_state: null t0 or state");
+    const int nw = batch_workers(b, workers);
+    if (int s = batch_state_buffers(b, nw, "dg_batch_initial_state")) return s;
+    DG_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    double* bu = static_cast<double*>(u);
+    return batch_run(b, nw, "dg_batch_initial_state", [&](int s, int w, hipStream_t st) -> int {
+      double* own = b->wstate[w].as<double>();
+      dg_step_report rep{};
+      const int code = dg_initial_state(b->subs[s], t0[s], own, opts, &rep, st);
+      if (reports) reports[s] = rep;
+      if (code) return code;
+      DG_HIP(batch_copy(b, s, bu, own, false, st));
+      DG_HIP(hipStreamSynchronize(st));
+      return DG_OK;
+    });
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_batch_initial_state: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_batch_initial_state: unexpected exception");
+  }
+}
+
+int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, const dg_solver_opts* opts,
+                  dg_step_report* reports, int32_t workers, dg_stream stream) {
+  try {
+    if (!b) return fail(DG_EINVAL, "dg_batch_step: null batch");
+    if (!t_n || !dt || !u) return fail(DG_EINVAL, "dg_batch_step: null t_n, dt or state");
+    for (size_t s = 0; s < b->subs.size(); ++s)
+      if (!(dt[s] > 0)) return fail(DG_EINVAL, "dg_batch_step: dt[" + std::to_string(s) + "] must be positive");
+    const int nw = batch_workers(b, workers);
+    if (int s = batch_state_buffers(b, nw, "dg_batch_step")) return s;
+    DG_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    double* bu = static_cast<double*>(u);
+    return batch_run(b, nw, "dg_batch_step", [&](int s, int w, hipStream_t st) -> int {
+      double* own = b->wstate[w].as<double>();
+      DG_HIP(batch_copy(b, s, bu, own, true, st));
+      dg_step_report rep{};
+      const int code = dg_step(b->subs[s], t_n[s], dt[s], own, opts, &rep, st);
+      if (reports) reports[s] = rep;
+      // the last iterate goes back on failure too, as dg_step leaves it in u
+      DG_HIP(batch_copy(b, s, bu, own, false, st));
+      DG_HIP(hipStreamSynchronize(st));
+      return code;
+    });
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_batch_step: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_batch_step: unexpected exception");
   }
 }
 

@@ -139,45 +139,49 @@ __device__ __forceinline__ S solid_tangent_row(const S* __restrict__ Cw, int row
 // fractions, get C = 0.  Once per linearisation point; every condensed
 // tangent at that point then costs at most two 7-term products per node.
 template <typename S>
+__device__ __forceinline__ void solid_tangent_node(const S* __restrict__ U, S* __restrict__ Cw, int ph,
+                                                   const DevParams& P, int64_t k, int64_t FS) {
+  if (P.react[ph] == 0.0 || !(P.active & kSolidsBit)) {
+#pragma unroll
+    for (int j = 0; j < 14; ++j) Cw[j * FS + k] = S(0);
+    return;
+  }
+  using D = Dual<S>;
+  D x[9], Sx[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) x[f] = D(U[f * FS + k], S(0));
+  x[7].d = S(1);
+  node_sources(P, ph, x, Sx);
+  const S c70 = Sx[7].d, c80 = Sx[8].d;
+  x[7].d = S(0);
+  x[8].d = S(1);
+  node_sources(P, ph, x, Sx);
+  const S c71 = Sx[7].d, c81 = Sx[8].d;
+  x[8].d = S(0);
+  const S idt = S(P.inv_dt);
+  const S a00 = S(P.rhoM[0]) * idt - c70, a01 = -c71;
+  const S a10 = -c80, a11 = S(P.rhoM[1]) * idt - c81;
+  const S det = a00 * a11 - a01 * a10;
+#pragma unroll 1
+  for (int j = 0; j < 7; ++j) {
+    x[j].d = S(1);
+    node_sources(P, ph, x, Sx);
+    x[j].d = S(0);
+    const S t7 = Sx[7].d, t8 = Sx[8].d;
+    const S w0 = (a11 * t7 - a01 * t8) / det;
+    const S w1 = (a00 * t8 - a10 * t7) / det;
+    Cw[j * FS + k] = w0;
+    Cw[(7 + j) * FS + k] = w0 + w1;
+  }
+}
+
+template <typename S>
 __global__ void __launch_bounds__(256)
 solid_tangent_kernel(const S* __restrict__ U, S* __restrict__ Cw, const uint8_t* __restrict__ phase,
                      DevParams P) {
   const int64_t FS = P.Ne * 8;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
-    const int ph = phase[k >> 3];
-    if (P.react[ph] == 0.0 || !(P.active & kSolidsBit)) {
-#pragma unroll
-      for (int j = 0; j < 14; ++j) Cw[j * FS + k] = S(0);
-      continue;
-    }
-    using D = Dual<S>;
-    D x[9], Sx[9];
-#pragma unroll
-    for (int f = 0; f < 9; ++f) x[f] = D(U[f * FS + k], S(0));
-    x[7].d = S(1);
-    node_sources(P, ph, x, Sx);
-    const S c70 = Sx[7].d, c80 = Sx[8].d;
-    x[7].d = S(0);
-    x[8].d = S(1);
-    node_sources(P, ph, x, Sx);
-    const S c71 = Sx[7].d, c81 = Sx[8].d;
-    x[8].d = S(0);
-    const S idt = S(P.inv_dt);
-    const S a00 = S(P.rhoM[0]) * idt - c70, a01 = -c71;
-    const S a10 = -c80, a11 = S(P.rhoM[1]) * idt - c81;
-    const S det = a00 * a11 - a01 * a10;
-#pragma unroll 1
-    for (int j = 0; j < 7; ++j) {
-      x[j].d = S(1);
-      node_sources(P, ph, x, Sx);
-      x[j].d = S(0);
-      const S t7 = Sx[7].d, t8 = Sx[8].d;
-      const S w0 = (a11 * t7 - a01 * t8) / det;
-      const S w1 = (a00 * t8 - a10 * t7) / det;
-      Cw[j * FS + k] = w0;
-      Cw[(7 + j) * FS + k] = w0 + w1;
-    }
-  }
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256)
+    solid_tangent_node(U, Cw, int(phase[k >> 3]), P, k, FS);
 }
 
 // Load the nine unknowns of one node as operator numbers (Cw: the
@@ -355,18 +359,13 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
 // and 2, N = Dual<S>, output = derivative part).  M: the old mass
 // (residual) or the linearisation coefficients of solid_tangent_kernel
 // (condensed tangent); unused otherwise.
+// Rows of node n of voxel e (e < P.Ne) with field stride FS; the arrays and
+// the phase map start at the structure's first voxel.
 template <typename S, typename N, int Mode>
-__device__ __forceinline__ void q1_body(const S* __restrict__ U, const S* __restrict__ V,
+__device__ __forceinline__ void q1_node(const S* __restrict__ U, const S* __restrict__ V,
                                         const S* __restrict__ M, S* __restrict__ Out,
                                         const uint8_t* __restrict__ phase, const DevParams& P,
-                                        int64_t nblocks_padded) {
-  const int64_t blk = xcd_block(nblocks_padded);
-  const int64_t gid = blk * 256 + threadIdx.x;
-  const int64_t Ne = P.Ne;
-  const int64_t e = gid >> 3;
-  if (e >= Ne) return;                       // whole 8-lane groups leave together
-  const int n = int(gid & 7);
-  const int64_t FS = Ne * 8;                 // field stride
+                                        int64_t e, int n, int64_t FS) {
   const int ix = int(e % P.nx);
   const int iy = int((e / P.nx) % P.ny);
   const int iz = int(e / (int64_t(P.nx) * P.ny));
@@ -385,6 +384,18 @@ __device__ __forceinline__ void q1_body(const S* __restrict__ U, const S* __rest
       Out[f * FS + e * 8 + n] = on ? deriv_of(r[f]) : S(0);
     }
   }
+}
+
+template <typename S, typename N, int Mode>
+__device__ __forceinline__ void q1_body(const S* __restrict__ U, const S* __restrict__ V,
+                                        const S* __restrict__ M, S* __restrict__ Out,
+                                        const uint8_t* __restrict__ phase, const DevParams& P,
+                                        int64_t nblocks_padded) {
+  const int64_t blk = xcd_block(nblocks_padded);
+  const int64_t gid = blk * 256 + threadIdx.x;
+  const int64_t e = gid >> 3;
+  if (e >= P.Ne) return;                     // whole 8-lane groups leave together
+  q1_node<S, N, Mode>(U, V, M, Out, phase, P, e, int(gid & 7), P.Ne * 8);
 }
 
 template <typename S, typename N, int Mode>

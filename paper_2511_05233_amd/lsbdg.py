@@ -46,6 +46,22 @@ _SIGNATURES = {
     "dg_controller_init": (None, [C.c_void_p, C.c_int32, C.c_double, C.c_double]),
     "dg_advance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
+    "dg_batch_setup": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dg_batch_destroy": (C.c_int, [C.c_void_p]),
+    "dg_batch_layout": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_batch_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_batch_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    "dg_batch_linearize": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_batch_jvp": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p]),
+    "dg_batch_blockjacobi_setup": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p]),
+    "dg_batch_blockjacobi_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_batch_initial_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                         C.c_void_p]),
+    "dg_batch_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int32, C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -171,6 +187,40 @@ def default_params():
     return p
 
 
+def _solver_opts(inner, opts):
+    """dg_solver_opts: library defaults, the inner precision, then opts."""
+    o = DgSolverOpts()
+    load().dg_solver_opts_default(C.byref(o))
+    o.inner_prec = DG_F32 if inner == "f32" else DG_F64
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solver option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def make_params(D0=None, kE=None, f_C=None, j_el=None, eps_struct=None, sigma=None, use_TH=None, T=None):
+    """dg_params: the paper's defaults with the given entries replaced."""
+    p = default_params()
+    if D0 is not None:
+        p.D0[:] = [float(x) for x in D0]
+    if kE is not None:
+        p.kE[:] = [float(x) for x in kE]
+    if f_C is not None:
+        p.f_C = float(f_C)
+    if j_el is not None:
+        p.j_el = float(j_el)
+    if eps_struct is not None:
+        p.eps_struct = float(eps_struct)
+    if sigma is not None:
+        p.sigma = float(sigma)
+    if use_TH is not None:
+        p.use_TH = int(bool(use_TH))
+    if T is not None:
+        p.T = float(T)
+    return p
+
+
 class Context:
     """One voxel structure: mesh, phase map and parameters on the device."""
 
@@ -183,23 +233,8 @@ class Context:
         ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8).reshape(-1))
         if ph.size != self.n_elem:
             raise ValueError("phase map size does not match the mesh")
-        p = default_params()
-        if D0 is not None:
-            p.D0[:] = [float(x) for x in D0]
-        if kE is not None:
-            p.kE[:] = [float(x) for x in kE]
-        if f_C is not None:
-            p.f_C = float(f_C)
-        if j_el is not None:
-            p.j_el = float(j_el)
-        if eps_struct is not None:
-            p.eps_struct = float(eps_struct)
-        if sigma is not None:
-            p.sigma = float(sigma)
-        if use_TH is not None:
-            p.use_TH = int(bool(use_TH))
-        if T is not None:
-            p.T = float(T)
+        p = make_params(D0=D0, kE=kE, f_C=f_C, j_el=j_el, eps_struct=eps_struct, sigma=sigma,
+                        use_TH=use_TH, T=T)
         self.params = p
         mesh = DgMesh(self.nx, self.ny, self.nz, self.order, self.h)
         handle = C.c_void_p()
@@ -307,12 +342,7 @@ class Context:
         return out
 
     def _opts(self, inner, opts):
-        o = DgSolverOpts()
-        self._lib.dg_solver_opts_default(C.byref(o))
-        o.inner_prec = DG_F32 if inner == "f32" else DG_F64
-        for k, v in opts.items():
-            setattr(o, k, v)
-        return o
+        return _solver_opts(inner, opts)
 
     def initial_state(self, u=None, t0=0.0, inner="f64", **opts):
         """Equilibrium concentrations plus the steady potential (FP64, 9 fields)."""
@@ -372,3 +402,168 @@ class Context:
             err.report = rep.as_dict()
             raise err
         return tt.value, rep.as_dict()
+
+
+_PARAM_KEYS = ("D0", "kE", "f_C", "j_el", "eps_struct", "sigma", "use_TH", "T")
+
+
+class Batch:
+    """Many voxel structures of uneven size behind one set of launches.
+
+    Arrays concatenate the structures voxel by voxel: shape (nf, E, 8) with
+    structure s in [offsets[s], offsets[s+1]) of the voxel axis.  Times and
+    steps are one value per structure (a scalar is broadcast)."""
+
+    def __init__(self, structures):
+        """structures: sequence of dicts with nx, ny, nz, h, phase and
+        optionally the parameter keys of Context (order 1)."""
+        lib = load()
+        n = len(structures)
+        if n < 1:
+            raise ValueError("a batch needs at least one structure")
+        meshes = (DgMesh * n)()
+        params = (DgParams * n)()
+        ptrs = (C.c_void_p * n)()
+        self._phases = []
+        for i, st in enumerate(structures):
+            nx, ny, nz = int(st["nx"]), int(st["ny"]), int(st["nz"])
+            ph = np.ascontiguousarray(np.asarray(st["phase"], dtype=np.uint8).reshape(-1))
+            if ph.size != nx * ny * nz:
+                raise ValueError(f"structure {i}: phase map size does not match the mesh")
+            self._phases.append(ph)
+            ptrs[i] = ph.ctypes.data
+            meshes[i] = DgMesh(nx, ny, nz, 1, float(st["h"]))
+            params[i] = make_params(**{k: st[k] for k in _PARAM_KEYS if k in st})
+        handle = C.c_void_p()
+        _check("dg_batch_setup", lib.dg_batch_setup(n, meshes, ptrs, params, C.byref(handle)))
+        self._h = handle
+        self._lib = lib
+        self.n = n
+        offs = (C.c_int64 * (n + 1))()
+        nt = C.c_int64()
+        _check("dg_batch_layout", lib.dg_batch_layout(handle, offs, C.byref(nt)))
+        self.offsets = [int(x) for x in offs]
+        self.n_tiles = int(nt.value)
+        self.n_elem = self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def part(self, a, s):
+        """Structure s's slice of a batch array (a view)."""
+        return a[:, self.offsets[s]:self.offsets[s + 1]]
+
+    def _shape(self, nf):
+        return (nf, self.n_elem, 8)
+
+    def _check_arr(self, t, nf):
+        if tuple(t.shape) != self._shape(nf):
+            raise ValueError(f"expected shape {self._shape(nf)}, got {tuple(t.shape)}")
+
+    def _times(self, x):
+        a = np.broadcast_to(np.asarray(x, dtype=np.float64), (self.n,))
+        return np.ascontiguousarray(a)
+
+    def mass(self, u, out=None):
+        import torch
+        self._check_arr(u, 9)
+        if out is None:
+            out = torch.empty(self._shape(8), dtype=u.dtype, device=u.device)
+        self._check_arr(out, 8)
+        _check("dg_batch_mass", self._lib.dg_batch_mass(self._h, _prec(u), _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def residual(self, u, m_old, t_new, dt, out=None):
+        import torch
+        self._check_arr(u, 9)
+        self._check_arr(m_old, 8)
+        if m_old.dtype != u.dtype:
+            raise ValueError("u and m_old must share a dtype")
+        if out is None:
+            out = torch.empty(self._shape(9), dtype=u.dtype, device=u.device)
+        self._check_arr(out, 9)
+        t, d = self._times(t_new), self._times(dt)
+        _check("dg_batch_residual", self._lib.dg_batch_residual(
+            self._h, _prec(u), _ptr(u), _ptr(m_old), t.ctypes.data, d.ctypes.data, _ptr(out), _stream()))
+        return out
+
+    def linearize(self, u, t_new, dt):
+        self._check_arr(u, 9)
+        t, d = self._times(t_new), self._times(dt)
+        _check("dg_batch_linearize", self._lib.dg_batch_linearize(
+            self._h, _prec(u), _ptr(u), t.ctypes.data, d.ctypes.data, _stream()))
+
+    def jvp(self, u, v, t_new, dt, out=None, condensed=False, linearized=False):
+        import torch
+        condensed = condensed or linearized
+        nf = 7 if condensed else 9
+        self._check_arr(u, 9)
+        self._check_arr(v, nf)
+        if v.dtype != u.dtype:
+            raise ValueError("u and v must share a dtype")
+        if out is None:
+            out = torch.empty(self._shape(nf), dtype=u.dtype, device=u.device)
+        self._check_arr(out, nf)
+        mode = DG_JVP_LINEARIZED7 if linearized else (DG_JVP_CONDENSED7 if condensed else DG_JVP_FULL9)
+        t, d = self._times(t_new), self._times(dt)
+        _check("dg_batch_jvp", self._lib.dg_batch_jvp(self._h, _prec(u), mode, _ptr(u), _ptr(v), t.ctypes.data,
+                                                      d.ctypes.data, _ptr(out), _stream()))
+        return out
+
+    def blockjacobi_setup(self, u, t_new, dt):
+        self._check_arr(u, 9)
+        t, d = self._times(t_new), self._times(dt)
+        _check("dg_batch_blockjacobi_setup", self._lib.dg_batch_blockjacobi_setup(
+            self._h, _prec(u), _ptr(u), t.ctypes.data, d.ctypes.data, _stream()))
+
+    def blockjacobi_apply(self, x, out=None):
+        import torch
+        self._check_arr(x, 7)
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_arr(out, 7)
+        _check("dg_batch_blockjacobi_apply", self._lib.dg_batch_blockjacobi_apply(
+            self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def initial_state(self, t0=0.0, inner="f64", workers=4, **opts):
+        """Initial states of every structure (FP64 batch array) and their reports."""
+        import torch
+        u = torch.empty(self._shape(9), dtype=torch.float64, device="cuda:0")
+        o = _solver_opts(inner, opts)
+        reps = (DgStepReport * self.n)()
+        t = self._times(t0)
+        code = self._lib.dg_batch_initial_state(self._h, t.ctypes.data, _ptr(u), C.byref(o), reps, int(workers),
+                                                _stream())
+        out = [r.as_dict() for r in reps]
+        if code != 0:
+            err = DgError("dg_batch_initial_state", code, self._lib.dg_last_error().decode())
+            err.reports = out
+            raise err
+        return u, out
+
+    def step(self, u, t_n, dt, inner="f32", workers=4, **opts):
+        """One backward-Euler step of every structure in place on u; the reports."""
+        import torch
+        self._check_arr(u, 9)
+        if u.dtype != torch.float64:
+            raise ValueError("the step state is FP64")
+        o = _solver_opts(inner, opts)
+        reps = (DgStepReport * self.n)()
+        t, d = self._times(t_n), self._times(dt)
+        code = self._lib.dg_batch_step(self._h, t.ctypes.data, d.ctypes.data, _ptr(u), C.byref(o), reps,
+                                       int(workers), _stream())
+        out = [r.as_dict() for r in reps]
+        if code != 0:
+            err = DgError("dg_batch_step", code, self._lib.dg_last_error().decode())
+            err.reports = out
+            raise err
+        return out

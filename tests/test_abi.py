@@ -82,3 +82,20 @@ def test_binding_structs_match_the_c_compiler(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_batch_setup_rejects_bad_arguments(lib):
+    """Both failures are found before any device call."""
+    import numpy as np
+    out = ctypes.c_void_p()
+    assert lib.dg_batch_setup(0, None, None, None, ctypes.byref(out)) == -1
+    mesh = (lsbdg.DgMesh * 2)(lsbdg.DgMesh(2, 2, 2, 1, 1e-6), lsbdg.DgMesh(2, 2, 2, 1, 1e-6))
+    params = (lsbdg.DgParams * 2)(lsbdg.default_params(), lsbdg.default_params())
+    bad = np.full(8, 2, np.uint8)
+    ptrs = (ctypes.c_void_p * 2)(bad.ctypes.data, bad.ctypes.data)
+    assert lib.dg_batch_setup(2, mesh, ptrs, params, ctypes.byref(out)) == -1
+    assert b"structure 0" in lib.dg_last_error()
+    ptrs = (ctypes.c_void_p * 2)(None, bad.ctypes.data)
+    assert lib.dg_batch_setup(2, mesh, ptrs, params, ctypes.byref(out)) == -1
+    assert b"null phase map of structure 0" in lib.dg_last_error()
+    assert not out.value
