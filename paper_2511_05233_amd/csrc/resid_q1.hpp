@@ -214,6 +214,40 @@ __device__ __forceinline__ void load_node(const S* __restrict__ U, const S* __re
   }
 }
 
+// Face flux from the lower element A to the upper element B at one face
+// point (outward normal +e_d of A), Eq. 45-47: traces ta, tb (9 fields) and
+// normal derivatives ga, gb (7 fields) of both sides; every coefficient is
+// taken from the traced state of its own side and averaged harmonically.
+template <typename T>
+__device__ __forceinline__ void face_flux(const DevParams& P, int phA, int phB, const T* ta, const T* tb,
+                                          const T* ga, const T* gb, T* flux) {
+  const T sigh = T(P.sig_h);
+  const T fa = transport_factor(ta, liquid_fraction(T(P.epsCBD[phA]), ta[7], ta[8], T(P.epsL_min)));
+  const T fb = transport_factor(tb, liquid_fraction(T(P.epsCBD[phB]), tb[7], tb[8], T(P.epsL_min)));
+  const T Hf = harm(fa, fb);
+  const T frt = T(P.frt);
+  const T dphi = ta[6] - tb[6];
+  T lama = T(0), lamb = T(0), sda = T(0), sdb = T(0), pen6 = T(0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const T D0 = T(P.D0[i]);
+    const T z = T(kZ[i]);
+    const T Fa = fa * (ga[i] + z * frt * ta[i] * ga[6]);
+    const T Fb = fb * (gb[i] + z * frt * tb[i] * gb[6]);
+    flux[i] = -T(0.5) * D0 * (Fa + Fb) +
+              sigh * D0 * (Hf * (ta[i] - tb[i]) + z * frt * harm(fa * ta[i], fb * tb[i]) * dphi);
+    lama += T(P.wL[i]) * ta[i];
+    lamb += T(P.wL[i]) * tb[i];
+    sda += T(P.zDA[i]) * ga[i];
+    sdb += T(P.zDA[i]) * gb[i];
+    pen6 += T(P.zDA[i]) * (ta[i] - tb[i]);
+  }
+  const T Fq = T(P.F);
+  const T Ga = fa * Fq * (sda + frt * lama * ga[6]);
+  const T Gb = fb * Fq * (sdb + frt * lamb * gb[6]);
+  flux[6] = -T(0.5) * (Ga + Gb) + sigh * Fq * (Hf * pen6 + frt * harm(fa * lama, fb * lamb) * dphi);
+}
+
 // Rows of the Q1 operator at one node (lane): residual rows (N = S) or their
 // tangents (N = Dual<S>).  u holds the lane's own nine unknowns as N.
 // Neighbour nodes are read from U (and from V in the JVP modes); with
@@ -227,7 +261,7 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
   const T epsCBD = T(P.epsCBD[ph]);
   const T eL = liquid_fraction(epsCBD, u[7], u[8], T(P.epsL_min));
   const T fN = transport_factor(u, eL);
-  const T W3 = T(P.W3), W2 = T(P.W2), sq3h = T(P.sq3_h), sigh = T(P.sig_h);
+  const T W3 = T(P.W3), W2 = T(P.W2), sq3h = T(P.sq3_h);
   const T lam1 = T(kLam1), lam0 = T(kLam0);
   {
     const T idt = T(P.inv_dt);
@@ -309,33 +343,11 @@ __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __rest
         }
       }
       const int phA = hi ? ph : ph2, phB = hi ? ph2 : ph;
-      const T fa = transport_factor(ta, liquid_fraction(T(P.epsCBD[phA]), ta[7], ta[8], T(P.epsL_min)));
-      const T fb = transport_factor(tb, liquid_fraction(T(P.epsCBD[phB]), tb[7], tb[8], T(P.epsL_min)));
-      const T Hf = harm(fa, fb);
-      const T frt = T(P.frt);
-      const T dphi = ta[6] - tb[6];
       const T side = hi ? T(1) : T(-1);          // +flux for A, -flux for B
-      T lama = T(0), lamb = T(0), sda = T(0), sdb = T(0), pen6 = T(0);
+      T flux[7];
+      face_flux(P, phA, phB, ta, tb, ga, gb, flux);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const T D0 = T(P.D0[i]);
-        const T z = T(kZ[i]);
-        const T Fa = fa * (ga[i] + z * frt * ta[i] * ga[6]);
-        const T Fb = fb * (gb[i] + z * frt * tb[i] * gb[6]);
-        const T flux = -T(0.5) * D0 * (Fa + Fb) +
-                       sigh * D0 * (Hf * (ta[i] - tb[i]) + z * frt * harm(fa * ta[i], fb * tb[i]) * dphi);
-        q[i] = side * flux;
-        lama += T(P.wL[i]) * ta[i];
-        lamb += T(P.wL[i]) * tb[i];
-        sda += T(P.zDA[i]) * ga[i];
-        sdb += T(P.zDA[i]) * gb[i];
-        pen6 += T(P.zDA[i]) * (ta[i] - tb[i]);
-      }
-      const T Fq = T(P.F);
-      const T Ga = fa * Fq * (sda + frt * lama * ga[6]);
-      const T Gb = fb * Fq * (sdb + frt * lamb * gb[6]);
-      const T flux6 = -T(0.5) * (Ga + Gb) + sigh * Fq * (Hf * pen6 + frt * harm(fa * lama, fb * lamb) * dphi);
-      q[6] = side * flux6;
+      for (int f = 0; f < 7; ++f) q[f] = side * flux[f];
     } else if (d == 0 && hi) {
       // separator face x = L_x: inward Li+ flux j_el/F and ionic current j_el
       q[0] = -T(P.jel) / T(P.F);
