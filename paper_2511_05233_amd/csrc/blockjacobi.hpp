@@ -65,11 +65,19 @@ __device__ __forceinline__ void q1_block_node(const S* __restrict__ U, const S* 
   S* Be = Bout + e * int64_t(NB) * NB;
   const S W3 = S(P.W3);
 
-  // Columns in the order (field fj, node nj).  The sources are node-local:
-  // a column seeded at node nj reaches this lane's source rows only when
-  // nj == n, through the tangent ks of the lane's own unknown fj (with the
-  // condensed solid-fraction tangent), formed once per field; the column
-  // loop evaluates the spatial terms only.
+  // Columns in the order (field fj, node nj).  Along axis d a node's rows
+  // depend only on the two nodes of its own d-line (volume term: the line
+  // gradient and the node's own state; face term: the traces of that line
+  // at the voxel side, the neighbour's direction being zero), so a node's
+  // rows see only itself and its three line partners n ^ 1, n ^ 2, n ^ 4.
+  // For each field fj and axis d two passes seed the nodes with bit d = 0,
+  // then those with bit d = 1 -- one node of every d-line -- and each lane
+  // reads off its rows' derivative with respect to its own node (seeded) or
+  // its d-partner (not seeded).  The own column accumulates the time term,
+  // the three axes in order and the node-local sources, as the operator
+  // itself does; the partner columns take their single axis.  The sources
+  // are node-local, through the tangent ks of the lane's own unknown fj
+  // (with the condensed solid-fraction tangent), formed once per field.
 #pragma unroll 1
   for (int fj = 0; fj < NF; ++fj) {
     if (!((P.active >> (fj < 7 ? fj : 7)) & 1)) {   // inactive unknown: identity columns
@@ -101,18 +109,52 @@ __device__ __forceinline__ void q1_block_node(const S* __restrict__ U, const S* 
 #pragma unroll
       for (int f = 0; f < NF; ++f) ks[f] = Sx[f].d;
     }
+    S own[NF], nb0[NF], nb1[NF], nb2[NF];
+    {
+      N x[9], r[9];
+#pragma unroll
+      for (int f = 0; f < 9; ++f) x[f] = N(us[f], vo[f]);
+      q1_mass_rows<S, N, kJvpFull>(static_cast<const S*>(nullptr), P, e, n, ph, FS, x, r);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        own[f] = r[f].d;
+        nb0[f] = nb1[f] = nb2[f] = S(0);
+      }
+    }
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll 1
+      for (int s = 0; s < 2; ++s) {
+        const bool seeded = ((n >> d) & 1) == s;
+        N u[9], r[9];
+#pragma unroll
+        for (int f = 0; f < 9; ++f) u[f] = N(us[f], seeded ? vo[f] : S(0));
+        const N eL = liquid_fraction(N(P.epsCBD[ph]), u[7], u[8], N(P.epsL_min));
+        const N fN = transport_factor(u, eL);
+#pragma unroll
+        for (int f = 0; f < 7; ++f) {
+          const S acc = seeded ? own[f] : (d == 0 ? nb0[f] : d == 1 ? nb1[f] : nb2[f]);
+          r[f] = N(S(0), acc);
+        }
+        q1_axis<S, N, kJvpFull, true>(U, nullptr, nullptr, phase, P, e, n, ph, ix, iy, iz, FS, u, fN, d, r);
+#pragma unroll
+        for (int f = 0; f < 7; ++f) {
+          const S v = r[f].d;
+          own[f] = seeded ? v : own[f];
+          nb0[f] = (!seeded && d == 0) ? v : nb0[f];
+          nb1[f] = (!seeded && d == 1) ? v : nb1[f];
+          nb2[f] = (!seeded && d == 2) ? v : nb2[f];
+        }
+      }
+    }
 #pragma unroll 1
     for (int nj = 0; nj < 8; ++nj) {
       const int col = fj * 8 + nj;
-      const bool seeded = (n == nj);
-      N u[9];
-#pragma unroll
-      for (int f = 0; f < 9; ++f) u[f] = N(us[f], seeded ? vo[f] : S(0));
-      N r[9];
-      q1_rows<S, N, kJvpFull, true, false>(U, nullptr, nullptr, phase, P, e, n, ph, ix, iy, iz, FS, u, r);
+      const int x = nj ^ n;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const S val = r[f].d - (seeded ? W3 * ks[f] : S(0));
+        const S val = x == 0 ? own[f] - W3 * ks[f]
+                             : x == 1 ? nb0[f] : x == 2 ? nb1[f] : x == 4 ? nb2[f] : S(0);
         Be[col * NB + f * 8 + n] = ((P.active >> (f < 7 ? f : 7)) & 1) ? val : S(0);
       }
     }

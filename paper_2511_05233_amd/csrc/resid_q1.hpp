@@ -248,114 +248,137 @@ __device__ __forceinline__ void face_flux(const DevParams& P, int phA, int phB, 
   flux[6] = -T(0.5) * (Ga + Gb) + sigh * Fq * (Hf * pen6 + frt * harm(fa * lama, fb * lamb) * dphi);
 }
 
+// Time (mass) rows of node n: W (eps_L c_i - m_i)/dt, W (rho/M)_s (eps_s -
+// m_{6+s})/dt (the old mass m enters the residual only), charge row 0.
+template <typename S, typename N, int Mode>
+__device__ __forceinline__ void q1_mass_rows(const S* __restrict__ M, const DevParams& P, int64_t e, int n,
+                                             int ph, int64_t FS, const N* u, N* r) {
+  using T = N;
+  const T eL = liquid_fraction(T(P.epsCBD[ph]), u[7], u[8], T(P.epsL_min));
+  const T W3 = T(P.W3);
+  const T idt = T(P.inv_dt);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const T mi = (Mode == kResidual) ? T(M[i * FS + e * 8 + n]) : T(0);
+    r[i] = W3 * (eL * u[i] - mi) * idt;
+  }
+  r[6] = T(0);
+  const T m6 = (Mode == kResidual) ? T(M[6 * FS + e * 8 + n]) : T(0);
+  const T m7 = (Mode == kResidual) ? T(M[7 * FS + e * 8 + n]) : T(0);
+  r[7] = W3 * T(P.rhoM[0]) * (u[7] - m6) * idt;
+  r[8] = W3 * T(P.rhoM[1]) * (u[8] - m7) * idt;
+}
+
+// Volume and face terms along axis d of node n's rows (fields 0..6), added
+// to r; fN is the transport factor at the node.  Neighbour nodes are read
+// from U (and from V in the JVP modes); with kNbrZero their direction is
+// zero (element-diagonal Jacobian blocks).
+template <typename S, typename N, int Mode, bool kNbrZero>
+__device__ __forceinline__ void q1_axis(const S* __restrict__ U, const S* __restrict__ V,
+                                        const S* __restrict__ M, const uint8_t* __restrict__ phase,
+                                        const DevParams& P, int64_t e, int n, int ph, int ix, int iy, int iz,
+                                        int64_t FS, const N* u, const N& fN, int d, N* r) {
+  using T = N;
+  const T W3 = T(P.W3), W2 = T(P.W2), sq3h = T(P.sq3_h);
+  const T lam1 = T(kLam1), lam0 = T(kLam0);
+  const int coord = d == 0 ? ix : d == 1 ? iy : iz;
+  const int ncell = d == 0 ? P.nx : d == 1 ? P.ny : P.nz;
+  const int64_t stride = d == 0 ? 1 : d == 1 ? int64_t(P.nx) : int64_t(P.nx) * P.ny;
+
+  const int mask = 1 << d;
+  const bool hi = (n & mask) != 0;
+  const T sgn = hi ? T(1) : T(-1);
+  T up[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) up[f] = xlane(u[f], mask);
+  T g[7];
+#pragma unroll
+  for (int f = 0; f < 7; ++f) g[f] = sq3h * (hi ? u[f] - up[f] : up[f] - u[f]);
+
+  // the face neighbour's two nodes on this lane's line, loaded before the
+  // volume term so the loads overlap it (at a boundary the lane's own
+  // voxel stands in: loaded, never used)
+  const int cn = coord + (hi ? 1 : -1);
+  const bool inside = cn >= 0 && cn < ncell;
+  const int64_t e2 = inside ? e + (hi ? stride : -stride) : e;
+  T vn[9], vf[9];
+  {
+    const int64_t in_ = e2 * 8 + (n ^ mask), if_ = e2 * 8 + n;   // nearest the face, far side
+    if constexpr (kNbrZero) {
+#pragma unroll
+      for (int f = 0; f < 9; ++f) {
+        vn[f] = T(U[f * FS + in_]);
+        vf[f] = T(U[f * FS + if_]);
+      }
+    } else {
+      load_node<S, N, Mode, true>(U, V, M, FS, in_, vn);
+      load_node<S, N, Mode, true>(U, V, M, FS, if_, vf);
+    }
+  }
+  const int ph2 = phase[e2];
+
+  // volume term along d: sqrt(3)/h sgn(a_d) W3 (F_d(a) + F_d(a'))
+  {
+    T Fd[7];
+    axis_flux(P, fN, u, g, Fd);
+#pragma unroll
+    for (int f = 0; f < 7; ++f) r[f] += sq3h * sgn * W3 * (Fd[f] + xlane(Fd[f], mask));
+  }
+
+  // face point on this lane's line at its own side s = sgn
+  T q[7];
+#pragma unroll
+  for (int f = 0; f < 7; ++f) q[f] = T(0);
+  if (inside) {
+    // Canonical orientation: A = the lower element of the face (outward
+    // normal +e_d), B = the upper one.  Both elements evaluate the flux
+    // from A to B with the same operation sequence on the same operands
+    // and take +-1 times it, so a face's two contributions cancel exactly
+    // in any sum over elements (discrete conservation to the last bit).
+    T ta[9], tb[9], ga[7], gb[7];
+    {
+#pragma unroll
+      for (int f = 0; f < 9; ++f) {
+        const T tm = face_trace(u[f], up[f]);
+        const T tp = face_trace(vn[f], vf[f]);
+        ta[f] = hi ? tm : tp;
+        tb[f] = hi ? tp : tm;
+        if (f < 7) {
+          const T gp = sq3h * (hi ? vf[f] - vn[f] : vn[f] - vf[f]);
+          ga[f] = hi ? g[f] : gp;
+          gb[f] = hi ? gp : g[f];
+        }
+      }
+    }
+    const int phA = hi ? ph : ph2, phB = hi ? ph2 : ph;
+    const T side = hi ? T(1) : T(-1);          // +flux for A, -flux for B
+    T flux[7];
+    face_flux(P, phA, phB, ta, tb, ga, gb, flux);
+#pragma unroll
+    for (int f = 0; f < 7; ++f) q[f] = side * flux[f];
+  } else if (d == 0 && hi) {
+    // separator face x = L_x: inward Li+ flux j_el/F and ionic current j_el
+    q[0] = -T(P.jel) / T(P.F);
+    q[6] = -T(P.jel);
+  }
+#pragma unroll
+  for (int f = 0; f < 7; ++f) r[f] += W2 * (lam1 * q[f] + lam0 * xlane(q[f], mask));
+}
+
 // Rows of the Q1 operator at one node (lane): residual rows (N = S) or their
 // tangents (N = Dual<S>).  u holds the lane's own nine unknowns as N.
-// Neighbour nodes are read from U (and from V in the JVP modes); with
-// kNbrZero their direction is zero (element-diagonal Jacobian blocks).
 template <typename S, typename N, int Mode, bool kNbrZero, bool kSources = true>
 __device__ __forceinline__ void q1_rows(const S* __restrict__ U, const S* __restrict__ V,
                                         const S* __restrict__ M, const uint8_t* __restrict__ phase,
                                         const DevParams& P, int64_t e, int n, int ph, int ix, int iy,
                                         int iz, int64_t FS, const N* u, N* r) {
   using T = N;
-  const T epsCBD = T(P.epsCBD[ph]);
-  const T eL = liquid_fraction(epsCBD, u[7], u[8], T(P.epsL_min));
+  const T W3 = T(P.W3);
+  q1_mass_rows<S, N, Mode>(M, P, e, n, ph, FS, u, r);
+  const T eL = liquid_fraction(T(P.epsCBD[ph]), u[7], u[8], T(P.epsL_min));
   const T fN = transport_factor(u, eL);
-  const T W3 = T(P.W3), W2 = T(P.W2), sq3h = T(P.sq3_h);
-  const T lam1 = T(kLam1), lam0 = T(kLam0);
-  {
-    const T idt = T(P.inv_dt);
-    // the old mass is a constant of the step: it enters the residual only
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      const T mi = (Mode == kResidual) ? T(M[i * FS + e * 8 + n]) : T(0);
-      r[i] = W3 * (eL * u[i] - mi) * idt;
-    }
-    r[6] = T(0);
-    const T m6 = (Mode == kResidual) ? T(M[6 * FS + e * 8 + n]) : T(0);
-    const T m7 = (Mode == kResidual) ? T(M[7 * FS + e * 8 + n]) : T(0);
-    r[7] = W3 * T(P.rhoM[0]) * (u[7] - m6) * idt;
-    r[8] = W3 * T(P.rhoM[1]) * (u[8] - m7) * idt;
-  }
-
-  const int coord[3] = {ix, iy, iz};
-  const int ncell[3] = {P.nx, P.ny, P.nz};
-  const int64_t stride[3] = {1, int64_t(P.nx), int64_t(P.nx) * P.ny};
-
 #pragma unroll 1
-  for (int d = 0; d < 3; ++d) {
-    const int mask = 1 << d;
-    const bool hi = (n & mask) != 0;
-    const T sgn = hi ? T(1) : T(-1);
-    T up[9];
-#pragma unroll
-    for (int f = 0; f < 9; ++f) up[f] = xlane(u[f], mask);
-    T g[7];
-#pragma unroll
-    for (int f = 0; f < 7; ++f) g[f] = sq3h * (hi ? u[f] - up[f] : up[f] - u[f]);
-
-    // volume term along d: sqrt(3)/h sgn(a_d) W3 (F_d(a) + F_d(a'))
-    {
-      T Fd[7];
-      axis_flux(P, fN, u, g, Fd);
-#pragma unroll
-      for (int f = 0; f < 7; ++f) r[f] += sq3h * sgn * W3 * (Fd[f] + xlane(Fd[f], mask));
-    }
-
-    // face point on this lane's line at its own side s = sgn
-    T q[7];
-#pragma unroll
-    for (int f = 0; f < 7; ++f) q[f] = T(0);
-    const int cn = coord[d] + (hi ? 1 : -1);
-    if (cn >= 0 && cn < ncell[d]) {
-      const int64_t e2 = e + (hi ? stride[d] : -stride[d]);
-      const int ph2 = phase[e2];
-      // Canonical orientation: A = the lower element of the face (outward
-      // normal +e_d), B = the upper one.  Both elements evaluate the flux
-      // from A to B with the same operation sequence on the same operands
-      // and take +-1 times it, so a face's two contributions cancel exactly
-      // in any sum over elements (discrete conservation to the last bit).
-      T ta[9], tb[9], ga[7], gb[7];
-      {
-        T vn[9], vf[9];
-        const int64_t in_ = e2 * 8 + (n ^ mask), if_ = e2 * 8 + n;   // nearest the face, far side
-        if constexpr (kNbrZero) {
-#pragma unroll
-          for (int f = 0; f < 9; ++f) {
-            vn[f] = T(U[f * FS + in_]);
-            vf[f] = T(U[f * FS + if_]);
-          }
-        } else {
-          load_node<S, N, Mode, true>(U, V, M, FS, in_, vn);
-          load_node<S, N, Mode, true>(U, V, M, FS, if_, vf);
-        }
-#pragma unroll
-        for (int f = 0; f < 9; ++f) {
-          const T tm = face_trace(u[f], up[f]);
-          const T tp = face_trace(vn[f], vf[f]);
-          ta[f] = hi ? tm : tp;
-          tb[f] = hi ? tp : tm;
-          if (f < 7) {
-            const T gp = sq3h * (hi ? vf[f] - vn[f] : vn[f] - vf[f]);
-            ga[f] = hi ? g[f] : gp;
-            gb[f] = hi ? gp : g[f];
-          }
-        }
-      }
-      const int phA = hi ? ph : ph2, phB = hi ? ph2 : ph;
-      const T side = hi ? T(1) : T(-1);          // +flux for A, -flux for B
-      T flux[7];
-      face_flux(P, phA, phB, ta, tb, ga, gb, flux);
-#pragma unroll
-      for (int f = 0; f < 7; ++f) q[f] = side * flux[f];
-    } else if (d == 0 && hi) {
-      // separator face x = L_x: inward Li+ flux j_el/F and ionic current j_el
-      q[0] = -T(P.jel) / T(P.F);
-      q[6] = -T(P.jel);
-    }
-#pragma unroll
-    for (int f = 0; f < 7; ++f) r[f] += W2 * (lam1 * q[f] + lam0 * xlane(q[f], mask));
-  }
+  for (int d = 0; d < 3; ++d) q1_axis<S, N, Mode, kNbrZero>(U, V, M, phase, P, e, n, ph, ix, iy, iz, FS, u, fN, d, r);
 
   if constexpr (kSources) {
     if (P.react[ph] != 0.0) {
