@@ -128,6 +128,90 @@ multi_axpy_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restr
   }
 }
 
+// One sweep of classical Gram-Schmidt applied twice: w -= sum_i h[i] V_i
+// (the first pass's update), then partial sums of V_i . w for the updated w
+// (the second pass's projections).  Each thread re-reads its quads of the
+// basis right after using them, from cache, so the basis streams from HBM
+// once for both; the arithmetic per entry is that of multi_axpy_kernel and
+// multi_dot_kernel.  Launch with the grid of multi_dot_kernel.
+template <typename S>
+__global__ void __launch_bounds__(256)
+multi_axpy_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h,
+                      S* __restrict__ w, int64_t n, S* __restrict__ partial) {
+  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
+  __shared__ S sh[4];
+  S acc[kMaxDots];
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
+  const int64_t n4 = n >> 2;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    Q s{S(0), S(0), S(0), S(0)};
+    for (int i = 0; i < nv; ++i) {
+      const S hi = h[i];
+      const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
+      s.a += hi * v.a;
+      s.b += hi * v.b;
+      s.c += hi * v.c;
+      s.d += hi * v.d;
+    }
+    Q wk = reinterpret_cast<Q*>(w)[k];
+    wk.a += S(-1) * s.a;
+    wk.b += S(-1) * s.b;
+    wk.c += S(-1) * s.c;
+    wk.d += S(-1) * s.d;
+    reinterpret_cast<Q*>(w)[k] = wk;
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) {
+        const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
+        acc[i] += v.a * wk.a + v.b * wk.b + v.c * wk.c + v.d * wk.d;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) {
+    if (i < nv) {
+      const S sum = block_sum(acc[i], sh);
+      if (threadIdx.x == 0) partial[i * gridDim.x + blockIdx.x] = sum;
+    }
+  }
+}
+
+// The second pass's update w -= sum_i h[i] V_i with partial sums of |w|^2
+// of the result in FP64 (one per block).
+template <typename S>
+__global__ void __launch_bounds__(256)
+multi_axpy_sumsq_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h,
+                        S* __restrict__ w, int64_t n, double* __restrict__ partial) {
+  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
+  __shared__ double sh[4];
+  double acc = 0.0;
+  const int64_t n4 = n >> 2;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    Q s{S(0), S(0), S(0), S(0)};
+    for (int i = 0; i < nv; ++i) {
+      const S hi = h[i];
+      const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
+      s.a += hi * v.a;
+      s.b += hi * v.b;
+      s.c += hi * v.c;
+      s.d += hi * v.d;
+    }
+    Q wk = reinterpret_cast<Q*>(w)[k];
+    wk.a += S(-1) * s.a;
+    wk.b += S(-1) * s.b;
+    wk.c += S(-1) * s.c;
+    wk.d += S(-1) * s.d;
+    reinterpret_cast<Q*>(w)[k] = wk;
+    const double a = double(wk.a), b = double(wk.b), c = double(wk.c), d = double(wk.d);
+    acc += a * a;
+    acc += b * b;
+    acc += c * c;
+    acc += d * d;
+  }
+  const double sum = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
 // partial sums per field f < 7 of a_f * b_f (field stride FS)
 template <typename S>
 __global__ void __launch_bounds__(256)

@@ -372,8 +372,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     precond(pJ, out);
     hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, out, out, n7);
   };
-  auto mdot = [&](const S* Vb, int nv, const S* ww, std::vector<double>& h) -> int {
-    hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, Vb, n7, nv, ww, n7, partial);
+  // dots[0..nv) and h <- the block partials of nv dot products
+  auto finish_dots = [&](int nv, std::vector<double>& h) -> int {
     const dim3 gnv{unsigned(nv), 1, 1};
     hipLaunchKernelGGL(finish_sum_kernel<S>, gnv, blk, 0, st, partial, kRedBlocks, dots);
     std::vector<S> hs(nv);
@@ -382,13 +382,24 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     h.assign(hs.begin(), hs.end());
     return DG_OK;
   };
-  auto sumsq = [&](const S* a, int64_t n, double& out) -> int {
-    hipLaunchKernelGGL(sumsq_kernel<S>, gred, blk, 0, st, a, n, partial64);
+  auto mdot = [&](const S* Vb, int nv, const S* ww, std::vector<double>& h) -> int {
+    hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, Vb, n7, nv, ww, n7, partial);
+    return finish_dots(nv, h);
+  };
+  // out <- the sum of the FP64 block partials in partial64
+  auto finish_sumsq = [&](double& out) -> int {
     hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, kRedBlocks,
                        reinterpret_cast<double*>(hbuf));
     double hs = 0;
     DG_HIP(hipMemcpyAsync(&hs, hbuf, sizeof(double), hipMemcpyDeviceToHost, st));
     DG_HIP(hipStreamSynchronize(st));
+    out = hs;
+    return DG_OK;
+  };
+  auto sumsq = [&](const S* a, int64_t n, double& out) -> int {
+    hipLaunchKernelGGL(sumsq_kernel<S>, gred, blk, 0, st, a, n, partial64);
+    double hs = 0;
+    if (int s = finish_sumsq(hs)) return s;
     out = hs;
     return DG_OK;
   };
@@ -565,13 +576,15 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
           // classical Gram-Schmidt applied twice: with FP32 basis vectors a
           // single pass (even with a reorthogonalisation test) loses enough
           // orthogonality to slow the two-level preconditioned iteration
+          // (three sweeps over the basis: projections; first update fused
+          // with the second projections; second update fused with |w|^2)
           if (int s = mdot(V, j + 1, w, h)) return s;
-          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
-          if (int s = mdot(V, j + 1, w, h2)) return s;
-          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j + 1, dots, S(-1), w, n7);
+          hipLaunchKernelGGL(multi_axpy_dot_kernel<S>, gred, blk, 0, st, V, n7, j + 1, dots, w, n7, partial);
+          if (int s = finish_dots(j + 1, h2)) return s;
+          hipLaunchKernelGGL(multi_axpy_sumsq_kernel<S>, gred, blk, 0, st, V, n7, j + 1, dots, w, n7, partial64);
           for (int i = 0; i <= j; ++i) h[i] += h2[i];
           double hn = 0.0;
-          if (int s = sumsq(w, n7, hn)) return s;
+          if (int s = finish_sumsq(hn)) return s;
           hn = std::sqrt(hn);
           ++its;
           for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
