@@ -50,6 +50,7 @@ if ROOT not in sys.path:
 
 METRIC = "DG operator GDoF/s (% roofline) + s per full discharge, mixed vs FP64 at fixed error"
 HBM_PEAK_GBS = 8000.0
+SOLVER_EXTRA = {}      # further dg_solver_opts fields of the timed solves (command line)
 FARADAY = 96485.332
 
 
@@ -165,6 +166,9 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     ms_res = time_launches(lambda: ctx.residual(u, m8, t, dt, out=r9), stream, reps)
     ctx.blockjacobi_setup(uS, t, dt)
     ms_apply = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7), stream, reps)
+    ms_apply_h = None
+    if S == torch.float32:
+        ms_apply_h = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7, bf16=True), stream, reps)
     ms_setup = time_launches(lambda: ctx.blockjacobi_setup(uS, t, dt), stream, 3)
 
     def gbs(nbytes, ms):
@@ -173,6 +177,7 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     b_jvp = nodes * (9 + 7 + 14 + 7) * sb + ctx.n_elem      # u, v, coefficients in; Jv out; phase
     b_res = nodes * (9 + 8 + 9) * 8 + ctx.n_elem            # u, old mass in; R out; phase
     b_apply = ctx.n_elem * (56 * 56 + 2 * 56) * sb          # blocks, x in, y out
+    b_apply_h = ctx.n_elem * (56 * 56 * 2 + 2 * 56 * 4)     # bfloat16 blocks, FP32 x in, y out
     kernels = {
         "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp},
         "residual_f64": {"ms": ms_res, "GB/s": gbs(b_res, ms_res), "bytes": b_res},
@@ -180,12 +185,16 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
         "block_setup": {"ms": ms_setup},
         "linearize": {"ms": ms_lin},
     }
+    if ms_apply_h is not None:
+        kernels["block_apply_bf16"] = {"ms": ms_apply_h, "GB/s": gbs(b_apply_h, ms_apply_h), "bytes": b_apply_h}
     for k in kernels.values():
         if "GB/s" in k:
             k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 4)
             k["GB/s"] = round(k["GB/s"], 1)
         k["ms"] = round(k["ms"], 4)
-    return kernels, (b_apply, ms_apply)
+    if ms_apply_h is not None and SOLVER_EXTRA.get("block_bf16", 1):
+        return kernels, ("apply_blocks_bf16_kernel", b_apply_h, ms_apply_h)
+    return kernels, ("apply_blocks_kernel", b_apply, ms_apply)
 
 
 def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
@@ -194,7 +203,7 @@ def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0, coarse_
     if n < 1:
         return {"newton_its": 0, "gmres_its": 0, "last_update": float("nan")}
     try:
-        rep = ctx.step(u, t, dt, inner=inner, verbose=verbose, newton_maxit=n, coarse=coarse,
+        rep = ctx.step(u, t, dt, inner=inner, verbose=verbose, newton_maxit=n, coarse=coarse, **SOLVER_EXTRA,
                        coarse_agg=coarse_agg)
     except lsbdg.DgError as e:
         if e.code != -4:                      # DG_ENOCONV: the iteration cap was reached
@@ -461,7 +470,8 @@ def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0, coarse_agg=0)
     """n accepted steps of the naive controller (halving on failed solves)."""
     tot = {"newton_its": 0, "gmres_its": 0, "trials": 0, "halvings": 0}
     for _ in range(n):
-        t, rep = ctx.advance(ctrl, t, u, inner=inner, verbose=verbose, coarse=coarse, coarse_agg=coarse_agg)
+        t, rep = ctx.advance(ctrl, t, u, inner=inner, verbose=verbose, coarse=coarse, coarse_agg=coarse_agg,
+                             **SOLVER_EXTRA)
         for k in tot:
             tot[k] += rep[k]
         log(f"[bench] step of {rep['dt']:.4g} s to t = {t:.4f} s: {rep['trials']} trials, "
@@ -481,6 +491,8 @@ def main(argv=None):
                     help="preconditioner coarse space (0: library default = 3, 1: global constants, "
                          "3: voxel aggregates, additive, 4: multiplicative)")
     ap.add_argument("--coarse-agg", type=int, default=0, help="aggregate edge in voxels (0: automatic)")
+    ap.add_argument("--fp32-blocks", action="store_true",
+                    help="stream the element-block inverses in FP32 in GMRES (default: a bfloat16 copy)")
     ap.add_argument("--workload", default="slab96_q1")
     ap.add_argument("--compare-f64", action="store_true",
                     help="repeat the timed steps with an FP64 inner solve from the same state")
@@ -503,6 +515,8 @@ def main(argv=None):
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args(argv)
+    if args.fp32_blocks:
+        SOLVER_EXTRA["block_bf16"] = 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path; "
               "run with --gpus 1.", file=sys.stderr)
@@ -542,7 +556,7 @@ def main(argv=None):
         print(json.dumps(out), flush=True)
         return 0
     u, rep0 = ctx.initial_state(inner=args.inner, verbose=args.verbose, coarse=args.coarse,
-                                coarse_agg=args.coarse_agg)
+                                coarse_agg=args.coarse_agg, **SOLVER_EXTRA)
     log(f"[bench] initial state: {rep0['newton_its']} Newton, {rep0['gmres_its']} GMRES")
     t = 0.0
     if args.mode == "newton":
@@ -571,7 +585,7 @@ def main(argv=None):
         done = args.steps
         ms_step = wall * 1e3 / args.steps
 
-    kernels, (b_apply, ms_apply) = time_kernels(ctx, u, t, args.dt, args.inner, stream, dev, log)
+    kernels, (k_apply, b_apply, ms_apply) = time_kernels(ctx, u, t, args.dt, args.inner, stream, dev, log)
     achieved = b_apply / (ms_apply * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -598,8 +612,8 @@ def main(argv=None):
                    "coarse": args.coarse, "coarse_agg": args.coarse_agg, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(w.name, "apply_blocks_kernel"),
-                     "kernel": "apply_blocks_kernel", "ms": round(ms_apply, 4),
+                     "traffic": recorded_traffic(w.name, k_apply),
+                     "kernel": k_apply, "ms": round(ms_apply, 4),
                      "bytes_per_launch": b_apply},
         "kernels": kernels,
     }

@@ -171,6 +171,14 @@ int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new,
  * DG_ESTATE before any setup). x and y must not overlap. */
 int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_stream stream);
 
+/* As dg_blockjacobi_apply after an FP32 setup, but streaming a bfloat16
+ * copy of the stored inverses (each entry rounded to nearest even; made on
+ * the first call after a setup and kept, Ne * 56 * 56 * 2 bytes): y_e =
+ * bf16(B_e^{-1}) x_e with FP32 accumulation.  This is the preconditioner
+ * apply of FP32 inner solves with block_bf16.  x, y: device, FP32, 7 fields,
+ * not overlapping.  DG_ESTATE unless the last setup was DG_F32. */
+int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream);
+
 /* Copy the stored inverse blocks (Ne blocks of 56 x 56, column-major:
  * out[e][col][row], row/col = field * 8 + node) to the device buffer out. */
 int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream);
@@ -200,9 +208,11 @@ typedef struct {
   int32_t coarse_agg;    /* aggregate edge in voxels for coarse = 3, 4 (0: the
                             smallest edge >= 4 with at most 8192 coarse
                             unknowns) */
-  int32_t block_bf16;    /* DG_F32 inner solves: 1 streams the element block
-                            inverses as bfloat16 in the preconditioner apply
-                            (half the bytes; the solution is unchanged) */
+  int32_t block_bf16;    /* DG_F32 inner solves: 1 (default) streams the
+                            element block inverses as bfloat16 in the
+                            preconditioner apply (half the bytes; only the
+                            preconditioner changes, not the Newton root);
+                            0 streams them in FP32 */
   int32_t verbose;       /* 1: one line per Newton iteration on stderr */
 } dg_solver_opts;
 

@@ -53,8 +53,9 @@ struct dg_ctx {
   // aggregation coarse space: LU of the equilibrated coarse operator,
   // equilibration, pivots, a coarse vector, LAPACK status
   DevBuf cE, cd, crc, crc2, cipiv, cinfo;
-  // bfloat16 copy of FP32 block inverses (block_bf16)
+  // bfloat16 copy of FP32 block inverses (block_bf16), current while bh_valid
   DevBuf bh;
+  bool bh_valid = false;
   rocblas_handle blas = nullptr;
   int lin_prec = -1;
   int* d_status = nullptr;
@@ -452,11 +453,13 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
     if (int s = linearize<S>(ctx, P, uS, st)) return s;
     if (int s = blocks_setup<S>(ctx, P, uS, st)) return s;
+    ctx->bh_valid = false;
     if (std::is_same<S, float>::value && o.block_bf16) {
       hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * 56 * 56 * 2);
       if (e != hipSuccess) return fail(DG_ENOMEM, std::string("bf16 blocks: ") + hipGetErrorString(e));
       hipLaunchKernelGGL((blocks_to_bf16_kernel<56>), dim3(8192), blk, 0, st,
                          static_cast<const float*>(ctx->d_blocks), ctx->bh.as<uint16_t>(), ctx->Ne);
+      ctx->bh_valid = true;
     }
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
     if (agg) {
@@ -1093,6 +1096,7 @@ int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new,
   DG_HIP(hipMemcpyAsync(&h_status, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
   DG_HIP(hipStreamSynchronize(st));
   ctx->blocks_prec = int(prec);
+  ctx->bh_valid = false;
   if (h_status) return fail(DG_ENAN, "dg_blockjacobi_setup: singular or non-finite element block");
   return DG_OK;
 }
@@ -1113,6 +1117,26 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
     hipLaunchKernelGGL((apply_blocks_kernel<float, 7>), grid, block, 0, st,
                        static_cast<const float*>(ctx->d_blocks), static_cast<const float*>(x),
                        static_cast<float*>(y), ctx->Ne);
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!x || !y) return fail(DG_EINVAL, "dg_blockjacobi_apply_bf16: null array");
+  if (ctx->blocks_prec != DG_F32) return fail(DG_ESTATE, "dg_blockjacobi_apply_bf16: no FP32 setup");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!ctx->bh_valid) {
+    hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * kNB * kNB * 2);
+    if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_blockjacobi_apply_bf16: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL((blocks_to_bf16_kernel<kNB>), dim3(8192), dim3(256), 0, st,
+                       static_cast<const float*>(ctx->d_blocks), ctx->bh.as<uint16_t>(), ctx->Ne);
+    DG_HIP(hipGetLastError());
+    ctx->bh_valid = true;
+  }
+  const dim3 grid{unsigned((ctx->Ne + 3) / 4), 1, 1}, block{256, 1, 1};
+  hipLaunchKernelGGL((apply_blocks_bf16_kernel<7>), grid, block, 0, st, ctx->bh.as<const uint16_t>(),
+                     static_cast<const float*>(x), static_cast<float*>(y), ctx->Ne);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -1144,6 +1168,7 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->gmres_rtol_final = 1e-11;
   o->newton_tol = 1e-11;
   o->coarse = 0;           // 0: the aggregation coarse space (3)
+  o->block_bf16 = 1;       // FP32 inner solves stream bfloat16 block inverses
   o->verbose = 0;
 }
 

@@ -35,6 +35,7 @@ _SIGNATURES = {
     "dg_blockjacobi_setup": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double,
                                        C.c_void_p]),
     "dg_blockjacobi_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_blockjacobi_apply_bf16": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_blockjacobi_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_solver_opts_default": (None, [C.c_void_p]),
     "dg_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -325,12 +326,19 @@ class Context:
         _check("dg_blockjacobi_setup", self._lib.dg_blockjacobi_setup(
             self._h, _prec(uu), _ptr(uu), float(t_new), float(dt), _stream()))
 
-    def blockjacobi_apply(self, x, out=None):
+    def blockjacobi_apply(self, x, out=None, bf16=False):
+        """y = B^-1 x; bf16: from the bfloat16 copy of FP32 inverses."""
         import torch
         self._check_arr(x, 7)
         if out is None:
             out = torch.empty_like(x)
         self._check_arr(out, 7)
+        if bf16:
+            if x.dtype != torch.float32:
+                raise ValueError("the bfloat16 apply takes FP32 vectors")
+            _check("dg_blockjacobi_apply_bf16", self._lib.dg_blockjacobi_apply_bf16(
+                self._h, _ptr(x), _ptr(out), _stream()))
+            return out
         _check("dg_blockjacobi_apply", self._lib.dg_blockjacobi_apply(
             self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
         return out

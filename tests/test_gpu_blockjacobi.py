@@ -60,3 +60,42 @@ def test_blockjacobi_errors():
     ctx.blockjacobi_setup(u, 1.0, 0.1)
     with pytest.raises(lsbdg.DgError, match="DG_EINVAL"):
         ctx.blockjacobi_apply(x)
+
+
+def test_bf16_apply_rounds_the_fp32_inverses():
+    """dg_blockjacobi_apply_bf16 applies the FP32 inverses rounded to
+    bfloat16 (nearest even), accumulating in FP32; a new setup replaces the
+    bfloat16 copy."""
+    P, ctx, mask = problem_and_context(5, 4, 3, mask_seed=2, param_seed=1)
+    dev = torch.device("cuda:0")
+    x = synth.random_vector(7, P.n_elem, P.n_nodes, 700)
+    xt = torch.tensor(x, device=dev, dtype=torch.float32)
+    xe = torch.tensor(x, dtype=torch.float64).permute(1, 0, 2).reshape(P.n_elem, 56)
+    for seed in (0, 1):
+        u = synth.random_state(P.n_elem, P.n_nodes, 710 + seed, phase=mask, phi_spread=5e-3)
+        ut = torch.tensor(u, device=dev, dtype=torch.float32)
+        ctx.blockjacobi_setup(ut, 0.9, 0.05)
+        inv = ctx.blockjacobi_export().cpu()                        # [e][col][row]
+        Bh = inv.to(torch.bfloat16).to(torch.float64)
+        ref = (Bh * xe[:, :, None]).sum(dim=1)                      # [e][row]
+        y = ctx.blockjacobi_apply(xt, bf16=True).cpu().to(torch.float64)
+        ye = y.permute(1, 0, 2).reshape(P.n_elem, 56)
+        scale = (Bh.abs() * xe.abs()[:, :, None]).sum(dim=1)
+        err = float(((ye - ref).abs() / scale.clamp_min(1e-300)).max())
+        print(f"[bj] bf16 apply, state {seed}: max error {err:.2e} of sum |B||x|", flush=True)
+        assert err < 1e-6
+        y32 = ctx.blockjacobi_apply(xt).cpu().to(torch.float64).permute(1, 0, 2).reshape(P.n_elem, 56)
+        assert not torch.equal(ye, y32)          # the rounding is visible: a different apply
+
+
+def test_bf16_apply_needs_an_fp32_setup():
+    from paper_2511_05233_amd import lsbdg
+    P, ctx, mask = problem_and_context(3, 3, 3, mask_seed=0, param_seed=0)
+    dev = torch.device("cuda:0")
+    x = torch.zeros((7, P.n_elem, 8), dtype=torch.float32, device=dev)
+    with pytest.raises(lsbdg.DgError, match="DG_ESTATE"):
+        ctx.blockjacobi_apply(x, bf16=True)
+    u = synth.random_state(P.n_elem, P.n_nodes, 3, phase=mask)
+    ctx.blockjacobi_setup(torch.tensor(u, device=dev), 0.9, 0.05)       # FP64 setup
+    with pytest.raises(lsbdg.DgError, match="DG_ESTATE"):
+        ctx.blockjacobi_apply(x, bf16=True)
