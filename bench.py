@@ -27,8 +27,9 @@ value = DG operator GDoF/s: transported DoF / mean duration of one
 application of the Krylov operator (the condensed tangent at a stored
 linearisation, in the inner precision), timed with HIP events on the stream
 it runs on.  roofline = the kernel with the largest share of a Newton
-iteration (the block apply: one per GMRES iteration) against the HBM peak;
-the other kernels are listed beside it.
+iteration (the block apply of the solver, by default from bfloat16
+inverses: one per GMRES iteration) against the HBM peak; the other kernels
+are listed beside it.
 
 Beside the line (skipped with --no-c3): five steps on the 16^3 cube and a
 full 1C discharge of it to the 1.9 V cutoff, each with FP64 and with mixed
