@@ -214,6 +214,13 @@ typedef struct {
                             preconditioner changes, not the Newton root);
                             0 streams them in FP32 */
   int32_t verbose;       /* 1: one line per Newton iteration on stderr */
+  int32_t coarse_every;  /* coarse = 3, 4: the coarse operator E = Z^T J Z
+                            and its inverse are rebuilt at the first Newton
+                            iterate, after an update whose largest
+                            relative change of an unknown exceeded 2, and
+                            every coarse_every iterates (0:
+                            default 3; 1: every iterate); the element blocks
+                            are rebuilt at every iterate */
 } dg_solver_opts;
 
 void dg_solver_opts_default(dg_solver_opts* o);
@@ -235,10 +242,11 @@ typedef struct {
  * line search (the paper uses PETSc newtonls, Sec. 2.8); positive unknowns
  * are updated multiplicatively (Newton in their logarithms).  Each linear
  * solve is GMRES(m) on the condensed 7-field Jacobian, scaled by the unknown
- * magnitudes and preconditioned by the element blocks plus a global
- * per-field coarse correction, in the inner precision of opts (NULL:
- * defaults).  Operator and preconditioner are rebuilt at every Newton
- * iterate.  Device workspace is allocated on first use and kept.
+ * magnitudes and preconditioned by the element blocks plus a coarse
+ * correction (opts.coarse), in the inner precision of opts (NULL:
+ * defaults).  The operator and the element blocks are rebuilt at every
+ * Newton iterate, the aggregation coarse operator every opts.coarse_every
+ * iterates.  Device workspace is allocated on first use and kept.
  * Converged when a full step changes no unknown by more than newton_tol,
  * or, once an update below 1e-7 has been reached (the attainable accuracy
  * of the iterative solve; report.stalled = 1), when three full steps in a

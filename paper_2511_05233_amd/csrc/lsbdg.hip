@@ -448,6 +448,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // Operator and preconditioner are rebuilt at every Newton iterate: a
   // preconditioner kept from an earlier iterate cost more GMRES iterations
   // than its rebuild on the 16^3 cube.
+  int coarse_built = 0;                       // iterate of the last coarse rebuild
   for (int it = 1; it <= o.newton_maxit; ++it) {
     r.newton_its = it;
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
@@ -462,9 +463,15 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       ctx->bh_valid = true;
     }
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
-    if (agg) {
+    // the aggregation coarse operator is rebuilt at the first iterate, after
+    // an update whose largest relative change of an unknown exceeded 2 (E
+    // moves with the iterate) and every coarse_every iterates; in between,
+    // E^-1 of the last rebuild stays a good coarse correction (the element
+    // blocks are rebuilt at every iterate)
+    if (agg && (it == 1 || r.last_update > 2.0 || it - coarse_built >= o.coarse_every)) {
       // aggregation coarse operator E = Z^T J Z by coloured probes, then LU;
       // Z keeps the unknown scales of this rebuild (scc)
+      coarse_built = it;
       hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), sc, S(0), scc, n7);
       DG_HIP(hipMemsetAsync(cE, 0, size_t(nc) * nc * 8, st));
       for (int f = 0; f < 7; ++f) {
@@ -749,6 +756,8 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
   if (o.coarse == 0) o.coarse = 3;
   if (o.coarse < 0) o.coarse = 0;
   if (o.coarse > 4) return fail(DG_EINVAL, std::string(fn) + ": coarse must be -1..4");
+  if (o.coarse_every == 0) o.coarse_every = 3;
+  if (o.coarse_every < 0) return fail(DG_EINVAL, std::string(fn) + ": coarse_every must be >= 0");
   return DG_OK;
 }
 
@@ -1170,6 +1179,7 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->coarse = 0;           // 0: the aggregation coarse space (3)
   o->block_bf16 = 1;       // FP32 inner solves stream bfloat16 block inverses
   o->verbose = 0;
+  o->coarse_every = 3;     // aggregation coarse operator rebuilt every third iterate
 }
 
 int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,

@@ -84,7 +84,7 @@ class DgSolverOpts(C.Structure):
                 ("newton_maxit", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_rtol_final", C.c_double),
                 ("newton_tol", C.c_double),
                 ("coarse", C.c_int32), ("coarse_agg", C.c_int32), ("block_bf16", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("verbose", C.c_int32), ("coarse_every", C.c_int32)]
 
 
 class DgStepReport(C.Structure):
