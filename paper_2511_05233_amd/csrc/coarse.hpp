@@ -131,15 +131,46 @@ agg_restrict_kernel(const S* __restrict__ sc, const S* __restrict__ r, AggGrid G
   if (threadIdx.x < 7) rc[int64_t(threadIdx.x) * G.na + b] = acc[threadIdx.x];
 }
 
-// Prolongation out += Z y: out[g][node] += sc[g][node] y[g * na + agg(node)].
+// Prolongation out += Z y: out[g][node] += sc[g][node] y[g * na + agg(node)];
+// one thread per node finds its aggregate once for the seven fields.
 template <typename S>
 __global__ void __launch_bounds__(256)
 agg_prolong_add_kernel(const S* __restrict__ sc, const double* __restrict__ y, AggGrid G, int64_t FS,
                        S* __restrict__ out) {
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 7 * FS; k += int64_t(gridDim.x) * 256) {
-    const int g = int(k / FS);
-    const int64_t node = k - int64_t(g) * FS;
-    out[k] += sc[k] * S(y[int64_t(g) * G.na + agg_of_voxel(G, node >> 3)]);
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
+    const int64_t a = agg_of_voxel(G, k >> 3);
+#pragma unroll
+    for (int g = 0; g < 7; ++g) out[g * FS + k] += sc[g * FS + k] * S(y[int64_t(g) * G.na + a]);
+  }
+}
+
+// Coarse correction y = d .* (A (d .* x)) with the explicit inverse A of the
+// equilibrated coarse operator (column-major, nc x nc, FP64).  Split over
+// column chunks so that the launch fills the chip: pass 1 writes
+// part[chunk][i] = sum over the chunk's columns j of A[i][j] d[j] x[j]
+// (grid: row tiles of 256 x kCoarseChunks), pass 2 sums the chunks.
+constexpr int kCoarseChunks = 32;
+
+__global__ void __launch_bounds__(256)
+coarse_gemv_partial_kernel(const double* __restrict__ A, int64_t nc, const double* __restrict__ x,
+                           const double* __restrict__ d, int64_t chunk, double* __restrict__ part) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t j0 = int64_t(blockIdx.y) * chunk;
+  const int64_t j1 = j0 + chunk < nc ? j0 + chunk : nc;
+  if (i >= nc) return;
+  double acc = 0.0;
+  for (int64_t j = j0; j < j1; ++j) acc += A[i + j * nc] * (d[j] * x[j]);
+  part[int64_t(blockIdx.y) * nc + i] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+coarse_gemv_finish_kernel(const double* __restrict__ part, int64_t nc, const double* __restrict__ d,
+                          double* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nc; i += int64_t(gridDim.x) * 256) {
+    double s = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < kCoarseChunks; ++k) s += part[int64_t(k) * nc + i];
+    y[i] = d[i] * s;
   }
 }
 
@@ -166,12 +197,6 @@ coarse_scale_kernel(double* __restrict__ E, int64_t nc, int64_t ld, const double
     const int64_t j = k / nc, i = k - j * nc;
     E[i + ld * j] *= d[i] * d[j];
   }
-}
-
-// x = d .* x (coarse vectors)
-__global__ void __launch_bounds__(256)
-coarse_dmul_kernel(double* __restrict__ x, const double* __restrict__ d, int64_t nc) {
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nc; i += int64_t(gridDim.x) * 256) x[i] *= d[i];
 }
 
 }  // namespace lsbdg

@@ -52,7 +52,7 @@ struct dg_ctx {
   DevBuf lin;
   // aggregation coarse space: LU of the equilibrated coarse operator,
   // equilibration, pivots, a coarse vector, LAPACK status
-  DevBuf cE, cd, crc, crc2, cipiv, cinfo;
+  DevBuf cE, cd, crc, crc2, cipiv, cinfo, cpart;
   // bfloat16 copy of FP32 block inverses (block_bf16), current while bh_valid
   DevBuf bh;
   bool bh_valid = false;
@@ -278,6 +278,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     if (nc > (int64_t(1) << 20)) return fail(DG_EINVAL, "dg_step: coarse space too large (raise coarse_agg)");
     for (auto pr : {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cd, size_t(nc) * 8),
                     std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->crc2, size_t(nc) * 8),
+                    std::make_pair(&ctx->cpart, size_t(kCoarseChunks) * nc * 8),
                     std::make_pair(&ctx->cipiv, size_t(nc) * 4),
                     std::make_pair(&ctx->cinfo, size_t(4))}) {
       hipError_t e = pr.first->ensure(pr.second);
@@ -291,6 +292,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   double* cd = ctx->cd.as<double>();
   double* crc = ctx->crc.as<double>();
   double* crc2 = ctx->crc2.as<double>();
+  double* cgemv = ctx->cpart.as<double>();     // partial sums of the coarse GEMV
   rocblas_int* cipiv = ctx->cipiv.as<rocblas_int>();
   rocblas_int* cinfo = ctx->cinfo.as<rocblas_int>();
   const dim3 gagg{unsigned(G.na > 0 ? G.na : 1), 1, 1};
@@ -319,13 +321,12 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // GEMV (triangular solves with the LU factors run far below HBM speed)
   auto coarse_solve_into = [&](const S* r, S* out, bool add) {
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
-    hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc, cd, nc);
-    const double one = 1.0, zero = 0.0;
-    rocblas_dgemv(ctx->blas, rocblas_operation_none, rocblas_int(nc), rocblas_int(nc), &one, cE, rocblas_int(nc),
-                  crc, 1, &zero, crc2, 1);
-    hipLaunchKernelGGL(coarse_dmul_kernel, grid1(nc), blk, 0, st, crc2, cd, nc);
+    const int64_t chunk = (nc + kCoarseChunks - 1) / kCoarseChunks;
+    hipLaunchKernelGGL(coarse_gemv_partial_kernel, dim3(unsigned((nc + 255) / 256), kCoarseChunks, 1), blk, 0, st,
+                       cE, nc, crc, cd, chunk, cgemv);
+    hipLaunchKernelGGL(coarse_gemv_finish_kernel, grid1(nc), blk, 0, st, cgemv, nc, cd, crc2);
     if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
-    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(n7), blk, 0, st, scc, crc2, G, FS, out);
+    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(FS), blk, 0, st, scc, crc2, G, FS, out);
   };
   auto precond = [&](S* r, S* out) {
     if (o.coarse == 4) {
@@ -953,7 +954,8 @@ int dg_destroy(dg_ctx* ctx) {
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   ctx->work.release_all();
   ctx->lin.release();
-  for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->crc2, &ctx->cipiv, &ctx->cinfo, &ctx->bh}) b->release();
+  for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->crc2, &ctx->cpart, &ctx->cipiv, &ctx->cinfo, &ctx->bh})
+    b->release();
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   delete ctx;
   return DG_OK;
