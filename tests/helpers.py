@@ -33,29 +33,80 @@ def field_errors(got, ref):
     return np.array(out)
 
 
+def _patch(P, e):
+    """The 3 x 3 x 3 patch of voxels around voxel e (clipped at the mesh
+    boundary, which keeps the true boundary faces) as an oracle Problem with
+    the full mesh's current density and structure fraction; the global
+    indices of its voxels and the position of e among them."""
+    mask = P.phase
+    ix, iy, iz = e % P.nx, (e // P.nx) % P.ny, e // (P.nx * P.ny)
+    xs = slice(max(ix - 1, 0), min(ix + 2, P.nx))
+    ys = slice(max(iy - 1, 0), min(iy + 2, P.ny))
+    zs = slice(max(iz - 1, 0), min(iz + 2, P.nz))
+    sub = mask[zs, ys, xs]
+    pz, py, px = sub.shape
+    Q = om.Problem(px, py, pz, P.h, P.k, sub, D0=P.D0, kE=P.kE, f_C=P.f_C, T=P.T,
+                   sigma=P.sigma, c_min=P.c_min, epsL_min=P.epsL_min, use_TH=P.use_TH,
+                   j_el=P.j_el, eps_struct=P.eps_struct_used)
+    g = np.arange(P.n_elem).reshape(P.nz, P.ny, P.nx)[zs, ys, xs].reshape(-1)
+    loc = int(np.nonzero(g == e)[0][0])
+    return Q, g, loc
+
+
 def oracle_residual_at(P, u, m_old, t_new, dt, elems):
     """Oracle residual of the listed elements of a large mesh.
 
     The residual of a voxel depends on itself and its face neighbours only,
-    so it is evaluated on the 3x3x3 patch around the voxel (clipped at the
-    mesh boundary, which keeps the true boundary faces) with the full mesh's
-    current density and structure fraction.
+    so it is evaluated on the 3x3x3 patch around the voxel.
     """
     out = np.zeros((u.shape[0], len(elems), u.shape[2]))
-    mask = P.phase
     for j, e in enumerate(elems):
-        e = int(e)
-        ix, iy, iz = e % P.nx, (e // P.nx) % P.ny, e // (P.nx * P.ny)
-        xs = slice(max(ix - 1, 0), min(ix + 2, P.nx))
-        ys = slice(max(iy - 1, 0), min(iy + 2, P.ny))
-        zs = slice(max(iz - 1, 0), min(iz + 2, P.nz))
-        sub = mask[zs, ys, xs]
-        pz, py, px = sub.shape
-        Q = om.Problem(px, py, pz, P.h, P.k, sub, D0=P.D0, kE=P.kE, f_C=P.f_C, T=P.T,
-                       sigma=P.sigma, c_min=P.c_min, epsL_min=P.epsL_min, use_TH=P.use_TH,
-                       j_el=P.j_el, eps_struct=P.eps_struct_used)
-        g = np.arange(P.n_elem).reshape(P.nz, P.ny, P.nx)[zs, ys, xs].reshape(-1)
-        R = odg.residual(Q, u[:, g], m_old[:, g], t_new, dt)
-        loc = int(np.nonzero(g == e)[0][0])
-        out[:, j] = R[:, loc]
+        Q, g, loc = _patch(P, int(e))
+        out[:, j] = odg.residual(Q, u[:, g], m_old[:, g], t_new, dt)[:, loc]
     return out
+
+
+def oracle_jvp_condensed_at(P, u, v7, m_old, t_new, dt, elems):
+    """Oracle condensed tangent (7 fields) of the listed elements, each on
+    the 3x3x3 patch around it (its rows depend on itself and its face
+    neighbours; the condensation is node-local)."""
+    out = np.zeros((7, len(elems), u.shape[2]))
+    for j, e in enumerate(elems):
+        Q, g, loc = _patch(P, int(e))
+        out[:, j] = odg.jvp_condensed(Q, u[:, g], v7[:, g], m_old[:, g], t_new, dt)[:, loc]
+    return out
+
+
+def oracle_blocks_at(P, u, m_old, t_new, dt, elems):
+    """Oracle condensed element blocks (56 x 56) of the listed elements,
+    each on the 3x3x3 patch around it."""
+    from oracle import solve as osolve
+    out = []
+    for e in elems:
+        Q, g, loc = _patch(P, int(e))
+        B = osolve.element_blocks(Q, u[:, g], m_old[:, g], t_new, dt, fields=range(7), condensed=True)
+        out.append(B[loc])
+    return np.stack(out)
+
+
+def slab_state(P, mask, seed):
+    """Seeded positive state around the equilibrium values for a large mesh
+    (9 fields, FP64, CPU torch tensor); no solid in pore voxels."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    Ne, npn = P.n_elem, P.n_nodes
+    typical = [1500.0, 6.0, 6.2e-3, 3.9e-3, 1.9e-3, 3.6e-12, 0.0, 0.2375, 6.9e-6]
+    u = torch.empty((9, Ne, npn), dtype=torch.float64)
+    for f in range(9):
+        z = torch.randn((Ne, npn), generator=g, dtype=torch.float64)
+        u[f] = 5e-3 * z if f == 6 else typical[f] * torch.exp(0.1 * z)
+    u[7:9, torch.tensor(mask.reshape(-1) == 0), :] = 0.0
+    return u
+
+
+def sampled_voxels(w, n, seed):
+    """Corner, edge and separator voxels of workload w's mesh plus n random ones."""
+    Ne = w.nx * w.ny * w.nz
+    rng = np.random.default_rng(seed)
+    corners = [0, w.nx - 1, (w.ny - 1) * w.nx, Ne - 1, Ne - w.nx, w.nx * w.ny * (w.nz // 2) + w.nx - 1]
+    return np.concatenate([corners, rng.integers(0, Ne, n)])

@@ -99,3 +99,28 @@ def test_bf16_apply_needs_an_fp32_setup():
     ctx.blockjacobi_setup(torch.tensor(u, device=dev), 0.9, 0.05)       # FP64 setup
     with pytest.raises(lsbdg.DgError, match="DG_ESTATE"):
         ctx.blockjacobi_apply(x, bf16=True)
+
+
+def test_blocks_full_slab_sampled():
+    """FP32 element blocks of the 96 x 96 x 192 slab as the solver builds
+    them; the apply at sampled voxels, boundaries included, inverts the
+    oracle's blocks of the same FP32-rounded state."""
+    from synth import WORKLOADS
+    from tests.helpers import oracle_blocks_at, sampled_voxels, slab_state
+    w = WORKLOADS["slab96_q1"]
+    print(f"[bj] full slab {w.nx}x{w.ny}x{w.nz}, FP32 blocks", flush=True)
+    P, ctx, mask = problem_and_context(w.nx, w.ny, w.nz, porosity=w.porosity,
+                                       mask_seed=w.mask_seed, param_seed=w.param_seed, f_C=w.f_C)
+    u = slab_state(P, mask, 21).to(torch.float32)
+    dev = torch.device("cuda:0")
+    ud = u.to(dev)
+    ctx.blockjacobi_setup(ud, 0.7, 0.05)
+    g = torch.Generator(device="cpu").manual_seed(22)
+    x = torch.randn((7, P.n_elem, P.n_nodes), generator=g, dtype=torch.float32)
+    y = ctx.blockjacobi_apply(x.to(dev)).cpu().numpy().astype(np.float64)
+    elems = sampled_voxels(w, 14, 2)
+    u64 = u.numpy().astype(np.float64)
+    Bor = oracle_blocks_at(P, u64, odg.old_mass(P, u64), 0.7, 0.05, elems)
+    err = _backward_error(Bor, y[:, elems], x.numpy().astype(np.float64)[:, elems])
+    print(f"  sampled backward error {err:.2e}", flush=True)
+    assert err < 2e-5

@@ -79,3 +79,31 @@ def test_linearized_jvp_equals_condensed(dtype):
     ctx.linearize(u, 0.7, 0.02)
     b = ctx.jvp(u, v, 0.7, 0.02, linearized=True)
     assert torch.equal(a, b)
+
+
+def test_krylov_jvp_full_slab_sampled():
+    """The Krylov operator as the solver and the benchmark launch it: FP32
+    condensed tangent at a stored linearisation on the 96 x 96 x 192 slab
+    (99 M DoF); sampled voxels, boundaries included, against the oracle's
+    condensed tangent of the same FP32-rounded inputs."""
+    from synth import WORKLOADS
+    from tests.helpers import oracle_jvp_condensed_at, sampled_voxels, slab_state
+    w = WORKLOADS["slab96_q1"]
+    print(f"[jvp] full slab {w.nx}x{w.ny}x{w.nz}, FP32 linearised", flush=True)
+    P, ctx, mask = problem_and_context(w.nx, w.ny, w.nz, porosity=w.porosity,
+                                       mask_seed=w.mask_seed, param_seed=w.param_seed, f_C=w.f_C)
+    u = slab_state(P, mask, 11).to(torch.float32)
+    g = torch.Generator(device="cpu").manual_seed(12)
+    scale = torch.tensor([1500, 6, 6e-3, 4e-3, 2e-3, 4e-12, 3e-3], dtype=torch.float32)
+    v = scale[:, None, None] * torch.randn((7, P.n_elem, P.n_nodes), generator=g, dtype=torch.float32)
+    dev = torch.device("cuda:0")
+    ud, vd = u.to(dev), v.to(dev)
+    ctx.linearize(ud, 0.7, 0.05)
+    jv = ctx.jvp(ud, vd, 0.7, 0.05, linearized=True).cpu().numpy().astype(np.float64)
+    elems = sampled_voxels(w, 40, 1)
+    u64, v64 = u.numpy().astype(np.float64), v.numpy().astype(np.float64)
+    m = odg.old_mass(P, u64)        # does not enter the tangent
+    ref = oracle_jvp_condensed_at(P, u64, v64, m, 0.7, 0.05, elems)
+    err = field_errors(jv[:, elems], ref)
+    print("  sampled field errors", err, flush=True)
+    assert np.all(err < TOL32), err
