@@ -16,7 +16,7 @@
  * are the Tradeoff Chemistry of Tab. 3 with Butler-Volmer kinetics
  * (Eq. 05-06, 18-24).  Space: interior-penalty DG with harmonic-mean
  * coefficients (Eq. 43-47) on tensor-product Gauss-Legendre nodes of degree
- * k in {0, 1} per axis; time: backward Euler (Eq. 50).  The separator face
+ * k = 1 per axis (Q1, 8 nodes per voxel); time: backward Euler (Eq. 50).  The separator face
  * x = L_x receives the Li+ flux j_el/F and the ionic current j_el; all other
  * faces are no-flux (Eq. 47 with the paper's galvanostatic condition).
  *
@@ -24,7 +24,10 @@
  *     f  field index (9 for a state, 7 for Krylov vectors, 8 for old mass)
  *     e  = ix + nx*(iy + ny*iz)            (x fastest)
  *     n  = a0 + K*(a1 + K*a2), K = k + 1   (x fastest within the voxel)
- * in the precision selected per call (double for DG_F64, float for DG_F32).
+ * in the precision selected per call (double for DG_F64, float for DG_F32;
+ * dg_blockjacobi_apply_bf16 streams bfloat16 copies of FP32 block inverses).
+ * Batches of several structures (dg_batch_*) concatenate them voxel by
+ * voxel in the same layout.
  *
  * Ownership: the caller owns every array passed in (state, residual and
  * vector buffers, on the device unless stated).  The library allocates its
