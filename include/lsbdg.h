@@ -178,8 +178,12 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
  * copy of the stored inverses (each entry rounded to nearest even; made on
  * the first call after a setup and kept, Ne * 56 * 56 * 2 bytes): y_e =
  * bf16(B_e^{-1}) x_e with FP32 accumulation.  This is the preconditioner
- * apply of FP32 inner solves with block_bf16.  x, y: device, FP32, 7 fields,
- * not overlapping.  DG_ESTATE unless the last setup was DG_F32. */
+ * apply of FP32 inner solves with block_bf16; such solves (dg_step,
+ * dg_initial_state, dg_advance) invert their blocks straight into the
+ * bfloat16 copy, which this call then applies, and leave no FP32 inverses
+ * (dg_blockjacobi_apply then needs a new setup).  x, y: device, FP32,
+ * 7 fields, not overlapping.  DG_ESTATE without an FP32 setup or such a
+ * solve before. */
 int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream);
 
 /* Copy the stored inverse blocks (Ne blocks of 56 x 56, column-major:

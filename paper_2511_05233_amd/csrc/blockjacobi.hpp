@@ -194,11 +194,24 @@ __device__ __forceinline__ int wave_argmax(float key, int lane) {
   return l;
 }
 
+// bfloat16 copy of FP32 inverses for the apply (half the bytes; only the
+// preconditioner changes, not the solution): entry (row, col) at
+// ((col / 8) * NB + row) * 8 + col % 8, rounded to nearest even.
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
 // In-place inversion of every element block (see header comment).  A block
-// whose best available pivot is zero or not finite sets *status = 1.
-template <typename S, int NB>
+// whose best available pivot is zero or not finite sets *status = 1.  With
+// kToBf16 (S = float) the inverse goes to H in the bfloat16 layout of
+// blocks_to_bf16_kernel instead, and B keeps the assembled blocks.
+template <typename S, int NB, bool kToBf16 = false>
 __global__ void __launch_bounds__(256)
-invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status) {
+invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status,
+                     uint16_t* __restrict__ H = nullptr) {
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t e = int64_t(blockIdx.x) * 4 + w;
@@ -236,7 +249,11 @@ invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status) {
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
     const int pm = __builtin_amdgcn_readlane(mypiv, m);
-    if (act) Be[quad_index<NB>(kk, pm)] = r[m];
+    if constexpr (kToBf16) {
+      if (act) H[e * int64_t(NB) * NB + ((pm >> 3) * NB + kk) * 8 + (pm & 7)] = to_bf16(float(r[m]));
+    } else {
+      if (act) Be[quad_index<NB>(kk, pm)] = r[m];
+    }
   }
 }
 
@@ -279,16 +296,6 @@ apply_blocks_kernel(const S* __restrict__ B, const S* __restrict__ X, S* __restr
     acc += q.d * bcast(xl, 4 * c4 + 3);
   }
   if (act) Y[fl * FS + e * 8 + nl] = acc;
-}
-
-// bfloat16 copy of FP32 inverses for the apply (half the bytes; only the
-// preconditioner changes, not the solution): entry (row, col) at
-// ((col / 8) * NB + row) * 8 + col % 8, rounded to nearest even.
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
 }
 
 template <int NB>

@@ -172,8 +172,10 @@ namespace {
 
 // Build and invert the condensed element blocks of precision S at uS
 // (needs the linearisation at uS).
+// bf16_only (S = float): the inverses go straight to the bfloat16 copy, and
+// the FP32 storage keeps the assembled blocks (not usable as inverses).
 template <typename S>
-int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
+int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st, bool bf16_only = false) {
   const size_t need = size_t(ctx->Ne) * 56 * 56 * sizeof(S);
   if (ctx->blocks_bytes < need) {
     if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
@@ -195,13 +197,28 @@ int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
   const dim3 grid_w{unsigned((ctx->Ne + 3) / 4), 1, 1};
   hipLaunchKernelGGL((q1_block_kernel<S, kJvpCondensed>), grid, block, 0, st, uS, ctx->lin.as<S>(),
                      static_cast<S*>(ctx->d_blocks), ctx->d_phase, P, nb);
-  hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), grid_w, block, 0, st, static_cast<S*>(ctx->d_blocks),
-                     ctx->Ne, ctx->d_status);
+  ctx->bh_valid = false;
+  if constexpr (std::is_same<S, float>::value) {
+    if (bf16_only) {
+      hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * 56 * 56 * 2);
+      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("bf16 blocks: ") + hipGetErrorString(e));
+      hipLaunchKernelGGL((invert_blocks_kernel<float, 56, true>), grid_w, block, 0, st,
+                         static_cast<float*>(ctx->d_blocks), ctx->Ne, ctx->d_status, ctx->bh.as<uint16_t>());
+    }
+  }
+  if (!bf16_only)
+    hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), grid_w, block, 0, st, static_cast<S*>(ctx->d_blocks),
+                       ctx->Ne, ctx->d_status, nullptr);
   DG_HIP(hipGetLastError());
   int h_status = 0;
   DG_HIP(hipMemcpyAsync(&h_status, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
   DG_HIP(hipStreamSynchronize(st));
-  ctx->blocks_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  if (bf16_only) {
+    ctx->blocks_prec = -1;                     // FP32 storage holds no inverses
+    ctx->bh_valid = true;
+  } else {
+    ctx->blocks_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  }
   if (h_status) return fail(DG_ENAN, "singular or non-finite element block");
   return DG_OK;
 }
@@ -454,15 +471,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     r.newton_its = it;
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
     if (int s = linearize<S>(ctx, P, uS, st)) return s;
-    if (int s = blocks_setup<S>(ctx, P, uS, st)) return s;
-    ctx->bh_valid = false;
-    if (std::is_same<S, float>::value && o.block_bf16) {
-      hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * 56 * 56 * 2);
-      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("bf16 blocks: ") + hipGetErrorString(e));
-      hipLaunchKernelGGL((blocks_to_bf16_kernel<56>), dim3(8192), blk, 0, st,
-                         static_cast<const float*>(ctx->d_blocks), ctx->bh.as<uint16_t>(), ctx->Ne);
-      ctx->bh_valid = true;
-    }
+    // FP32 inner solves with block_bf16 use only the bfloat16 inverses
+    if (int s = blocks_setup<S>(ctx, P, uS, st, std::is_same<S, float>::value && o.block_bf16 != 0)) return s;
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
     // the aggregation coarse operator is rebuilt at the first iterate, after
     // an update whose largest relative change of an unknown exceeded 2 (E
@@ -1135,7 +1145,8 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
 int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
   if (!x || !y) return fail(DG_EINVAL, "dg_blockjacobi_apply_bf16: null array");
-  if (ctx->blocks_prec != DG_F32) return fail(DG_ESTATE, "dg_blockjacobi_apply_bf16: no FP32 setup");
+  if (!ctx->bh_valid && ctx->blocks_prec != DG_F32)
+    return fail(DG_ESTATE, "dg_blockjacobi_apply_bf16: no FP32 setup");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!ctx->bh_valid) {
     hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * kNB * kNB * 2);

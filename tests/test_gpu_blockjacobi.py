@@ -124,3 +124,24 @@ def test_blocks_full_slab_sampled():
     err = _backward_error(Bor, y[:, elems], x.numpy().astype(np.float64)[:, elems])
     print(f"  sampled backward error {err:.2e}", flush=True)
     assert err < 2e-5
+
+
+def test_solver_leaves_bf16_inverses_only():
+    """An FP32 inner solve with block_bf16 (the default) inverts its blocks
+    straight into the bfloat16 copy: after dg_step the bfloat16 apply works
+    and gives finite values, the FP32 apply needs a new setup, and a setup
+    restores both."""
+    from paper_2511_05233_amd import lsbdg
+    P, ctx, mask = problem_and_context(5, 4, 3, mask_seed=1, param_seed=1, f_C=0.1)
+    dev = torch.device("cuda:0")
+    u, _ = ctx.initial_state(inner="f32")
+    ctx.step(u, 0.0, 0.1, inner="f32")
+    x = torch.tensor(synth.random_vector(7, P.n_elem, P.n_nodes, 720), device=dev, dtype=torch.float32)
+    y = ctx.blockjacobi_apply(x, bf16=True)
+    assert bool(torch.isfinite(y).all()) and float(y.abs().max()) > 0
+    with pytest.raises(lsbdg.DgError, match="DG_ESTATE"):
+        ctx.blockjacobi_apply(x)
+    ctx.blockjacobi_setup(u.to(torch.float32), 0.1, 0.1)
+    y32 = ctx.blockjacobi_apply(x)
+    yh = ctx.blockjacobi_apply(x, bf16=True)
+    assert float((yh - y32).abs().max() / y32.abs().max()) < 1e-2
