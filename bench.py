@@ -2,7 +2,8 @@
 
     python bench.py [--steps K] [--warmup W] [--mode newton|controller] [--dt S]
                     [--inner f32|f64] [--workload slab96_q1] [--compare-f64]
-                    [--no-cpu-baseline] [--no-c3] [--kernels-only] [--copy-probe]
+                    [--no-cpu-baseline] [--no-mixed] [--no-batch] [--kernels-only] [--copy-probe]
+                    [--batch] [--fp32-blocks]
                     [--discharge WORKLOAD [--discharge-rate C]]
 
 Workload (default): the 96 x 96 x 192 voxel cathode slab (x = transport
@@ -31,7 +32,7 @@ iteration (the block apply of the solver, by default from bfloat16
 inverses: one per GMRES iteration) against the HBM peak; the other kernels
 are listed beside it.
 
-Beside the line (skipped with --no-c3): five steps on the 16^3 cube and a
+Beside the line (skipped with --no-mixed): five steps on the 16^3 cube and a
 full 1C discharge of it to the 1.9 V cutoff, each with FP64 and with mixed
 (FP32 inner) solves -- wall times, speedup and the difference of the results.
 """
@@ -216,8 +217,9 @@ def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0, coarse_
 
 
 def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
-    """Row C3: 5 backward-Euler steps on the 16^3 cube with FP64 and with
-    mixed (FP32 inner) solves from the same GPU initial state."""
+    """Mixed precision against FP64: 5 backward-Euler steps on the 16^3 cube
+    with FP64 and with mixed (FP32 inner) solves from the same GPU initial
+    state."""
     import torch
     import synth
     from paper_2511_05233_amd import lsbdg
@@ -240,7 +242,7 @@ def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
         res[inner] = (time.perf_counter() - t0, u, its)
     rel = [float(torch.linalg.norm(res["f32"][1][f] - res["f64"][1][f]) /
                  torch.clamp(torch.linalg.norm(res["f64"][1][f]), min=1e-300)) for f in range(9)]
-    log(f"[bench] C3: f64 {res['f64'][0]:.3f} s, mixed {res['f32'][0]:.3f} s")
+    log(f"[bench] five 16^3 steps: f64 {res['f64'][0]:.3f} s, mixed {res['f32'][0]:.3f} s")
     return {"workload": "cube16_q1: 16^3 voxels, 0.1C, 5 backward-Euler steps of 0.1 s from the initial state",
             "s_f64": round(res["f64"][0], 4), "s_mixed": round(res["f32"][0], 4),
             "mixed_speedup": round(res["f64"][0] / res["f32"][0], 3),
@@ -306,7 +308,7 @@ def discharge_mixed_vs_f64(workload, f_C, coarse, coarse_agg, log):
 
 
 def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
-    """Row a13 (batching) on the batch workload: n cubic structures with
+    """Batching on the batch workload: n cubic structures with
     edges ~ U{24..64} voxels and porosities ~ U(0.4, 0.75) (seeded), each
     with its own kinetics draw.  Every operator runs as one launch over all
     structures; the same work as one launch per structure is timed beside
@@ -498,7 +500,7 @@ def main(argv=None):
     ap.add_argument("--compare-f64", action="store_true",
                     help="repeat the timed steps with an FP64 inner solve from the same state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-c3", action="store_true",
+    ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 comparisons on the 16^3 cube (5 steps and a full 1C discharge)")
     ap.add_argument("--verbose", type=int, default=0, help="Newton progress lines on stderr")
     ap.add_argument("--kernels-only", action="store_true",
@@ -519,7 +521,7 @@ def main(argv=None):
     if args.fp32_blocks:
         SOLVER_EXTRA["block_bf16"] = 0
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path; "
+        print("bench.py measures one GPU: the library has no multi-GPU path; "
               "run with --gpus 1.", file=sys.stderr)
         return 2
 
@@ -637,7 +639,7 @@ def main(argv=None):
                             "newton_its": tot64["newton_its"], "gmres_its": tot64["gmres_its"],
                             "mixed_speedup": round(wall64 / wall, 3),
                             "rel_l2_mixed_vs_f64": [float(f"{x:.3e}") for x in rel]}
-    if not args.no_c3:
+    if not args.no_mixed:
         out["mixed_vs_f64"] = mixed_vs_f64(args.coarse, log)
         out["discharge_mixed_vs_f64"] = discharge_mixed_vs_f64("cube16_q1", 1.0, args.coarse, 0, log)
     if not args.no_batch:
