@@ -383,6 +383,31 @@ def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
     ms_jvp_g = time_launches(graph.replay, stream, reps)
     graph_same = all(torch.equal(ys[s], ref[s]) for s in range(n))
     del graph
+    # the autotuner: every launch shape of the residual and both tangents in
+    # FP32 (the Krylov operator) and FP64 (the Newton residual), then the
+    # batched calls again in the chosen shapes (same values as before)
+    y_def, r_def = y7.clone(), r9.clone()
+    v9 = torch.randn((9, E, 8), generator=g, dtype=torch.float32, device=dev)
+    tune32, ncand = B.autotune(u32, v9, m8.float(), tt, dd, reps=reps)
+    v9 = v9.double()
+    tune64, _ = B.autotune(u64, v9, m8, tt, dd, reps=reps)
+    del v9
+    torch.cuda.empty_cache()
+    B.linearize(u32, tt, dd)
+    ms_jvp_t = time_launches(lambda: B.jvp(u32, v7, tt, dd, out=y7, linearized=True), stream, reps)
+    ms_res_t = time_launches(lambda: B.residual(u64, m8, tt, dd, out=r9), stream, reps)
+    tuned_same = bool(torch.equal(y7, y_def) and torch.equal(r9, r_def))
+    del y_def, r_def
+
+    def tuned(tune):
+        return {op: {"shape": {"tile_voxels": sh[0], "persistent_per_cu": sh[1]}, "ms": round(ms, 3),
+                     "ms_default": round(md, 3)} for op, (sh, ms, md) in tune.items()}
+
+    autotune = {"shapes_per_operator": ncand, "f32": tuned(tune32), "f64": tuned(tune64),
+                "jvp_f32_ms_tuned": round(ms_jvp_t, 3), "residual_f64_ms_tuned": round(ms_res_t, 3),
+                "tuned_equals_default": tuned_same}
+    log(f"[bench] batch autotune: JVP {ms_jvp_t:.3f} ms in {tune32['jvp_condensed'][0]}, residual "
+        f"{ms_res_t:.3f} ms in {tune64['residual'][0]}")
     dof = E * 56
     b_apply = E * (56 * 56 + 2 * 56) * 4
     ms_setup_b = ms_apply_b = None
@@ -415,6 +440,7 @@ def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
         "max_rel_diff_batched_vs_per_structure": {"jvp_f32": float(f"{diff_jvp:.3e}"),
                                                   "residual_f64": float(f"{diff_res:.3e}")},
         "graph_replay_equals_eager": bool(graph_same),
+        "autotune": autotune,
         "implicit_step": solve,
     }
     if not full:

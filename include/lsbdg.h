@@ -352,7 +352,8 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u, const dg_solve
  * structures voxel by voxel in the field-major layout a[f][E][n]: E is the
  * total voxel count, structure s owns voxels [off[s], off[s+1]) in its own
  * x-fastest order, n = 0..7 the Q1 node.  Every operator runs as one launch
- * over work items of 32 voxels of one structure and gives, structure by
+ * over work items of 32 voxels of one structure (the residual and tangents
+ * in a tunable shape: dg_batch_shape) and gives, structure by
  * structure, the values of the single-structure call (dg_mass, dg_residual,
  * dg_jvp, dg_linearize, dg_blockjacobi_*) on that structure's slice.
  * t_new and dt are HOST arrays of n values (each structure steps on its own
@@ -403,6 +404,55 @@ int dg_batch_blockjacobi_setup(dg_batch* b, dg_prec prec, const void* u, const d
 /* y = B^-1 x for every voxel of the batch (7 x E x 8, precision of the
  * setup).  DG_ESTATE before a setup. */
 int dg_batch_blockjacobi_apply(dg_batch* b, dg_prec prec, const void* x, void* y, dg_stream stream);
+
+/* Launch shapes of the batched residual and tangents.  A work item is a
+ * tile of tile_voxels voxels of one structure (8 lanes per voxel, so 64,
+ * 128 or 256 lanes per workgroup).  persistent = 0 launches one workgroup
+ * per work item; persistent = k > 0 launches k workgroups per compute unit
+ * (rounded down to a multiple of 8, at least 8, at most one per work item),
+ * each looping over work items in a fixed stride, so every workgroup ends.
+ * The shape changes only which workgroup computes a node: results are the
+ * same in every shape.  Default: {32, 0}, unless dg_batch_autotune has run
+ * in this process on a batch of the same precision and size class (the bit
+ * length of E), whose choice a new batch starts from. */
+typedef struct dg_batch_shape {
+  int32_t tile_voxels; /* 8, 16 or 32 */
+  int32_t persistent;  /* 0, or workgroups per compute unit in [1, 64] */
+} dg_batch_shape;
+
+/* Batched operators whose launch shape is tunable. */
+typedef enum dg_batch_op {
+  DG_BOP_RESIDUAL = 0,      /* dg_batch_residual */
+  DG_BOP_JVP_FULL9 = 1,     /* dg_batch_jvp, DG_JVP_FULL9 */
+  DG_BOP_JVP_CONDENSED7 = 2 /* dg_batch_jvp, DG_JVP_CONDENSED7 and DG_JVP_LINEARIZED7 */
+} dg_batch_op;
+
+typedef struct dg_batch_tuning {
+  dg_batch_shape shape[3]; /* chosen shape, by dg_batch_op */
+  double ms[3];            /* mean time per launch in that shape */
+  double ms_default[3];    /* mean time per launch in the default shape {32, 0} */
+  int32_t candidates;      /* shapes timed per operator (6, or 3 without occupancy data) */
+  int32_t pad;
+} dg_batch_tuning;
+
+/* Set or read the launch shape of operator op (a dg_batch_op) in precision
+ * prec.  DG_EINVAL for an unknown op or precision, tile_voxels outside
+ * {8, 16, 32} or persistent outside [0, 64]. */
+int dg_batch_set_shape(dg_batch* b, dg_prec prec, int32_t op, const dg_batch_shape* shape);
+int dg_batch_get_shape(const dg_batch* b, dg_prec prec, int32_t op, dg_batch_shape* shape);
+
+/* Autotuner: times the three tunable operators on these arrays in every
+ * launch shape (tile sizes 8, 16 and 32, each with one workgroup per work
+ * item and as a persistent grid at the occupancy the compiled kernel
+ * allows), reps launches each after one warm-up (reps <= 0: 5; at most
+ * 1000), keeps the fastest shape per operator for this batch and for later
+ * batches of its precision and size class, and fills report.  u, v: device,
+ * 9 x E x 8 (the condensed tangent reads v's first 7 fields); m_old: device,
+ * 8 x E x 8; work: device, 9 x E x 8, overwritten.  Leaves the batch
+ * linearisation at u.  Synchronises the stream. */
+int dg_batch_autotune(dg_batch* b, dg_prec prec, const void* u, const void* v, const void* m_old,
+                      const double* t_new, const double* dt, void* work, int32_t reps,
+                      dg_batch_tuning* report, dg_stream stream);
 
 /* Initial state (as dg_initial_state, at t0[s]) of every structure into the
  * batch state u (device, FP64, 9 x E x 8).  The structures' solves run side

@@ -28,7 +28,21 @@ struct BatchTile {
   int64_t base;    // first voxel of the structure in the concatenation
 };
 
-constexpr int kTileVoxels = 32;   // 256 lanes / 8 nodes
+constexpr int kTileVoxels = 32;   // 256 lanes / 8 nodes: the default work item
+
+// Work-item sizes the batched residual and tangents can be launched with
+// (8 lanes per voxel: 64, 128 or 256 lanes).  The batch keeps one tile list
+// per size; the size and whether the grid is persistent are chosen per
+// operator and precision (the library's autotuner times them all).
+constexpr int kTileChoices[3] = {8, 16, 32};
+
+// Position `i` of a padded grid in XCD-aware order (as xcd_block).  A
+// persistent grid strides by a multiple of 8 workgroups, so every pass of a
+// workgroup stays within the voxel range of the XCD it was dispatched to.
+__device__ __forceinline__ int64_t xcd_order(int64_t i, int64_t nblocks_padded) {
+  const int64_t per = nblocks_padded / 8;
+  return (i % 8) * per + i / 8;
+}
 
 // The tile of this workgroup (XCD-aware order) and the lane's voxel within
 // its structure; false for lanes past the structure's last voxel and for
@@ -47,36 +61,59 @@ __device__ __forceinline__ bool batch_lane(const BatchTile* __restrict__ tiles, 
 template <typename S>
 __device__ __forceinline__ const S* shift(const S* p, int64_t o) { return p ? p + o : p; }
 
+// Residual or tangent of the work items of this workgroup.  One-shot grid
+// (a workgroup per item, gridDim.x = nblocks_padded): one item.  Persistent
+// grid (gridDim.x a smaller multiple of 8): items blockIdx.x, blockIdx.x +
+// gridDim.x, ... -- bounds fixed at launch, so every workgroup exits.  The
+// two forms are separate kernels: the loop's own registers would push the
+// FP64 residual past 256 and halve its occupancy in the one-shot form.
 template <typename S, typename N, int Mode>
+__device__ __forceinline__ void q1_batch_item(const S* __restrict__ U, const S* __restrict__ V,
+                                              const S* __restrict__ M, S* __restrict__ Out,
+                                              const uint8_t* __restrict__ phase,
+                                              const DevParams* __restrict__ Ps,
+                                              const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS,
+                                              int64_t nblocks_padded, int64_t i) {
+  const int64_t blk = xcd_order(i, nblocks_padded);
+  if (blk >= ntiles) return;
+  const BatchTile t = tiles[blk];
+  const DevParams* P = Ps + t.s;
+  const int64_t e = int64_t(t.v0) + (threadIdx.x >> 3);
+  if (e >= P->Ne) return;                    // whole 8-lane groups leave together
+  const int64_t o = t.base * 8;
+  q1_node<S, N, Mode>(U + o, shift(V, o), shift(M, o), Out + o, phase + t.base, *P, e, int(threadIdx.x & 7), FS);
+}
+
+template <typename S, typename N, int Mode, bool kPersistent>
 __device__ __forceinline__ void q1_batch_body(const S* __restrict__ U, const S* __restrict__ V,
                                               const S* __restrict__ M, S* __restrict__ Out,
                                               const uint8_t* __restrict__ phase,
                                               const DevParams* __restrict__ Ps,
                                               const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS,
                                               int64_t nblocks_padded) {
-  BatchTile t;
-  const DevParams* P;
-  int64_t e;
-  if (!batch_lane(tiles, ntiles, nblocks_padded, Ps, t, P, e)) return;
-  const int64_t o = t.base * 8;
-  q1_node<S, N, Mode>(U + o, shift(V, o), shift(M, o), Out + o, phase + t.base, *P, e, int(threadIdx.x & 7), FS);
+  if constexpr (kPersistent) {
+    for (int64_t i = blockIdx.x; i < nblocks_padded; i += gridDim.x)
+      q1_batch_item<S, N, Mode>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded, i);
+  } else {
+    q1_batch_item<S, N, Mode>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded, blockIdx.x);
+  }
 }
 
-template <typename S, typename N, int Mode>
-__global__ void __launch_bounds__(256)
+template <typename S, typename N, int Mode, int kLanes, bool kPersistent>
+__global__ void __launch_bounds__(kLanes)
 q1_batch_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M, S* __restrict__ Out,
                 const uint8_t* __restrict__ phase, const DevParams* __restrict__ Ps,
                 const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS, int64_t nblocks_padded) {
-  q1_batch_body<S, N, Mode>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded);
+  q1_batch_body<S, N, Mode, kPersistent>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded);
 }
 
 // As q1_kernel_w2: the FP32 tangent held to two waves per SIMD.
-template <typename S, typename N, int Mode>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename S, typename N, int Mode, int kLanes, bool kPersistent>
+__global__ void __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2)))
 q1_batch_kernel_w2(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
                    S* __restrict__ Out, const uint8_t* __restrict__ phase, const DevParams* __restrict__ Ps,
                    const BatchTile* __restrict__ tiles, int64_t ntiles, int64_t FS, int64_t nblocks_padded) {
-  q1_batch_body<S, N, Mode>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded);
+  q1_batch_body<S, N, Mode, kPersistent>(U, V, M, Out, phase, Ps, tiles, ntiles, FS, nblocks_padded);
 }
 
 // Element blocks of every structure (Bout: E blocks of nb x nb).

@@ -11,10 +11,13 @@
 #include <cstring>
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -788,7 +791,11 @@ struct dg_batch {
   int64_t E = 0;                       // total voxels
   int64_t ntiles = 0;
   uint8_t* d_phase = nullptr;
-  BatchTile* d_tiles = nullptr;
+  BatchTile* d_tiles = nullptr;        // 32-voxel work items (= d_tiles_by[2])
+  BatchTile* d_tiles_by[3] = {};       // work items of kTileChoices[i] voxels
+  int64_t ntiles_by[3] = {};
+  dg_batch_shape shape[2][3];          // launch shape by precision and operator (dg_batch_op)
+  int n_cu = 0;                        // compute units of the device
   DevParams* d_params = nullptr;
   DevParams* h_params = nullptr;       // pinned staging of d_params
   hipEvent_t staged = nullptr;         // recorded after each upload of h_params
@@ -819,19 +826,97 @@ int batch_params(dg_batch* b, const double* t_new, const double* dt, bool step, 
 
 int64_t batch_grid(const dg_batch* b) { return (b->ntiles + 7) / 8 * 8; }
 
+// Launch shapes chosen by dg_batch_autotune, kept for the process by
+// precision, operator and size class (the bit length of the voxel count);
+// batches set up later in the same class start from them.
+std::mutex g_shape_mu;
+std::map<std::tuple<int, int, int>, dg_batch_shape> g_shape_cache;
+
+int size_class(int64_t E) {
+  int c = 0;
+  while (E >>= 1) ++c;
+  return c;
+}
+
+constexpr dg_batch_shape kDefaultShape{kTileVoxels, 0};
+
+template <typename S>
+constexpr int prec_index() { return std::is_same<S, double>::value ? DG_F64 : DG_F32; }
+
+template <int Mode>
+constexpr int op_index() {
+  return Mode == kResidual ? DG_BOP_RESIDUAL : Mode == kJvpFull ? DG_BOP_JVP_FULL9 : DG_BOP_JVP_CONDENSED7;
+}
+
+template <typename S, typename N, int Mode, int kLanes, bool kPersistent>
+const void* q1_batch_symbol() {
+  if constexpr (std::is_same<S, float>::value && Mode != kResidual)
+    return reinterpret_cast<const void*>(&q1_batch_kernel_w2<S, N, Mode, kLanes, kPersistent>);
+  else
+    return reinterpret_cast<const void*>(&q1_batch_kernel<S, N, Mode, kLanes, kPersistent>);
+}
+
+// One launch of a batched residual or tangent in tiles of kLanes / 8
+// voxels.  persistent > 0: that many workgroups per compute unit (at least
+// 8 and at most one per work item, a multiple of 8), each striding over the
+// work items; 0: one workgroup per work item.
+template <typename S, typename N, int Mode, int kLanes>
+void launch_q1_batch_lanes(const dg_batch* b, int persistent, const void* u, const void* v, const void* m,
+                           void* out, hipStream_t st) {
+  constexpr int ti = kLanes == 64 ? 0 : kLanes == 128 ? 1 : 2;
+  static_assert(kTileChoices[ti] * 8 == kLanes, "tile size and workgroup size disagree");
+  const int64_t nt = b->ntiles_by[ti];
+  const int64_t nb = (nt + 7) / 8 * 8;
+  int64_t grid = nb;
+  if (persistent > 0) grid = std::min(nb, std::max<int64_t>(8, int64_t(persistent) * b->n_cu / 8 * 8));
+  const dim3 g{unsigned(grid), 1, 1}, blk{unsigned(kLanes), 1, 1};
+  const int64_t FS = b->E * 8;
+  using K = void (*)(const S*, const S*, const S*, S*, const uint8_t*, const DevParams*, const BatchTile*, int64_t,
+                     int64_t, int64_t);
+  const K kern = reinterpret_cast<K>(const_cast<void*>(
+      persistent > 0 ? q1_batch_symbol<S, N, Mode, kLanes, true>() : q1_batch_symbol<S, N, Mode, kLanes, false>()));
+  hipLaunchKernelGGL(kern, g, blk, 0, st, static_cast<const S*>(u), static_cast<const S*>(v),
+                     static_cast<const S*>(m), static_cast<S*>(out), b->d_phase, b->d_params, b->d_tiles_by[ti], nt,
+                     FS, nb);
+}
+
+template <typename S, typename N, int Mode>
+void launch_q1_batch_shape(const dg_batch* b, dg_batch_shape sh, const void* u, const void* v, const void* m,
+                           void* out, hipStream_t st) {
+  switch (sh.tile_voxels) {
+    case 8: launch_q1_batch_lanes<S, N, Mode, 64>(b, sh.persistent, u, v, m, out, st); break;
+    case 16: launch_q1_batch_lanes<S, N, Mode, 128>(b, sh.persistent, u, v, m, out, st); break;
+    default: launch_q1_batch_lanes<S, N, Mode, 256>(b, sh.persistent, u, v, m, out, st); break;
+  }
+}
+
+// Workgroups of tile_voxels * 8 lanes of the persistent kernel that one
+// compute unit holds at once (0 if the runtime cannot tell).
+template <typename S, typename N, int Mode>
+int q1_batch_resident(int tile_voxels) {
+  int n = 0;
+  hipError_t e;
+  switch (tile_voxels) {
+    case 8:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, q1_batch_symbol<S, N, Mode, 64, true>(), 64, 0);
+      break;
+    case 16:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, q1_batch_symbol<S, N, Mode, 128, true>(), 128, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, q1_batch_symbol<S, N, Mode, 256, true>(), 256, 0);
+      break;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
 template <typename S, typename N, int Mode>
 void launch_q1_batch(const dg_batch* b, const void* u, const void* v, const void* m, void* out, hipStream_t st) {
-  const int64_t nb = batch_grid(b);
-  const int64_t FS = b->E * 8;
-  const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
-  if constexpr (std::is_same<S, float>::value && Mode != kResidual)
-    hipLaunchKernelGGL((q1_batch_kernel_w2<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
-                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), b->d_phase,
-                       b->d_params, b->d_tiles, b->ntiles, FS, nb);
-  else
-    hipLaunchKernelGGL((q1_batch_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
-                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), b->d_phase,
-                       b->d_params, b->d_tiles, b->ntiles, FS, nb);
+  launch_q1_batch_shape<S, N, Mode>(b, b->shape[prec_index<S>()][op_index<Mode>()], u, v, m, out, st);
 }
 
 template <typename S>
@@ -1428,7 +1513,8 @@ int dg_batch_destroy(dg_batch* b) {
   if (!b) return DG_OK;
   for (dg_ctx* c : b->subs) dg_destroy(c);
   if (b->d_phase) (void)hipFree(b->d_phase);
-  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  for (BatchTile* t : b->d_tiles_by)
+    if (t) (void)hipFree(t);
   if (b->d_params) (void)hipFree(b->d_params);
   if (b->staged) {
     (void)hipEventSynchronize(b->staged);
@@ -1470,22 +1556,39 @@ int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phase
       b->off.push_back(b->off.back() + c->Ne);
     }
     b->E = b->off.back();
-    std::vector<BatchTile> tiles;
-    for (int s = 0; s < n; ++s)
-      for (int64_t v0 = 0; v0 < b->subs[s]->Ne; v0 += kTileVoxels)
-        tiles.push_back(BatchTile{int32_t(s), int32_t(v0), b->off[s]});
-    b->ntiles = int64_t(tiles.size());
+    std::vector<BatchTile> tiles[3];
+    for (int ti = 0; ti < 3; ++ti)
+      for (int s = 0; s < n; ++s)
+        for (int64_t v0 = 0; v0 < b->subs[s]->Ne; v0 += kTileChoices[ti])
+          tiles[ti].push_back(BatchTile{int32_t(s), int32_t(v0), b->off[s]});
     hipError_t e = hipMalloc(&b->d_phase, size_t(b->E));
-    if (e == hipSuccess) e = hipMalloc(&b->d_tiles, tiles.size() * sizeof(BatchTile));
+    for (int ti = 0; ti < 3 && e == hipSuccess; ++ti) {
+      b->ntiles_by[ti] = int64_t(tiles[ti].size());
+      e = hipMalloc(&b->d_tiles_by[ti], tiles[ti].size() * sizeof(BatchTile));
+    }
+    b->d_tiles = b->d_tiles_by[2];
+    b->ntiles = b->ntiles_by[2];
     if (e == hipSuccess) e = hipMalloc(&b->d_params, size_t(n) * sizeof(DevParams));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_params, size_t(n) * sizeof(DevParams));
     if (e != hipSuccess) return abandon(fail(DG_ENOMEM, std::string("dg_batch_setup: ") + hipGetErrorString(e)));
-    e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
     for (int s = 0; s < n && e == hipSuccess; ++s)
       e = hipMemcpy(b->d_phase + b->off[s], phases[s], size_t(b->subs[s]->Ne), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+    for (int ti = 0; ti < 3 && e == hipSuccess; ++ti)
+      e = hipMemcpy(b->d_tiles_by[ti], tiles[ti].data(), tiles[ti].size() * sizeof(BatchTile),
+                    hipMemcpyHostToDevice);
     if (e != hipSuccess) return abandon(fail(DG_EHIP, std::string("dg_batch_setup: ") + hipGetErrorString(e)));
+    {
+      std::lock_guard<std::mutex> lk(g_shape_mu);
+      for (int p = 0; p < 2; ++p)
+        for (int op = 0; op < 3; ++op) {
+          auto it = g_shape_cache.find({p, op, size_class(b->E)});
+          b->shape[p][op] = it == g_shape_cache.end() ? kDefaultShape : it->second;
+        }
+    }
     *out = b;
     return DG_OK;
   } catch (const std::bad_alloc&) {
@@ -1696,9 +1799,109 @@ int batch_workers(const dg_batch* b, int32_t workers) {
   return std::max(1, std::min(w, n));
 }
 
+// Times one batched operator in every launch shape (three tile sizes, each
+// with one workgroup per work item and as a persistent grid at the
+// occupancy the compiled kernel allows), keeps the fastest for the batch
+// and the process cache, and reports it with the default shape's time.
+template <typename S, typename N, int Mode>
+int tune_op(dg_batch* b, const void* u, const void* v, const void* m, void* work, int reps, hipEvent_t t0,
+            hipEvent_t t1, dg_batch_tuning* rep, hipStream_t st) {
+  constexpr int op = op_index<Mode>();
+  dg_batch_shape best = kDefaultShape;
+  double best_ms = INFINITY, def_ms = NAN;
+  int tried = 0;
+  for (int tv : kTileChoices) {
+    const int occ = q1_batch_resident<S, N, Mode>(tv);
+    const int forms = occ > 0 ? 2 : 1;             // occupancy unknown: no persistent form
+    for (int f = 0; f < forms; ++f) {
+      const dg_batch_shape sh{tv, f == 0 ? 0 : occ};
+      launch_q1_batch_shape<S, N, Mode>(b, sh, u, v, m, work, st);   // warm-up
+      DG_HIP(hipEventRecord(t0, st));
+      for (int r = 0; r < reps; ++r) launch_q1_batch_shape<S, N, Mode>(b, sh, u, v, m, work, st);
+      DG_HIP(hipGetLastError());
+      DG_HIP(hipEventRecord(t1, st));
+      DG_HIP(hipEventSynchronize(t1));
+      float ms = 0.f;
+      DG_HIP(hipEventElapsedTime(&ms, t0, t1));
+      const double per = double(ms) / reps;
+      if (sh.tile_voxels == kDefaultShape.tile_voxels && sh.persistent == 0) def_ms = per;
+      if (per < best_ms) {
+        best_ms = per;
+        best = sh;
+      }
+      tried += 1;
+    }
+  }
+  b->shape[prec_index<S>()][op] = best;
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape_cache[{prec_index<S>(), op, size_class(b->E)}] = best;
+  }
+  rep->shape[op] = best;
+  rep->ms[op] = best_ms;
+  rep->ms_default[op] = def_ms;
+  rep->candidates = tried;
+  return DG_OK;
+}
+
+template <typename S>
+int batch_autotune(dg_batch* b, const S* u, const S* v, const S* m_old, S* work, int reps, dg_batch_tuning* rep,
+                   hipStream_t st) {
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  int status = e == hipSuccess ? DG_OK : fail(DG_EHIP, std::string("dg_batch_autotune: ") + hipGetErrorString(e));
+  if (!status) status = tune_op<S, S, kResidual>(b, u, nullptr, m_old, work, reps, t0, t1, rep, st);
+  if (!status) status = tune_op<S, Dual<S>, kJvpFull>(b, u, v, nullptr, work, reps, t0, t1, rep, st);
+  if (!status) status = batch_linearize<S>(b, u, st);
+  if (!status) status = tune_op<S, Dual<S>, kJvpCondensed>(b, u, v, b->lin.p, work, reps, t0, t1, rep, st);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  return status;
+}
+
 }  // namespace
 
 extern "C" {
+
+int dg_batch_set_shape(dg_batch* b, dg_prec prec, int32_t op, const dg_batch_shape* shape) {
+  if (!b || !shape) return fail(DG_EINVAL, "dg_batch_set_shape: null argument");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_set_shape: bad precision");
+  if (op < 0 || op > 2) return fail(DG_EINVAL, "dg_batch_set_shape: bad operator");
+  const int tv = shape->tile_voxels;
+  if (std::find(std::begin(kTileChoices), std::end(kTileChoices), tv) == std::end(kTileChoices))
+    return fail(DG_EINVAL, "dg_batch_set_shape: tile_voxels must be 8, 16 or 32");
+  if (shape->persistent < 0 || shape->persistent > 64)
+    return fail(DG_EINVAL, "dg_batch_set_shape: persistent must be in [0, 64]");
+  b->shape[prec][op] = *shape;
+  return DG_OK;
+}
+
+int dg_batch_get_shape(const dg_batch* b, dg_prec prec, int32_t op, dg_batch_shape* shape) {
+  if (!b || !shape) return fail(DG_EINVAL, "dg_batch_get_shape: null argument");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_get_shape: bad precision");
+  if (op < 0 || op > 2) return fail(DG_EINVAL, "dg_batch_get_shape: bad operator");
+  *shape = b->shape[prec][op];
+  return DG_OK;
+}
+
+int dg_batch_autotune(dg_batch* b, dg_prec prec, const void* u, const void* v, const void* m_old,
+                      const double* t_new, const double* dt, void* work, int32_t reps, dg_batch_tuning* report,
+                      dg_stream stream) {
+  if (!b || !report) return fail(DG_EINVAL, "dg_batch_autotune: null argument");
+  if (!u || !v || !m_old || !work) return fail(DG_EINVAL, "dg_batch_autotune: null array");
+  if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_autotune: bad precision");
+  if (reps > 1000) return fail(DG_EINVAL, "dg_batch_autotune: reps above 1000");
+  const int r = reps > 0 ? reps : 5;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::memset(report, 0, sizeof(*report));
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_autotune")) return s;
+  return prec == DG_F64
+             ? batch_autotune<double>(b, static_cast<const double*>(u), static_cast<const double*>(v),
+                                      static_cast<const double*>(m_old), static_cast<double*>(work), r, report, st)
+             : batch_autotune<float>(b, static_cast<const float*>(u), static_cast<const float*>(v),
+                                     static_cast<const float*>(m_old), static_cast<float*>(work), r, report, st);
+}
 
 int dg_batch_initial_state(dg_batch* b, const double* t0, void* u, const dg_solver_opts* opts,
                            dg_step_report* reports, int32_t workers, dg_stream stream) {

@@ -63,6 +63,10 @@ _SIGNATURES = {
                                          C.c_void_p]),
     "dg_batch_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_void_p]),
+    "dg_batch_set_shape": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p]),
+    "dg_batch_get_shape": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p]),
+    "dg_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -94,6 +98,22 @@ class DgStepReport(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+DG_BOP_RESIDUAL, DG_BOP_JVP_FULL9, DG_BOP_JVP_CONDENSED7 = 0, 1, 2
+BATCH_OPS = {"residual": DG_BOP_RESIDUAL, "jvp": DG_BOP_JVP_FULL9, "jvp_condensed": DG_BOP_JVP_CONDENSED7}
+
+
+class DgBatchShape(C.Structure):
+    _fields_ = [("tile_voxels", C.c_int32), ("persistent", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.tile_voxels, self.persistent)
+
+
+class DgBatchTuning(C.Structure):
+    _fields_ = [("shape", DgBatchShape * 3), ("ms", C.c_double * 3), ("ms_default", C.c_double * 3),
+                ("candidates", C.c_int32), ("pad", C.c_int32)]
 
 
 DG_CTRL_NAIVE, DG_CTRL_H211B = 0, 1
@@ -173,12 +193,16 @@ def _stream():
 
 
 def _prec(t):
+    return _prec_of(t.dtype)
+
+
+def _prec_of(dtype):
     import torch
-    if t.dtype == torch.float64:
+    if dtype == torch.float64:
         return DG_F64
-    if t.dtype == torch.float32:
+    if dtype == torch.float32:
         return DG_F32
-    raise ValueError(f"unsupported dtype {t.dtype}")
+    raise ValueError(f"unsupported dtype {dtype}")
 
 
 def default_params():
@@ -541,6 +565,40 @@ class Batch:
         _check("dg_batch_blockjacobi_apply", self._lib.dg_batch_blockjacobi_apply(
             self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
         return out
+
+    def set_shape(self, dtype, op, tile_voxels, persistent=0):
+        """Launch shape of one batched operator ("residual", "jvp" or
+        "jvp_condensed") in one precision."""
+        sh = DgBatchShape(int(tile_voxels), int(persistent))
+        _check("dg_batch_set_shape", self._lib.dg_batch_set_shape(self._h, _prec_of(dtype), BATCH_OPS[op],
+                                                                  C.byref(sh)))
+
+    def get_shape(self, dtype, op):
+        sh = DgBatchShape()
+        _check("dg_batch_get_shape", self._lib.dg_batch_get_shape(self._h, _prec_of(dtype), BATCH_OPS[op],
+                                                                  C.byref(sh)))
+        return sh.as_tuple()
+
+    def autotune(self, u, v, m_old, t_new, dt, reps=5, work=None):
+        """Time every launch shape of the residual and both tangents on
+        these arrays (v: 9 fields), keep the fastest; returns, per operator,
+        (shape, ms, ms of the default shape), and the number of shapes tried."""
+        import torch
+        self._check_arr(u, 9)
+        self._check_arr(v, 9)
+        self._check_arr(m_old, 8)
+        if v.dtype != u.dtype or m_old.dtype != u.dtype:
+            raise ValueError("u, v and m_old must share a dtype")
+        if work is None:
+            work = torch.empty(self._shape(9), dtype=u.dtype, device=u.device)
+        self._check_arr(work, 9)
+        rep = DgBatchTuning()
+        t, d = self._times(t_new), self._times(dt)
+        _check("dg_batch_autotune", self._lib.dg_batch_autotune(
+            self._h, _prec(u), _ptr(u), _ptr(v), _ptr(m_old), t.ctypes.data, d.ctypes.data, _ptr(work),
+            int(reps), C.byref(rep), _stream()))
+        out = {op: (rep.shape[i].as_tuple(), rep.ms[i], rep.ms_default[i]) for op, i in BATCH_OPS.items()}
+        return out, int(rep.candidates)
 
     def initial_state(self, t0=0.0, inner="f64", workers=4, **opts):
         """Initial states of every structure (FP64 batch array) and their reports."""

@@ -54,7 +54,8 @@ def test_struct_layouts_match_the_header():
 
 _STRUCTS = {"dg_mesh": lsbdg.DgMesh, "dg_params": lsbdg.DgParams, "dg_solver_opts": lsbdg.DgSolverOpts,
             "dg_step_report": lsbdg.DgStepReport, "dg_controller": lsbdg.DgController,
-            "dg_advance_report": lsbdg.DgAdvanceReport}
+            "dg_advance_report": lsbdg.DgAdvanceReport, "dg_batch_shape": lsbdg.DgBatchShape,
+            "dg_batch_tuning": lsbdg.DgBatchTuning}
 
 
 def test_binding_structs_match_the_c_compiler(tmp_path):
@@ -99,3 +100,13 @@ def test_batch_setup_rejects_bad_arguments(lib):
     assert lib.dg_batch_setup(2, mesh, ptrs, params, ctypes.byref(out)) == -1
     assert b"null phase map of structure 0" in lib.dg_last_error()
     assert not out.value
+
+
+def test_batch_shape_calls_reject_bad_arguments(lib):
+    """Null batches and reports are refused before any device call."""
+    sh = lsbdg.DgBatchShape(32, 0)
+    assert lib.dg_batch_set_shape(None, 0, 0, ctypes.byref(sh)) == -1
+    assert lib.dg_batch_get_shape(None, 0, 0, ctypes.byref(sh)) == -1
+    rep = lsbdg.DgBatchTuning()
+    assert lib.dg_batch_autotune(None, 0, None, None, None, None, None, None, 5, ctypes.byref(rep), None) == -1
+    assert b"null argument" in lib.dg_last_error()

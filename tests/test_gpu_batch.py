@@ -172,3 +172,92 @@ def test_batched_step_rejects_bad_steps(batch_case):
     u = torch.zeros((9, b.n_elem, 8), dtype=torch.float64, device="cuda:0")
     with pytest.raises(lsbdg.DgError, match="DG_EINVAL"):
         b.step(u, 0.0, [0.1, 0.1, -1.0, 0.1])
+
+
+# Launch shapes tried beside the default (32 voxels, one workgroup per work
+# item): every tile size, one workgroup per item and persistent grids.
+LAUNCH_SHAPES = [(8, 0), (16, 0), (8, 1), (16, 2), (32, 1), (32, 3)]
+
+
+@pytest.fixture(scope="module")
+def shape_case():
+    """Two structures, 4,096 and 1,287 voxels: with 8-voxel tiles 680 grid
+    positions, so a persistent grid of one workgroup per compute unit makes
+    several passes, and both structures end in a partly filled tile."""
+    from paper_2511_05233_amd import lsbdg
+    structs, us, uos = [], [], []
+    for s, (nx, ny, nz, por, seed) in enumerate([(16, 16, 16, 0.6, 5), (13, 11, 9, 0.5, 6)]):
+        mask = synth.porosity_mask((nz, ny, nx), por, seed)
+        D0, i0 = synth.sample_transport_kinetics(s)
+        structs.append(dict(nx=nx, ny=ny, nz=nz, h=1e-6, phase=mask, D0=D0, kE=i0 / om.F, f_C=0.5))
+        us.append(synth.random_state(nx * ny * nz, 8, 40 + s, phase=mask, phi_spread=5e-3))
+        uos.append(synth.random_state(nx * ny * nz, 8, 50 + s, phase=mask))
+    b = lsbdg.Batch(structs)
+    v9 = np.concatenate([synth.random_vector(9, nx * ny * nz, 8, 60 + s)
+                         for s, (nx, ny, nz) in enumerate([(16, 16, 16), (13, 11, 9)])], axis=1)
+    print(f"[batch] shape case: {b.n_elem} voxels", flush=True)
+    return structs, b, us, uos, v9
+
+
+def _operators(b, u, m, v9, t, dt):
+    v7 = v9[:7].contiguous()
+    return (b.residual(u, m, t, dt), b.jvp(u, v9, t, dt), b.jvp(u, v7, t, dt, condensed=True))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_every_launch_shape_gives_the_same_results(shape_case, dtype):
+    """Residual, full and condensed tangent: bit for bit the default
+    shape's values in every tile size, with and without a persistent grid
+    (only the workgroup that computes a node changes)."""
+    from paper_2511_05233_amd import lsbdg
+    structs, b, us, uos, v9 = shape_case
+    u = _cat(us, dtype)
+    m = b.mass(_cat(uos, dtype))
+    v = torch.tensor(v9, dtype=dtype, device="cuda:0")
+    t, dt = [0.7, 2.0], [0.1, 0.5]
+    for op in lsbdg.BATCH_OPS:
+        b.set_shape(dtype, op, 32, 0)
+    ref = _operators(b, u, m, v, t, dt)
+    for tv, pers in LAUNCH_SHAPES:
+        print(f"[batch] {dtype} shape ({tv}, {pers})", flush=True)
+        for op in lsbdg.BATCH_OPS:
+            b.set_shape(dtype, op, tv, pers)
+            assert b.get_shape(dtype, op) == (tv, pers)
+        got = _operators(b, u, m, v, t, dt)
+        for name, g, r in zip(lsbdg.BATCH_OPS, got, ref):
+            assert torch.equal(g, r), (tv, pers, name)
+    for op in lsbdg.BATCH_OPS:
+        b.set_shape(dtype, op, 32, 0)
+
+
+def test_set_shape_checks_its_arguments(shape_case):
+    from paper_2511_05233_amd import lsbdg
+    _, b, *_ = shape_case
+    for tv, pers in [(4, 0), (64, 0), (32, -1), (32, 65)]:
+        with pytest.raises(lsbdg.DgError, match="DG_EINVAL"):
+            b.set_shape(torch.float32, "residual", tv, pers)
+    assert b.get_shape(torch.float32, "residual") == (32, 0)
+
+
+def test_autotune_keeps_the_fastest_timed_shape(shape_case):
+    """FP32: every operator gets the shape with the smallest timed launch
+    (never slower than the default, which is among the candidates), and a
+    later batch of the same size class starts from it."""
+    from paper_2511_05233_amd import lsbdg
+    structs, b, us, uos, v9 = shape_case
+    u = _cat(us, torch.float32)
+    m = b.mass(_cat(uos, torch.float32))
+    v = torch.tensor(v9, dtype=torch.float32, device="cuda:0")
+    tune, ncand = b.autotune(u, v, m, [0.7, 2.0], [0.1, 0.5], reps=3)
+    print(f"[batch] autotune: {tune}, {ncand} shapes per operator", flush=True)
+    assert ncand in (3, 6)
+    for op, (shape, ms, ms_def) in tune.items():
+        assert shape[0] in (8, 16, 32) and shape[1] >= 0
+        assert 0.0 < ms <= ms_def
+        assert b.get_shape(torch.float32, op) == shape
+    b2 = lsbdg.Batch(structs)
+    for op, (shape, _, _) in tune.items():
+        assert b2.get_shape(torch.float32, op) == shape
+    b2.close()
+    for op in lsbdg.BATCH_OPS:
+        b.set_shape(torch.float32, op, 32, 0)
