@@ -247,7 +247,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
                   std::make_pair(&W.dots, size_t(kMaxDots) * 8), std::make_pair(&W.yc, size_t(8) * 8),
                   std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8),
                   std::make_pair(&W.pc, size_t(n7) * sS), std::make_pair(&W.pc2, size_t(n7) * sS),
-                  std::make_pair(&W.scc, size_t(n7) * sS)}) {
+                  std::make_pair(&W.scc, size_t(n7) * sS),
+                  std::make_pair(&W.gsum, size_t(8) + 2 * size_t(kMaxDots) * sS)}) {
     hipError_t e = pr.first->ensure(pr.second);
     if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_step workspace: ") + hipGetErrorString(e));
   }
@@ -272,8 +273,17 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   S *pc = W.pc.as<S>(), *pc2 = W.pc2.as<S>(), *scc = W.scc.as<S>();
   double* partial64 = W.partial64.as<double>();
   double* Ainv = W.Ainv.as<double>();
+  double* gs = W.gsum.as<double>();             // [|w|^2 (FP64)][h1 (kMaxDots x S)][h2 (kMaxDots x S)]
+  S* gs_h1 = reinterpret_cast<S*>(gs + 1);
+  S* gs_h2 = gs_h1 + kMaxDots;
+  std::vector<unsigned char> gs_host(sizeof(double) + 2 * kMaxDots * sizeof(S));
   const dim3 blk{256, 1, 1};
-  const dim3 gred{unsigned(kRedBlocks), 1, 1};
+  // Reductions run on kRedBlocks workgroups, or on fewer for small meshes:
+  // no more workgroups than a Krylov vector has quads of 4 entries per 256
+  // lanes (the extra ones would only add empty block sums and partials).
+  // The consumers of the partials read exactly nred of them.
+  const int nred = int(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n7 / 4 + 255) / 256)));
+  const dim3 gred{unsigned(nred), 1, 1};
   const dim3 gw{unsigned((ctx->Ne + 3) / 4), 1, 1};
   const dim3 g1{1, 1, 1}, g7{7, 1, 1};
 
@@ -326,7 +336,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // coarse coefficients yc = E^-1 Z^T r (E = Z^T J Z, Z_f = sc on field f)
   auto coarse_coeffs = [&](const S* r) {
     hipLaunchKernelGGL(field_dot_kernel<S>, gred, blk, 0, st, sc, r, FS, partial);
-    hipLaunchKernelGGL(coarse_solve_kernel<S>, g1, blk, 0, st, partial, kRedBlocks, Ainv, yc);
+    hipLaunchKernelGGL(coarse_solve_kernel<S>, g1, blk, 0, st, partial, nred, Ainv, yc);
   };
   // deflation r <- P r = r - J Z E^-1 Z^T r (leaves yc = E^-1 Z^T r)
   auto deflate = [&](S* r) {
@@ -394,23 +404,9 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     precond(pJ, out);
     hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, out, out, n7);
   };
-  // dots[0..nv) and h <- the block partials of nv dot products
-  auto finish_dots = [&](int nv, std::vector<double>& h) -> int {
-    const dim3 gnv{unsigned(nv), 1, 1};
-    hipLaunchKernelGGL(finish_sum_kernel<S>, gnv, blk, 0, st, partial, kRedBlocks, dots);
-    std::vector<S> hs(nv);
-    DG_HIP(hipMemcpyAsync(hs.data(), dots, nv * sizeof(S), hipMemcpyDeviceToHost, st));
-    DG_HIP(hipStreamSynchronize(st));
-    h.assign(hs.begin(), hs.end());
-    return DG_OK;
-  };
-  auto mdot = [&](const S* Vb, int nv, const S* ww, std::vector<double>& h) -> int {
-    hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, Vb, n7, nv, ww, n7, partial);
-    return finish_dots(nv, h);
-  };
   // out <- the sum of the FP64 block partials in partial64
   auto finish_sumsq = [&](double& out) -> int {
-    hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, kRedBlocks,
+    hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, nred,
                        reinterpret_cast<double*>(hbuf));
     double hs = 0;
     DG_HIP(hipMemcpyAsync(&hs, hbuf, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -445,7 +441,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     double a = 0.0;
     if (int s = sumsq(pJ, n7, a)) return s;
     hipLaunchKernelGGL(solid_merit_kernel, gred, blk, 0, st, Rv, u, FS, P, partial64);
-    hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, kRedBlocks,
+    hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, nred,
                        reinterpret_cast<double*>(hbuf));
     double bsum = 0.0;
     DG_HIP(hipMemcpyAsync(&bsum, hbuf, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -525,7 +521,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
         hipLaunchKernelGGL(field_select_kernel<S>, grid1(n7), blk, 0, st, sc, f, t, FS);
         jvp_cond(t, JZf);
         hipLaunchKernelGGL(field_dot_kernel<S>, gred, blk, 0, st, sc, JZf, FS, partial);
-        hipLaunchKernelGGL(finish_sum_kernel<S>, g7, blk, 0, st, partial, kRedBlocks, dots);
+        hipLaunchKernelGGL(finish_sum_kernel<S>, g7, blk, 0, st, partial, nred, dots);
         std::vector<S> hs(7);
         DG_HIP(hipMemcpyAsync(hs.data(), dots, 7 * sizeof(S), hipMemcpyDeviceToHost, st));
         DG_HIP(hipStreamSynchronize(st));
@@ -574,7 +570,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     const int maxit = near_root ? std::min(o.gmres_maxit, std::max(200, 4 * prev_its)) : o.gmres_maxit;
     double rel = 0.0;
     if (beta0 > 0.0) {
-      std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), h, h2;
+      std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), h;
       while (its < maxit) {
         S* V0 = V;
         if (its == 0) {
@@ -602,13 +598,26 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
           // orthogonality to slow the two-level preconditioned iteration
           // (three sweeps over the basis: projections; first update fused
           // with the second projections; second update fused with |w|^2)
-          if (int s = mdot(V, j + 1, w, h)) return s;
-          hipLaunchKernelGGL(multi_axpy_dot_kernel<S>, gred, blk, 0, st, V, n7, j + 1, dots, w, n7, partial);
-          if (int s = finish_dots(j + 1, h2)) return s;
-          hipLaunchKernelGGL(multi_axpy_sumsq_kernel<S>, gred, blk, 0, st, V, n7, j + 1, dots, w, n7, partial64);
-          for (int i = 0; i <= j; ++i) h[i] += h2[i];
+          // (the three sums stay on the device, where the updates read
+          // them, and come back to the host in one copy)
+          const dim3 gj{unsigned(j + 1), 1, 1};
+          hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, V, n7, j + 1, w, n7, partial);
+          hipLaunchKernelGGL(finish_sum_kernel<S>, gj, blk, 0, st, partial, nred, gs_h1);
+          hipLaunchKernelGGL(multi_axpy_dot_kernel<S>, gred, blk, 0, st, V, n7, j + 1, gs_h1, w, n7, partial);
+          hipLaunchKernelGGL(finish_sum_kernel<S>, gj, blk, 0, st, partial, nred, gs_h2);
+          hipLaunchKernelGGL(multi_axpy_sumsq_kernel<S>, gred, blk, 0, st, V, n7, j + 1, gs_h2, w, n7, partial64);
+          hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, nred, gs);
+          DG_HIP(hipMemcpyAsync(gs_host.data(), gs, gs_host.size(), hipMemcpyDeviceToHost, st));
+          DG_HIP(hipStreamSynchronize(st));
           double hn = 0.0;
-          if (int s = finish_sumsq(hn)) return s;
+          std::memcpy(&hn, gs_host.data(), sizeof(double));
+          {
+            S h1[kMaxDots], h2s[kMaxDots];
+            std::memcpy(h1, gs_host.data() + sizeof(double), kMaxDots * sizeof(S));
+            std::memcpy(h2s, gs_host.data() + sizeof(double) + kMaxDots * sizeof(S), kMaxDots * sizeof(S));
+            h.assign(j + 1, 0.0);
+            for (int i = 0; i <= j; ++i) h[i] = double(h1[i]) + double(h2s[i]);
+          }
           hn = std::sqrt(hn);
           ++its;
           for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
@@ -689,8 +698,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     bool found = false;
     for (int ls = 0; ls <= (near_root ? 3 : 40); ++ls) {
       hipLaunchKernelGGL(newton_update_kernel, gred, blk, 0, st, u, du, lam, u_try, FS, phi_floor, partial64);
-      std::vector<double> pm(kRedBlocks);
-      DG_HIP(hipMemcpyAsync(pm.data(), partial64, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, st));
+      std::vector<double> pm(nred);
+      DG_HIP(hipMemcpyAsync(pm.data(), partial64, nred * sizeof(double), hipMemcpyDeviceToHost, st));
       resid64(u_try, Rtry);
       if (int s = merit(Rtry, mt)) return s;
       upd = *std::max_element(pm.begin(), pm.end());

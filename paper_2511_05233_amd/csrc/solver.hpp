@@ -58,13 +58,14 @@ struct SolverWork {
   DevBuf m_old, R, Rtry, u_try, du, wR;            // FP64
   DevBuf uS, sc, V, w, t, pJ, rhs, b, x, y9, v9, JZ;   // precision S
   DevBuf partial, partial64, dots, yc, Ainv, hbuf;
+  DevBuf gsum;                                     // one Gram-Schmidt step's sums: [|w|^2][h1][h2]
   DevBuf z0, zC, zF, out_partial;                  // time controller, outputs (FP64)
   DevBuf pc, pc2, scc;                             // two-level preconditioner temporaries, scales (S)
   int m = 0;
   void release_all() {
     for (DevBuf* d : {&m_old, &R, &Rtry, &u_try, &du, &wR, &uS, &sc, &V, &w, &t, &pJ, &rhs, &b, &x,
                       &y9, &v9, &JZ, &partial, &partial64, &dots, &yc, &Ainv, &hbuf, &z0, &zC, &zF,
-                      &out_partial, &pc, &pc2, &scc})
+                      &out_partial, &pc, &pc2, &scc, &gsum})
       d->release();
   }
 };
