@@ -60,6 +60,32 @@ __device__ __forceinline__ S block_sum(S v, S* sh) {
   return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// Block sums of acc[0..nv) over 256 threads into partial[i * gridDim + b]:
+// for each sum the tree of block_sum (wave shuffle tree, then the four wave
+// sums added in order), so the values are those of nv block_sum calls, but
+// with one barrier for all of them instead of two per sum.
+template <typename S>
+__device__ __forceinline__ void store_block_sums(S (&acc)[kMaxDots], int nv, S (*sh)[kMaxDots],
+                                                 S* __restrict__ partial) {
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i)
+    if (i < nv) {
+      S v = acc[i];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+      acc[i] = v;
+    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) sh[w][i] = acc[i];
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < nv) partial[i * gridDim.x + blockIdx.x] = sh[0][i] + sh[1][i] + sh[2][i] + sh[3][i];
+}
+
 // partial[i * gridDim + b] = sum over block b's share of V_i . w, i < nv
 template <typename S>
 __global__ void __launch_bounds__(256)
@@ -68,7 +94,7 @@ multi_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restri
   // four consecutive entries per thread (n and ldv are multiples of 4:
   // Krylov vectors hold 7 fields x 8 nodes per voxel)
   struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
-  __shared__ S sh[4];
+  __shared__ S sh[4][kMaxDots];
   S acc[kMaxDots];
 #pragma unroll
   for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
@@ -82,13 +108,7 @@ multi_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restri
         acc[i] += v.a * wk.a + v.b * wk.b + v.c * wk.c + v.d * wk.d;
       }
   }
-#pragma unroll
-  for (int i = 0; i < kMaxDots; ++i) {
-    if (i < nv) {
-      const S s = block_sum(acc[i], sh);
-      if (threadIdx.x == 0) partial[i * gridDim.x + blockIdx.x] = s;
-    }
-  }
+  store_block_sums(acc, nv, sh, partial);
 }
 
 // out[i] = sum_b partial[i * nb + b]; one block per i
@@ -139,7 +159,7 @@ __global__ void __launch_bounds__(256)
 multi_axpy_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h,
                       S* __restrict__ w, int64_t n, S* __restrict__ partial) {
   struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
-  __shared__ S sh[4];
+  __shared__ S sh[4][kMaxDots];
   S acc[kMaxDots];
 #pragma unroll
   for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
@@ -167,13 +187,7 @@ multi_axpy_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __r
         acc[i] += v.a * wk.a + v.b * wk.b + v.c * wk.c + v.d * wk.d;
       }
   }
-#pragma unroll
-  for (int i = 0; i < kMaxDots; ++i) {
-    if (i < nv) {
-      const S sum = block_sum(acc[i], sh);
-      if (threadIdx.x == 0) partial[i * gridDim.x + blockIdx.x] = sum;
-    }
-  }
+  store_block_sums(acc, nv, sh, partial);
 }
 
 // The second pass's update w -= sum_i h[i] V_i with partial sums of |w|^2
