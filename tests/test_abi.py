@@ -110,3 +110,19 @@ def test_batch_shape_calls_reject_bad_arguments(lib):
     rep = lsbdg.DgBatchTuning()
     assert lib.dg_batch_autotune(None, 0, None, None, None, None, None, None, 5, ctypes.byref(rep), None) == -1
     assert b"null argument" in lib.dg_last_error()
+
+
+def test_binding_constants_match_the_header_enums():
+    """Every enumerator of include/lsbdg.h equals the binding's constant
+    (status codes through the binding's name table)."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    enums = {}
+    for body in re.findall(r"typedef\s+enum\s*\w*\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"\b(DG_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            enums[name] = int(val)
+    assert len(enums) == 18, sorted(enums)   # status 8, precision 2, JVP 3, controller 2, batch op 3
+    for name, val in enums.items():
+        if hasattr(lsbdg, name):
+            assert getattr(lsbdg, name) == val, name
+        else:
+            assert lsbdg._STATUS[val] == name, name
