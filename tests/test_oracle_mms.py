@@ -14,9 +14,15 @@ which has no flux through both ends; the old mass that makes it exact is
     m_old = c* - dt d/dx (D(c*) dc*/dx),
     d/dx (D dc/dx) = D (c'' - 8 eta c'^2),   D = D0 exp(-eta c_S),
 
-evaluated at the nodes (the time term is collocated, Sec. 2.6).  The error
-of the oracle's Newton root at the Gauss-Legendre nodes must then fall at
-the textbook rates of the interior-penalty schemes on uniform meshes:
+evaluated at the nodes (the time term is collocated, Sec. 2.6).  A second
+family pins the migration part of the Nernst-Planck flux (Tab. 4): Li+
+(z = 1) drifts and diffuses in a frozen potential Phi(x) = B cos(pi x / L),
+flux D (grad c + (F/RT) c grad Phi) with no flux through both ends, and
+
+    m_old = c* - dt D (c*'' + (F/RT) (c*' Phi' + c* Phi'')).
+
+The error of the oracle's Newton root at the Gauss-Legendre nodes must then
+fall at the textbook rates of the interior-penalty schemes on uniform meshes:
 second order for k = 0 (the two-point flux of Eq. 48 at the cell centres)
 and k = 1, and -- the mark of the incomplete form, Eq. 46 without the
 symmetrising term -- only second order again for k = 2, where the
@@ -117,4 +123,62 @@ def test_a_wrong_transport_law_stalls(monkeypatch):
     e16 = _mms_error(16, 1, 0, no_viscosity, monkeypatch)
     e32 = _mms_error(32, 1, 0, no_viscosity, monkeypatch)
     print(f"correct {ok:.3e}; planted mistake: 16 cells {e16:.3e}, 32 cells {e32:.3e}")
+    assert e32 > 10.0 * ok and e32 > 0.8 * e16
+
+
+# Li+ in a frozen potential: amplitudes [mol/m^3] and [V]; c0 = 1500 mol/m^3
+AMP_LI, AMP_PHI = 100.0, 0.01
+
+
+def _mms_error_li(N, k, axis, transport=None, monkeypatch=None):
+    """Relative discrete L2 error of the Li+ root in the frozen potential."""
+    P = _column(N, k, axis)
+    u = solve.uniform_state(P)
+    c = u[0:6, 0, 0]
+    c0 = c[0]
+    cS = c[5] + 4.0 * c[4] + 6.0 * c[3] + 8.0 * c[2] + 8.0 * c[1]
+    x = _node_coordinate(P, axis)
+    q = np.pi / L
+    cs = c0 + AMP_LI * np.cos(q * x)
+    c1, c2 = -AMP_LI * q * np.sin(q * x), -AMP_LI * q * q * np.cos(q * x)
+    p1, p2 = -AMP_PHI * q * np.sin(q * x), -AMP_PHI * q * q * np.cos(q * x)
+    D = P.D0[0] * np.exp(-M.ETA_K * cS)
+    frt = 1.0 / M.rt_over_f(P.T)
+    u[6] = AMP_PHI * np.cos(q * x)
+    m_old = dg.old_mass(P, u)
+    m_old[0] = cs - DT * D * (c2 + frt * (c1 * p1 + cs * p2))
+    if transport is not None:
+        monkeypatch.setattr(chem, "transport_coefficients", transport)
+    sol, _ = solve.newton(P, u, m_old, 1.0, DT, fields=(0,))
+    _, w = dg.gl_nodes_weights(k)
+    K = k + 1
+    n = np.arange(K ** 3)
+    W = np.broadcast_to(w[n % K] * w[(n // K) % K] * w[n // (K * K)], cs.shape)
+    err = sol[0] - cs
+    return float(np.sqrt(np.sum(W * err ** 2) / np.sum(W * (cs - c0) ** 2)))
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("k", [0, 1])
+def test_drift_diffusion_second_order(k, axis):
+    errs = [_mms_error_li(N, k, axis) for N in (4, 8, 16, 32)]
+    rates = [float(np.log2(a / b)) for a, b in zip(errs, errs[1:])]
+    print(f"Li+ k={k} axis={axis}: errors {errs}, rates {rates}")
+    assert all(1.9 < r < 2.15 for r in rates), rates
+
+
+def test_dropped_migration_stalls(monkeypatch):
+    """Planted mistake (on the CPU): the oracle's migration coefficients
+    zeroed.  The error at 32 cells is then far above the correct one and no
+    longer falls."""
+    good = chem.transport_coefficients
+
+    def no_migration(P, c, eps, epsCBD):
+        D, Mi, K, kap = good(P, c, eps, epsCBD)
+        return D, 0.0 * Mi, K, kap
+
+    ok = _mms_error_li(32, 1, 0)
+    e16 = _mms_error_li(16, 1, 0, no_migration, monkeypatch)
+    e32 = _mms_error_li(32, 1, 0, no_migration, monkeypatch)
+    print(f"correct {ok:.3e}; migration dropped: 16 cells {e16:.3e}, 32 cells {e32:.3e}")
     assert e32 > 10.0 * ok and e32 > 0.8 * e16
