@@ -140,17 +140,22 @@ template <typename S, typename N, int Mode>
 void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void* v, const void* m,
                void* out, hipStream_t st) {
   const int64_t threads = ctx->Ne * 8;
+  if constexpr (std::is_same<S, float>::value && Mode != kResidual) {
+    // the FP32 tangent (two waves per SIMD) in workgroups of one wave, the
+    // shape the batch autotuner picks for the batched form of this kernel
+    constexpr int kLanes = 64;
+    const int64_t nb = ((threads + kLanes - 1) / kLanes + 7) / 8 * 8;
+    hipLaunchKernelGGL((q1_kernel_w2<S, N, Mode, kLanes>), dim3(unsigned(nb)), dim3(kLanes), 0, st,
+                       static_cast<const S*>(u), static_cast<const S*>(v), static_cast<const S*>(m),
+                       static_cast<S*>(out), ctx->d_phase, P, nb);
+    return;
+  }
   int64_t nb = (threads + 255) / 256;
   nb = (nb + 7) / 8 * 8;
   const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
-  if constexpr (std::is_same<S, float>::value && Mode != kResidual)
-    hipLaunchKernelGGL((q1_kernel_w2<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
-                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
-                       ctx->d_phase, P, nb);
-  else
-    hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
-                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out),
-                       ctx->d_phase, P, nb);
+  hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
+                     static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), ctx->d_phase, P,
+                     nb);
 }
 
 // Linearisation coefficients of the condensed tangent at u (precision S).

@@ -421,35 +421,36 @@ __device__ __forceinline__ void q1_node(const S* __restrict__ U, const S* __rest
   }
 }
 
-template <typename S, typename N, int Mode>
+// kLanes lanes per workgroup (kLanes / 8 voxels).
+template <typename S, typename N, int Mode, int kLanes>
 __device__ __forceinline__ void q1_body(const S* __restrict__ U, const S* __restrict__ V,
                                         const S* __restrict__ M, S* __restrict__ Out,
                                         const uint8_t* __restrict__ phase, const DevParams& P,
                                         int64_t nblocks_padded) {
   const int64_t blk = xcd_block(nblocks_padded);
-  const int64_t gid = blk * 256 + threadIdx.x;
+  const int64_t gid = blk * kLanes + threadIdx.x;
   const int64_t e = gid >> 3;
   if (e >= P.Ne) return;                     // whole 8-lane groups leave together
   q1_node<S, N, Mode>(U, V, M, Out, phase, P, e, int(gid & 7), P.Ne * 8);
 }
 
-template <typename S, typename N, int Mode>
-__global__ void __launch_bounds__(256)
+template <typename S, typename N, int Mode, int kLanes = 256>
+__global__ void __launch_bounds__(kLanes)
 q1_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
           S* __restrict__ Out, const uint8_t* __restrict__ phase, DevParams P,
           int64_t nblocks_padded) {
-  q1_body<S, N, Mode>(U, V, M, Out, phase, P, nblocks_padded);
+  q1_body<S, N, Mode, kLanes>(U, V, M, Out, phase, P, nblocks_padded);
 }
 
 // The same operator held to 256 registers per lane (two waves per SIMD):
 // the FP32 tangent otherwise takes a few accumulation registers beyond 256
 // and drops to one wave per SIMD.
-template <typename S, typename N, int Mode>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename S, typename N, int Mode, int kLanes = 256>
+__global__ void __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2)))
 q1_kernel_w2(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ M,
              S* __restrict__ Out, const uint8_t* __restrict__ phase, DevParams P,
              int64_t nblocks_padded) {
-  q1_body<S, N, Mode>(U, V, M, Out, phase, P, nblocks_padded);
+  q1_body<S, N, Mode, kLanes>(U, V, M, Out, phase, P, nblocks_padded);
 }
 
 // Old mass: m[i] = eps_L c_i (i < 6), m[6 + s] = eps_s.
