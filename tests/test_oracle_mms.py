@@ -26,7 +26,7 @@ fall at the textbook rates of the interior-penalty schemes on uniform meshes:
 second order for k = 0 (the two-point flux of Eq. 48 at the cell centres)
 and k = 1, and -- the mark of the incomplete form, Eq. 46 without the
 symmetrising term -- only second order again for k = 2, where the
-symmetric scheme reaches third order.  A wrong sign, a dropped term or a
+symmetric scheme reaches third order; k = 3, odd again, reaches fourth.  A wrong sign, a dropped term or a
 wrong length scale in any volume or face term, on any axis, makes the
 scheme inconsistent and the error stall.
 """
@@ -182,3 +182,14 @@ def test_dropped_migration_stalls(monkeypatch):
     e32 = _mms_error_li(32, 1, 0, no_migration, monkeypatch)
     print(f"correct {ok:.3e}; migration dropped: 16 cells {e16:.3e}, 32 cells {e32:.3e}")
     assert e32 > 10.0 * ok and e32 > 0.8 * e16
+
+
+def test_degree_three_reaches_fourth_order():
+    """k = 3 (the order of the high-order workload): odd degree, so the
+    incomplete scheme keeps the optimal order k + 1 = 4, for the nonlinear
+    diffusion and for drift-diffusion alike."""
+    for fn in (_mms_error, _mms_error_li):
+        errs = [fn(N, 3, 0) for N in (2, 4, 8)]
+        rates = [float(np.log2(a / b)) for a, b in zip(errs, errs[1:])]
+        print(f"{fn.__name__} k=3: errors {errs}, rates {rates}")
+        assert all(3.8 < r < 4.2 for r in rates), rates
