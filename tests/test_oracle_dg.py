@@ -319,3 +319,43 @@ def test_condensed_jvp_is_the_schur_complement(tiny):
         sl = slice(f * Ne * npn, (f + 1) * Ne * npn)
         scale = np.max(np.abs(ref[sl])) + 1e-300
         assert np.max(np.abs(got[sl] - ref[sl])) < 1e-10 * scale, f
+
+
+@pytest.fixture(scope="module")
+def tiny3():
+    """k = 3 (64 nodes per voxel) on 2 x 2 x 1 voxels."""
+    P = _prob(2, 2, 1, 3, seed=2)
+    u = synth.random_state(P.n_elem, P.n_nodes, 43, phase=P.phase, phi_spread=4e-3)
+    m = dg.old_mass(P, synth.random_state(P.n_elem, P.n_nodes, 44, phase=P.phase))
+    return P, u, m
+
+
+def test_jvp_matches_central_differences_at_degree_three(tiny3):
+    P, u, m = tiny3
+    rng = np.random.default_rng(4)
+    S = np.maximum(np.abs(u), 1e-3 * np.abs(u).max(axis=(1, 2), keepdims=True) + 1e-12)
+    v = S * rng.standard_normal(u.shape)
+    d = 1e-6
+    fd = (dg.residual(P, u + d * v, m, 2.0, 0.1) - dg.residual(P, u - d * v, m, 2.0, 0.1)) / (2 * d)
+    Jv = dg.jvp(P, u, v, m, 2.0, 0.1)
+    for f in range(9):
+        scale = np.max(np.abs(Jv[f])) + 1e-300
+        assert np.max(np.abs(Jv[f] - fd[f])) < 1e-6 * scale, f
+
+
+def test_element_blocks_at_degree_three_are_jacobian_columns(tiny3):
+    """Sampled columns of each 576 x 576 element block equal the element's
+    rows of J e_j (J e_j by the complex-step product)."""
+    P, u, m = tiny3
+    blocks = solve.element_blocks(P, u, m, 2.0, 0.1)
+    Ne, npn = P.n_elem, P.n_nodes
+    rng = np.random.default_rng(6)
+    for e in range(Ne):
+        for col in rng.choice(9 * npn, size=6, replace=False):
+            f, a = divmod(int(col), npn)
+            v = np.zeros_like(u)
+            v[f, e, a] = 1.0
+            Jv = dg.jvp(P, u, v, m, 2.0, 0.1)
+            ref = Jv[:, e, :].reshape(-1)
+            scale = np.abs(blocks[e]).max()
+            assert np.max(np.abs(blocks[e][:, col] - ref)) < 1e-14 * scale, (e, f, a)
