@@ -13,7 +13,7 @@ What it computes, in the paper's order and notation (arXiv 2511.05233):
                     equilibrium initial state (Tab. InitialState), the 3D
                     localisation (Eq. 57) and the applied current (App. C).
 * chem.py        -- pointwise constitutive laws: viscosity / Stokes-Einstein
-                    (Eq. 02-03), Bruggeman (Sec. 2.4), the anion-eliminated
+                    (Eq. 02-03), Bruggeman (Sec. 2.3), the anion-eliminated
                     charge coefficients (Tab. 4), the specific surface
                     (Eq. 18), Butler-Volmer rates (Eq. 19-24), the smoothed
                     Heaviside regularisation (Eq. 56).

@@ -89,7 +89,7 @@ def reaction_rates(P, c, phi, t):
         dG_E = F (V - Phi_L - U_eq), U_eq = U0 - RT/F ln Q
             = a_reac exp(-A) - a_prod exp(A),  A = F (V - Phi_L - U0)/(2RT).
     Activities of solids and electrons are 1.  Reactions involving S^2-
-    (C2 and E4) are multiplied by T_H(t) (Eq. 56; Sec. 2.9).
+    (C2 and E4) are multiplied by T_H(t) (Eq. 56; Sec. 2.10).
 
     Returns r of shape (8, ...) in the column order C1, C2, E1..E6.
     """

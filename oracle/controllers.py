@@ -2,14 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
 
-Naive feedback controller (Sec. 2.7, Fig. 4): a success counter sct is
+Naive feedback controller (Sec. 2.8, Fig. 4): a success counter sct is
 raised after every converged step; when it reaches 3 the step grows by 1.2
 and sct restarts.  A failed solve halves the step and retries; more than 30
 consecutive halvings abort the run.  Reading (the flowchart is not
 available): a failure also resets sct, and steps are capped at dt_max
 (the snapshot interval, 100 s).
 
-H211b controller (Sec. 2.7, Eq. 51-54): each trial solves one coarse step
+H211b controller (Sec. 2.8, Eq. 51-54): each trial solves one coarse step
 (dt) and two fine steps (dt/2); err = ||z_F - z_C||_2/||z_F||_2 over all
 unknowns (reading of Eq. 53 as a ratio of l2 norms);
 rho = (tol/err)^(1/4) (tol/err_prev)^(1/4) (dt/dt_prev)^(-1/4),

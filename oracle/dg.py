@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
 
-Discretisation (Sec. 2.6, Eq. 43-47), for every scalar field psi with flux
+Discretisation (Sec. 2.7, Eq. 43-47), for every scalar field psi with flux
 f = -(K grad psi + ...):
   * nodal Lagrange basis of degree k per axis on the (k+1) Gauss-Legendre
     points of each voxel; volume quadrature on the same points (weights
@@ -17,7 +17,7 @@ f = -(K grad psi + ...):
     {K}_H the harmonic mean of Eq. 45, set to 0 unless K^- K^+ > 0;
     the symmetrising term of SIPG is absent (incomplete IP, as written).
     Every gradient term of a flux is penalised with the harmonic mean of its
-    own coefficient ("component-wise", Sec. 2.6), which at k = 0 is the
+    own coefficient ("component-wise", Sec. 2.7), which at k = 0 is the
     only place migration enters;
   * Neumann faces (Eq. 47): + int f^N phi_a, f^N the outward normal flux;
   * sigma = 1 at k = 0 (the paper's scheme, Eq. 48) and (k+1)^2 for k >= 1.

@@ -17,7 +17,7 @@ Readings taken where the paper is silent or inconsistent:
     in Tab. 5 are reproduced (to one unit in the last digit) only with
     298.15 K; U0_5 and U0_6 are recomputed from Tab. InitialState instead of
     taking their rounded printed values.
-  * The solid is equipotential at V (the gauge of Sec. 2.9); Phi_S is not a
+  * The solid is equipotential at V (the gauge of Sec. 2.10); Phi_S is not a
     field.  The separator face x = L_x receives the Li+ flux j_el/F and the
     ionic current j_el; all other faces are no-flux.
   * Voxel phases: pore voxels carry no solid, no carbon-binder and no
@@ -37,7 +37,7 @@ import numpy as np
 F = 96485.332          # C/mol
 R_GAS = 8.3145         # J/(mol K)
 T_K = 298.15           # K (reading: see module docstring)
-C_REF = 1000.0         # mol/m^3 (Sec. 2.3 and Sec. 2.5)
+C_REF = 1000.0         # mol/m^3 (Sec. 2.4 and Sec. 2.5)
 ETA_K = 7.76e-4        # m^3/mol, exponent of the viscosity law (Eq. 02)
 
 # Species of the liquid phase, in state order, plus the eliminated anion.
@@ -159,7 +159,7 @@ class Problem:
         eq = equilibrium_state(self.T)
         self.eq = eq
         self.U0 = eq["U0"]
-        self.V = eq["dphi0"]            # solid potential gauge (Sec. 2.9)
+        self.V = eq["dphi0"]            # solid potential gauge (Sec. 2.10)
         if self.sigma is None:
             self.sigma = 1.0 if self.k == 0 else float((self.k + 1) ** 2)
         ph = self.phase.reshape(-1).astype(np.float64)

@@ -288,7 +288,7 @@ def initial_state(P, t0=0.0, **kw):
     """Equilibrium state of Tab. InitialState plus the steady potential.
 
     The paper relaxes the potentials with an added time derivative and a
-    ramped current until steady (Sec. 2.9); this solves for the same fixed
+    ramped current until steady (Sec. 2.10); this solves for the same fixed
     point directly: the charge equation for Phi_L at frozen concentrations
     and solid fractions with the full current and T_H at t0.
     """

@@ -1,6 +1,6 @@
 // Pointwise constitutive laws and reaction sources on the device.
 //
-// Transport (Eq. 02-03 with Bruggeman, Sec. 2.4): every effective
+// Transport (Eq. 02-03 with Bruggeman, Sec. 2.3): every effective
 // diffusivity is D_i = D0_i * f with the common factor
 //     f = eps_L^(3/2) exp(-7.76e-4 c_S),   c_S = c_S^2- + 4c_S4 + 6c_S6 + 8c_S8^2- + 8c_S8,
 // so the migration, charge-diffusion and conductivity coefficients of
@@ -20,7 +20,7 @@ namespace lsbdg {
 template <typename T>
 __device__ __forceinline__ T clamp_lo(T x, T lo) { return x > lo ? x : lo; }
 
-// Liquid fraction eps_L = 1 - eps_CBD - eps_S8 - eps_Li2S (Sec. 2.6 (ii)), floored.
+// Liquid fraction eps_L = 1 - eps_CBD - eps_S8 - eps_Li2S (Sec. 2.7 (ii)), floored.
 template <typename T>
 __device__ __forceinline__ T liquid_fraction(T epsCBD, T eS8, T eLi2S, T floor_) {
   return clamp_lo(T(1) - epsCBD - eS8 - eLi2S, floor_);

@@ -37,7 +37,7 @@ def test_basis_partition_of_unity_and_exact_derivatives():
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_residual_vanishes_at_equilibrium(k):
     """Uniform equilibrium state, no current: every flux and source is zero
-    for any mask (the pin of Sec. 2.9's consistent initial state)."""
+    for any mask (the pin of Sec. 2.10's consistent initial state)."""
     P = _prob(3, 4, 2, k, seed=k, j_el=0.0)
     u = _eq_state(P)
     R = dg.residual(P, u, dg.old_mass(P, u), 7.0, 0.1)
@@ -188,7 +188,7 @@ def test_penalty_of_a_discontinuity(k):
 def test_discrete_conservation_sums():
     """Testing with phi = 1 on every element: transport cancels face by face, so
     each row sums to its time term minus its source minus the separator inflow
-    (local conservation of DG, Sec. 2.6)."""
+    (local conservation of DG, Sec. 2.7)."""
     P = _prob(4, 3, 3, 1, seed=4)
     u = synth.random_state(P.n_elem, P.n_nodes, 11, phase=P.phase, phi_spread=5e-3)
     m = dg.old_mass(P, synth.random_state(P.n_elem, P.n_nodes, 12, phase=P.phase))

@@ -14,7 +14,7 @@ which has no flux through both ends; the old mass that makes it exact is
     m_old = c* - dt d/dx (D(c*) dc*/dx),
     d/dx (D dc/dx) = D (c'' - 8 eta c'^2),   D = D0 exp(-eta c_S),
 
-evaluated at the nodes (the time term is collocated, Sec. 2.6).  A second
+evaluated at the nodes (the time term is collocated, Sec. 2.7).  A second
 family pins the migration part of the Nernst-Planck flux (Tab. 4): Li+
 (z = 1) drifts and diffuses in a frozen potential Phi(x) = B cos(pi x / L),
 flux D (grad c + (F/RT) c grad Phi) with no flux through both ends, and
