@@ -54,31 +54,75 @@ METRIC = "DG operator GDoF/s (% roofline) + s per full discharge, mixed vs FP64 
 HBM_PEAK_GBS = 8000.0
 SOLVER_EXTRA = {}      # further dg_solver_opts fields of the timed solves (command line)
 FARADAY = 96485.332
+# coefficients per node that the Krylov operator reads from the stored
+# linearisation (the solid-fraction condensation, both rows)
+LIN_COEFFS = 14
+# the kernel of the Krylov operator (condensed tangent at a stored
+# linearisation), by inner precision, as rocprofv3 names it
+JVP_KERNEL = {"f32": "q1_kernel_w2", "f64": "q1_kernel<double,Dual<double>,2>"}
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """Oracle condensed JVP (the Krylov operator) on a 24 x 24 x 48 sub-block."""
+def _oracle_timing(workload, budget_s):
+    """Worker of the CPU baseline (runs in a child process whose thread
+    count is fixed by its environment): the oracle's FP64 residual and its
+    condensed tangent (complex step) on a 12 x 12 x 24-voxel sub-block of
+    the workload, each repeated for about budget_s / 2 seconds."""
     import synth
     from oracle import dg as odg
     from oracle import model as om
-    mask = w.mask()[:48, :24, :24].copy()
+    w = synth.WORKLOADS[workload]
+    mask = w.mask()[:24, :12, :12].copy()
     D0, i0 = synth.sample_transport_kinetics(w.param_seed)
-    P = om.Problem(24, 24, 48, w.h, w.order, mask, D0=D0, kE=i0 / om.F, f_C=w.f_C)
+    P = om.Problem(12, 12, 24, w.h, w.order, mask, D0=D0, kE=i0 / om.F, f_C=w.f_C)
     u = synth.random_state(P.n_elem, P.n_nodes, 1, phase=mask, phi_spread=5e-3)
     m = odg.old_mass(P, synth.random_state(P.n_elem, P.n_nodes, 2, phase=mask))
     v = synth.random_vector(7, P.n_elem, P.n_nodes, 3)
-    odg.jvp_condensed(P, u, v, m, 0.5, 0.05)
-    n, t0, c0 = 0, time.perf_counter(), time.process_time()
-    while time.perf_counter() - t0 < budget_s:
-        odg.jvp_condensed(P, u, v, m, 0.5, 0.05)
-        n += 1
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
     dof = P.n_elem * P.n_nodes * 7
-    return {"value": dof * n / wall / 1e9, "unit": "GDoF/s", "cores": max(1, round(cpu / wall)),
+    out = {"dof": dof, "voxels": "12x12x24"}
+    for name, fn in (("residual", lambda: odg.residual(P, u, m, 0.5, 0.05)),
+                     ("jvp_condensed", lambda: odg.jvp_condensed(P, u, v, m, 0.5, 0.05))):
+        fn()
+        n, t0, c0 = 0, time.perf_counter(), time.process_time()
+        while time.perf_counter() - t0 < budget_s / 2:
+            fn()
+            n += 1
+        wall = time.perf_counter() - t0
+        out[name] = {"gdofs": dof * n / wall / 1e9, "runs": n, "wall_s": wall,
+                     "cpu_over_wall": (time.process_time() - c0) / wall}
+    return out
+
+
+def cpu_baseline(w, budget_s=24.0):
+    """The oracle on the host: all host threads, then one thread (child
+    processes with the BLAS/OpenMP thread counts set), about budget_s of
+    CPU work in total."""
+    import subprocess
+    nproc = os.cpu_count() or 1
+    legs = {}
+    for label, threads in (("all", nproc), ("one", 1)):
+        env = dict(os.environ)
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[k] = str(threads)
+        env["CUDA_VISIBLE_DEVICES"] = ""
+        env["HIP_VISIBLE_DEVICES"] = ""
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-timing", w.name,
+                              str(budget_s / 2)], capture_output=True, text=True, env=env, timeout=600)
+        if res.returncode != 0:
+            return {"error": res.stderr[-400:]}
+        legs[label] = json.loads(res.stdout.strip().splitlines()[-1])
+    a = legs["all"]
+    dof = a["dof"]
+    return {"value": round(a["jvp_condensed"]["gdofs"], 6), "unit": "GDoF/s", "cores": nproc,
             "kind": "oracle",
-            "sample": f"FP64 condensed JVP (complex step) of a 24x24x48-voxel sub-block (Q1, {dof} DoF) "
-                      f"of the same workload, {n} applications in {wall:.1f} s"}
+            "sample": f"FP64 condensed JVP (complex step, numpy) of a 12x12x24-voxel sub-block (Q1, {dof} DoF) "
+                      f"of the same workload, {a['jvp_condensed']['runs']} applications in "
+                      f"{a['jvp_condensed']['wall_s']:.1f} s with {nproc} host threads allowed",
+            "host_nproc": nproc,
+            "cpu_over_wall_all_threads": round(a["jvp_condensed"]["cpu_over_wall"], 2),
+            "one_core": {"jvp_condensed_gdofs": round(legs["one"]["jvp_condensed"]["gdofs"], 6),
+                         "residual_gdofs": round(legs["one"]["residual"]["gdofs"], 6)},
+            "all_cores": {"jvp_condensed_gdofs": round(a["jvp_condensed"]["gdofs"], 6),
+                          "residual_gdofs": round(a["residual"]["gdofs"], 6)}}
 
 
 def source_hash():
@@ -176,12 +220,18 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9
 
-    b_jvp = nodes * (9 + 7 + 14 + 7) * sb + ctx.n_elem      # u, v, coefficients in; Jv out; phase
+    # algorithmic bytes: every array of the operation's definition once per
+    # launch -- the tangent reads u (9 fields) and v (7) and writes Jv (7);
+    # the coefficients the linearisation stores are the implementation's
+    # own traffic (listed apart, not counted)
+    b_jvp = nodes * (9 + 7 + 7) * sb + ctx.n_elem           # u, v in; Jv out; phase
+    b_lin = nodes * LIN_COEFFS * sb                         # stored linearisation read by the kernel
     b_res = nodes * (9 + 8 + 9) * 8 + ctx.n_elem            # u, old mass in; R out; phase
     b_apply = ctx.n_elem * (56 * 56 + 2 * 56) * sb          # blocks, x in, y out
     b_apply_h = ctx.n_elem * (56 * 56 * 2 + 2 * 56 * 4)     # bfloat16 blocks, FP32 x in, y out
     kernels = {
-        "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp},
+        "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp,
+                          "linearisation_bytes_not_counted": b_lin},
         "residual_f64": {"ms": ms_res, "GB/s": gbs(b_res, ms_res), "bytes": b_res},
         "block_apply": {"ms": ms_apply, "GB/s": gbs(b_apply, ms_apply), "bytes": b_apply},
         "block_setup": {"ms": ms_setup},
@@ -194,9 +244,7 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
             k["frac"] = round(k["GB/s"] / HBM_PEAK_GBS, 4)
             k["GB/s"] = round(k["GB/s"], 1)
         k["ms"] = round(k["ms"], 4)
-    if ms_apply_h is not None and SOLVER_EXTRA.get("block_bf16", 1):
-        return kernels, ("apply_blocks_bf16_kernel", b_apply_h, ms_apply_h)
-    return kernels, ("apply_blocks_kernel", b_apply, ms_apply)
+    return kernels, (JVP_KERNEL[inner], b_jvp, ms_jvp)
 
 
 def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
@@ -216,42 +264,85 @@ def newton_iterations(ctx, u, t, dt, n, inner, log, verbose=0, coarse=0, coarse_
     return rep
 
 
+GOLDEN_CUBE16 = os.path.join(ROOT, "tests", "golden", "cube16_q1_trajectory.npz")
+
+
 def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
-    """Mixed precision against FP64: 5 backward-Euler steps on the 16^3 cube
-    with FP64 and with mixed (FP32 inner) solves from the same GPU initial
-    state."""
+    """Mixed precision against FP64 at fixed error: 5 backward-Euler steps
+    on the 16^3 cube from the oracle's initial state, once with FP64 and
+    once with mixed (FP32 inner) solves.  Each path's error against the
+    oracle's own trajectory (stored by tests/golden/make_cube16_trajectory.py,
+    read here as data) is reported per output: the nine fields (relative L2,
+    largest over the steps), the cell voltage, the volume means and the
+    conservation sums."""
     import torch
     import synth
     from paper_2511_05233_amd import lsbdg
     w = synth.WORKLOADS["cube16_q1"]
     D0, i0 = synth.sample_transport_kinetics(w.param_seed)
     ctx = lsbdg.Context(w.nx, w.ny, w.nz, w.h, w.order, w.mask(), D0=D0, kE=i0 / FARADAY, f_C=w.f_C)
-    u0, _ = ctx.initial_state(inner="f64", coarse=coarse)
+    gold = None
+    if os.path.exists(GOLDEN_CUBE16):
+        with np.load(GOLDEN_CUBE16, allow_pickle=False) as z:
+            gold = {k: z[k] for k in z.files}
+    if gold is not None and abs(float(gold["dt"]) - dt) == 0.0 and gold["u"].shape[0] > steps:
+        u0 = torch.tensor(gold["u"][0], device="cuda:0")
+        start = "the oracle's initial state"
+    else:
+        gold = None
+        u0, _ = ctx.initial_state(inner="f64", coarse=coarse)
+        start = "the GPU initial state (no stored oracle trajectory)"
+    area = w.ny * w.nz * w.h ** 2
     res = {}
     for inner in ("f64", "f32"):
         u = u0.clone()
         its = [0, 0]
         ctx.step(u.clone(), 0.0, dt, inner=inner, coarse=coarse)      # warm-up (allocations)
+        keep = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
             rep = ctx.step(u, k * dt, dt, inner=inner, coarse=coarse)
             its[0] += rep["newton_its"]
             its[1] += rep["gmres_its"]
+            keep.append(u.clone())
         torch.cuda.synchronize()
-        res[inner] = (time.perf_counter() - t0, u, its)
+        wall = time.perf_counter() - t0
+        err = None
+        if gold is not None:
+            fe = np.zeros(9)
+            ue = me = 0.0
+            se = np.zeros(4)
+            for k, uk in enumerate(keep, start=1):
+                ref = gold["u"][k]
+                got = uk.cpu().numpy()
+                fe = np.maximum(fe, [np.linalg.norm(got[f] - ref[f]) / max(np.linalg.norm(ref[f]), 1e-300)
+                                     for f in range(9)])
+                out = ctx.outputs(uk, k * dt)
+                ue = max(ue, abs(out["U_cell"] - gold["U_cell"][k]) / abs(gold["U_cell"][k]))
+                scale = np.append(np.sqrt(np.mean(ref ** 2, axis=(1, 2))), abs(gold["means"][k][9]))
+                me = max(me, float(np.max(np.abs(out["means"] - gold["means"][k]) / np.maximum(scale, 1e-300))))
+                ds = np.abs(out["sums"] - gold["sums"][k])
+                ds[:3] /= np.abs(gold["sums"][k][:3])
+                ds[3] /= float(gold["j_el"]) * area
+                se = np.maximum(se, ds)
+            err = {"rel_l2_per_field": [float(f"{x:.2e}") for x in fe], "U_cell_rel": float(f"{ue:.2e}"),
+                   "means_rel": float(f"{me:.2e}"), "sums_rel": [float(f"{x:.2e}") for x in se]}
+        res[inner] = (wall, u, its, err)
     rel = [float(torch.linalg.norm(res["f32"][1][f] - res["f64"][1][f]) /
                  torch.clamp(torch.linalg.norm(res["f64"][1][f]), min=1e-300)) for f in range(9)]
     log(f"[bench] five 16^3 steps: f64 {res['f64'][0]:.3f} s, mixed {res['f32'][0]:.3f} s")
-    return {"workload": "cube16_q1: 16^3 voxels, 0.1C, 5 backward-Euler steps of 0.1 s from the initial state",
+    ctx.close()
+    return {"workload": f"cube16_q1: 16^3 voxels, 0.1C, 5 backward-Euler steps of 0.1 s from {start}",
             "s_f64": round(res["f64"][0], 4), "s_mixed": round(res["f32"][0], 4),
             "mixed_speedup": round(res["f64"][0] / res["f32"][0], 3),
             "newton_gmres_f64": res["f64"][2], "newton_gmres_mixed": res["f32"][2],
+            "error_vs_oracle_f64": res["f64"][3], "error_vs_oracle_mixed": res["f32"][3],
             "rel_l2_mixed_vs_f64": [float(f"{x:.2e}") for x in rel]}
 
 
 def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9, max_steps=5000):
-    """Full galvanostatic discharge under the naive controller (Sec. 2.7):
+    """Full galvanostatic discharge under the naive controller (Sec. 2.8):
     from the initial state until U_cell <= cutoff or t >= 3600 / f_C."""
     import torch
     import synth
@@ -543,7 +634,12 @@ def main(argv=None):
                     help="skip the batched-operator record of the default line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--oracle-timing", nargs=2, metavar=("WORKLOAD", "SECONDS"), default=None,
+                    help=argparse.SUPPRESS)
     args = ap.parse_args(argv)
+    if args.oracle_timing:
+        print(json.dumps(_oracle_timing(args.oracle_timing[0], float(args.oracle_timing[1]))), flush=True)
+        return 0
     if args.fp32_blocks:
         SOLVER_EXTRA["block_bf16"] = 0
     if args.gpus != 1:
@@ -589,7 +685,10 @@ def main(argv=None):
     log(f"[bench] initial state: {rep0['newton_its']} Newton, {rep0['gmres_its']} GMRES")
     t = 0.0
     if args.mode == "newton":
-        newton_iterations(ctx, u, t, args.dt, args.warmup, args.inner, log, args.verbose, args.coarse, args.coarse_agg)
+        # warm-up on a copy: the timed iterations start from the step's own
+        # initial iterate (the old mass of the step is that of u)
+        newton_iterations(ctx, u.clone(), t, args.dt, args.warmup, args.inner, log, args.verbose, args.coarse,
+                          args.coarse_agg)
         u_start = u.clone() if args.compare_f64 else None
         t_start = t
         torch.cuda.synchronize()
@@ -614,8 +713,8 @@ def main(argv=None):
         done = args.steps
         ms_step = wall * 1e3 / args.steps
 
-    kernels, (k_apply, b_apply, ms_apply) = time_kernels(ctx, u, t, args.dt, args.inner, stream, dev, log)
-    achieved = b_apply / (ms_apply * 1e-3) / 1e9
+    kernels, (k_op, b_op, ms_op) = time_kernels(ctx, u, t, args.dt, args.inner, stream, dev, log)
+    achieved = b_op / (ms_op * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(n_dof / (kernels["jvp_condensed"]["ms"] * 1e-3) / 1e9, 3),
@@ -641,9 +740,11 @@ def main(argv=None):
                    "coarse": args.coarse, "coarse_agg": args.coarse_agg, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(w.name, k_apply),
-                     "kernel": k_apply, "ms": round(ms_apply, 4),
-                     "bytes_per_launch": b_apply},
+                     "traffic": recorded_traffic(w.name, k_op),
+                     "kernel": k_op, "ms": round(ms_op, 4),
+                     "bytes_per_launch": b_op,
+                     "bytes_per_dof": round(b_op / n_dof, 2),
+                     "residual_f64": {k: kernels["residual_f64"][k] for k in ("ms", "GB/s", "frac", "bytes")}},
         "kernels": kernels,
     }
     if args.compare_f64 and args.inner == "f32":

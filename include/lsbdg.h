@@ -3,16 +3,16 @@
  * scale-resolved lithium-sulfur cathode model of arXiv 2511.05233
  * ("Structure Matters"), for AMD Instinct MI355X (gfx950).
  *
- * The problem (Sec. 2.4-2.6, Tab. 4): on a voxelised porous cathode of
+ * The problem (Sec. 2.2-2.6, Tab. 4): on a voxelised porous cathode of
  * nx x ny x nz cubic voxels of edge h (x = transport axis), the unknowns per
  * DG node are the six dissolved-species concentrations
  *     c = (Li+, S8(L), S8^2-, S6^2-, S4^2-, S^2-)  [mol/m^3],
  * the liquid potential Phi_L [V], and the solid volume fractions
  * (eps_S8, eps_Li2S) of Tab. 4's solid-phase mass equations.  The solid is
- * equipotential at V = dPhi0 of Tab. InitialState (the gauge of Sec. 2.9).
+ * equipotential at V = dPhi0 of Tab. InitialState (the gauge of Sec. 2.10).
  * Species obey Nernst-Planck transport with Bruggeman-effective,
  * viscosity-scaled diffusivities (Eq. 02-03, 16a); Phi_L obeys the
- * anion-eliminated charge balance (Tab. 4, Sec. 2.6 item (i)); reactions
+ * anion-eliminated charge balance (Tab. 4; Sec. 2.7 item (i)); reactions
  * are the Tradeoff Chemistry of Tab. 3 with Butler-Volmer kinetics
  * (Eq. 05-06, 18-24).  Space: interior-penalty DG with harmonic-mean
  * coefficients (Eq. 43-47) on tensor-product Gauss-Legendre nodes of degree
@@ -99,7 +99,7 @@ typedef struct {
   double sigma;         /* interior-penalty factor; <= 0: 1 for k = 0, (k+1)^2 else */
   double c_min;         /* activity clamp [mol/m^3] */
   double epsL_min;      /* floor of the liquid fraction */
-  int32_t use_TH;       /* 1: multiply C2 and E4 by T_H(t) (Eq. 56, Sec. 2.9) */
+  int32_t use_TH;       /* 1: multiply C2 and E4 by T_H(t) (Eq. 56, Sec. 2.10) */
   int32_t reserved;
 } dg_params;
 
@@ -158,7 +158,7 @@ int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const voi
 int dg_linearize(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt, dg_stream stream);
 
 /* Element block-Jacobi preconditioner (replaces the paper's BoomerAMG
- * preconditioner of Sec. 2.8 inside GMRES).  Builds the exact
+ * preconditioner of Sec. 2.9 inside GMRES).  Builds the exact
  * element-diagonal blocks of the condensed 7-field Jacobian at (u, t_new,
  * dt) -- volume, own-face, time and source terms of each voxel's rows with
  * respect to its own 56 unknowns (Q1) -- and inverts them in place (Gauss-
@@ -187,8 +187,17 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
 int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream);
 
 /* Copy the stored inverse blocks (Ne blocks of 56 x 56, column-major:
- * out[e][col][row], row/col = field * 8 + node) to the device buffer out. */
+ * out[e][col][row], row/col = field * 8 + node) to the device buffer out,
+ * in the precision of the setup (dg_blockjacobi_info); out must hold
+ * Ne * 56 * 56 values of that precision.  DG_ESTATE when no inverses are
+ * stored (none set up, or only the bfloat16 copy of a solve). */
 int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream);
+
+/* Precision (DG_F64 or DG_F32) and edge (56) of the stored inverse blocks,
+ * so that a caller sizes the buffer of dg_blockjacobi_export from the
+ * library's own state.  Host call, no device work.  DG_ESTATE when no
+ * inverses are stored. */
+int dg_blockjacobi_info(const dg_ctx* ctx, int32_t* prec, int32_t* block_size);
 
 /* Options of the Newton-Krylov step solver. */
 typedef struct {
@@ -246,7 +255,7 @@ typedef struct {
 /* One backward-Euler step (Eq. 50) from t_n to t_n + dt: on entry u holds
  * u^n (device, FP64, 9 fields), on exit the Newton root u^{n+1} of
  * dg_residual (T_H at t_n + dt).  Newton's method in FP64 with a backtracking
- * line search (the paper uses PETSc newtonls, Sec. 2.8); positive unknowns
+ * line search (the paper uses PETSc newtonls, Sec. 2.9); positive unknowns
  * are updated multiplicatively (Newton in their logarithms).  Each linear
  * solve is GMRES(m) on the condensed 7-field Jacobian, scaled by the unknown
  * magnitudes and preconditioned by the element blocks plus a coarse
@@ -261,12 +270,12 @@ typedef struct {
  * slowly) fail to halve the update, when the linear solve stagnates above
  * its tolerance, or when the line search finds no decrease.
  * Synchronises the stream.  DG_ENOCONV: u holds the last iterate and the
- * report is filled; the controller halves dt (Sec. 2.7).  DG_ENAN: non-finite
+ * report is filled; the controller halves dt (Sec. 2.8).  DG_ENAN: non-finite
  * residual. */
 int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,
             dg_step_report* report, dg_stream stream);
 
-/* Initial state (Tab. InitialState, Sec. 2.9): u (device, FP64, 9 fields)
+/* Initial state (Tab. InitialState, Sec. 2.10): u (device, FP64, 9 fields)
  * is set to the chemical-equilibrium concentrations, the phase's solid
  * fractions and the electrolyte potential of the steady charge balance at
  * time t0: the charge rows of dg_residual are solved for Phi_L with the
@@ -296,7 +305,7 @@ int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts
 int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* means, double* sums,
                dg_stream stream);
 
-/* Adaptive time control (Sec. 2.7). */
+/* Adaptive time control (Sec. 2.8). */
 typedef enum { DG_CTRL_NAIVE = 0, DG_CTRL_H211B = 1 } dg_controller_kind;
 
 typedef struct {

@@ -972,6 +972,20 @@ int batch_blocks(dg_batch* b, const S* u, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+
+// Means, sums and cell voltage from the kNumSums node sums of outputs_kernel.
+void outputs_from_sums(const dg_ctx* ctx, const double* acc, double* U_cell, double* means, double* sums) {
+  const double nodes = double(ctx->Ne) * ctx->np;
+  if (means)
+    for (int f = 0; f < 10; ++f) means[f] = acc[f] / nodes;
+  if (sums)
+    for (int j = 0; j < 4; ++j) sums[j] = acc[10 + j];
+  if (U_cell) *U_cell = acc[14] / (double(ctx->mesh.ny) * ctx->mesh.nz * 4.0);
+}
+
+}  // namespace
+
 extern "C" {
 
 void dg_params_default(dg_params* p) {
@@ -1262,6 +1276,15 @@ int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream str
   return DG_OK;
 }
 
+int dg_blockjacobi_info(const dg_ctx* ctx, int32_t* prec, int32_t* block_size) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!prec || !block_size) return fail(DG_EINVAL, "dg_blockjacobi_info: null argument");
+  if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_info: no inverses stored");
+  *prec = ctx->blocks_prec;
+  *block_size = kNB;
+  return DG_OK;
+}
+
 int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
   if (!out) return fail(DG_EINVAL, "dg_blockjacobi_export: null array");
@@ -1364,12 +1387,7 @@ int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* mea
       for (int b = 0; b < nb; ++b) a += part[size_t(j) * nb + b];
       acc[j] = a;
     }
-    const double nodes = double(ctx->Ne) * ctx->np;
-    if (means)
-      for (int f = 0; f < 10; ++f) means[f] = acc[f] / nodes;
-    if (sums)
-      for (int j = 0; j < 4; ++j) sums[j] = acc[10 + j];
-    if (U_cell) *U_cell = acc[14] / (double(ctx->mesh.ny) * ctx->mesh.nz * 4.0);
+    outputs_from_sums(ctx, acc, U_cell, means, sums);
     return DG_OK;
   } catch (const std::bad_alloc&) {
     return fail(DG_ENOMEM, "dg_outputs: host allocation failed");

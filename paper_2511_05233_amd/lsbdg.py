@@ -37,6 +37,7 @@ _SIGNATURES = {
     "dg_blockjacobi_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_blockjacobi_apply_bf16": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_blockjacobi_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_blockjacobi_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_solver_opts_default": (None, [C.c_void_p]),
     "dg_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p]),
@@ -187,6 +188,19 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _check_layout(t, shape, like=None):
+    """Shape of an array argument, and dtype and device equal to those of
+    `like` (the library reads and writes every array of a call in one
+    precision: a mismatched buffer would be over- or under-run)."""
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if like is not None:
+        if t.dtype != like.dtype:
+            raise ValueError(f"expected dtype {like.dtype}, got {t.dtype}")
+        if t.device != like.device:
+            raise ValueError(f"expected device {like.device}, got {t.device}")
+
+
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -292,28 +306,25 @@ class Context:
     def _shape(self, nf):
         return (nf, self.n_elem, self.n_nodes)
 
-    def _check_arr(self, t, nf):
-        if tuple(t.shape) != self._shape(nf):
-            raise ValueError(f"expected shape {self._shape(nf)}, got {tuple(t.shape)}")
+    def _check_arr(self, t, nf, like=None):
+        _check_layout(t, self._shape(nf), like)
 
     def mass(self, u, out=None):
         import torch
         self._check_arr(u, 9)
         if out is None:
             out = torch.empty(self._shape(8), dtype=u.dtype, device=u.device)
-        self._check_arr(out, 8)
+        self._check_arr(out, 8, like=u)
         _check("dg_mass", self._lib.dg_mass(self._h, _prec(u), _ptr(u), _ptr(out), _stream()))
         return out
 
     def residual(self, u, m_old, t_new, dt, out=None):
         import torch
         self._check_arr(u, 9)
-        self._check_arr(m_old, 8)
-        if m_old.dtype != u.dtype:
-            raise ValueError("u and m_old must share a dtype")
+        self._check_arr(m_old, 8, like=u)
         if out is None:
             out = torch.empty(self._shape(9), dtype=u.dtype, device=u.device)
-        self._check_arr(out, 9)
+        self._check_arr(out, 9, like=u)
         _check("dg_residual", self._lib.dg_residual(self._h, _prec(u), _ptr(u), _ptr(m_old),
                                                     float(t_new), float(dt), _ptr(out), _stream()))
         return out
@@ -331,12 +342,10 @@ class Context:
         condensed = condensed or linearized
         nf = 7 if condensed else 9
         self._check_arr(u, 9)
-        self._check_arr(v, nf)
-        if v.dtype != u.dtype:
-            raise ValueError("u and v must share a dtype")
+        self._check_arr(v, nf, like=u)
         if out is None:
             out = torch.empty(self._shape(nf), dtype=u.dtype, device=u.device)
-        self._check_arr(out, nf)
+        self._check_arr(out, nf, like=u)
         mode = DG_JVP_LINEARIZED7 if linearized else (DG_JVP_CONDENSED7 if condensed else DG_JVP_FULL9)
         _check("dg_jvp", self._lib.dg_jvp(self._h, _prec(u), mode, _ptr(u), _ptr(v), float(t_new),
                                           float(dt), _ptr(out), _stream()))
@@ -346,7 +355,6 @@ class Context:
         """Build and invert the condensed element blocks at u (precision dtype)."""
         self._check_arr(u, 9)
         uu = u if dtype is None or u.dtype == dtype else u.to(dtype)
-        self._bj_dtype = uu.dtype
         _check("dg_blockjacobi_setup", self._lib.dg_blockjacobi_setup(
             self._h, _prec(uu), _ptr(uu), float(t_new), float(dt), _stream()))
 
@@ -356,7 +364,7 @@ class Context:
         self._check_arr(x, 7)
         if out is None:
             out = torch.empty_like(x)
-        self._check_arr(out, 7)
+        self._check_arr(out, 7, like=x)
         if bf16:
             if x.dtype != torch.float32:
                 raise ValueError("the bfloat16 apply takes FP32 vectors")
@@ -369,7 +377,10 @@ class Context:
 
     def blockjacobi_export(self):
         import torch
-        out = torch.empty((self.n_elem, 56, 56), dtype=self._bj_dtype, device="cuda")
+        prec, nb = C.c_int32(), C.c_int32()
+        _check("dg_blockjacobi_info", self._lib.dg_blockjacobi_info(self._h, C.byref(prec), C.byref(nb)))
+        dtype = torch.float64 if prec.value == DG_F64 else torch.float32
+        out = torch.empty((self.n_elem, nb.value, nb.value), dtype=dtype, device="cuda")
         _check("dg_blockjacobi_export", self._lib.dg_blockjacobi_export(self._h, _ptr(out), _stream()))
         return out
 
@@ -410,7 +421,10 @@ class Context:
 
     def outputs(self, u, t):
         """U_cell [V], means (9 unknowns + c_S), sums (S, Li, electrons [mol], current [A])."""
+        import torch
         self._check_arr(u, 9)
+        if u.dtype != torch.float64:
+            raise ValueError("the state is FP64")
         U = C.c_double()
         means = (C.c_double * 10)()
         sums = (C.c_double * 4)()
@@ -496,9 +510,8 @@ class Batch:
     def _shape(self, nf):
         return (nf, self.n_elem, 8)
 
-    def _check_arr(self, t, nf):
-        if tuple(t.shape) != self._shape(nf):
-            raise ValueError(f"expected shape {self._shape(nf)}, got {tuple(t.shape)}")
+    def _check_arr(self, t, nf, like=None):
+        _check_layout(t, self._shape(nf), like)
 
     def _times(self, x):
         a = np.broadcast_to(np.asarray(x, dtype=np.float64), (self.n,))
@@ -509,19 +522,17 @@ class Batch:
         self._check_arr(u, 9)
         if out is None:
             out = torch.empty(self._shape(8), dtype=u.dtype, device=u.device)
-        self._check_arr(out, 8)
+        self._check_arr(out, 8, like=u)
         _check("dg_batch_mass", self._lib.dg_batch_mass(self._h, _prec(u), _ptr(u), _ptr(out), _stream()))
         return out
 
     def residual(self, u, m_old, t_new, dt, out=None):
         import torch
         self._check_arr(u, 9)
-        self._check_arr(m_old, 8)
-        if m_old.dtype != u.dtype:
-            raise ValueError("u and m_old must share a dtype")
+        self._check_arr(m_old, 8, like=u)
         if out is None:
             out = torch.empty(self._shape(9), dtype=u.dtype, device=u.device)
-        self._check_arr(out, 9)
+        self._check_arr(out, 9, like=u)
         t, d = self._times(t_new), self._times(dt)
         _check("dg_batch_residual", self._lib.dg_batch_residual(
             self._h, _prec(u), _ptr(u), _ptr(m_old), t.ctypes.data, d.ctypes.data, _ptr(out), _stream()))
@@ -538,12 +549,10 @@ class Batch:
         condensed = condensed or linearized
         nf = 7 if condensed else 9
         self._check_arr(u, 9)
-        self._check_arr(v, nf)
-        if v.dtype != u.dtype:
-            raise ValueError("u and v must share a dtype")
+        self._check_arr(v, nf, like=u)
         if out is None:
             out = torch.empty(self._shape(nf), dtype=u.dtype, device=u.device)
-        self._check_arr(out, nf)
+        self._check_arr(out, nf, like=u)
         mode = DG_JVP_LINEARIZED7 if linearized else (DG_JVP_CONDENSED7 if condensed else DG_JVP_FULL9)
         t, d = self._times(t_new), self._times(dt)
         _check("dg_batch_jvp", self._lib.dg_batch_jvp(self._h, _prec(u), mode, _ptr(u), _ptr(v), t.ctypes.data,
@@ -561,7 +570,7 @@ class Batch:
         self._check_arr(x, 7)
         if out is None:
             out = torch.empty_like(x)
-        self._check_arr(out, 7)
+        self._check_arr(out, 7, like=x)
         _check("dg_batch_blockjacobi_apply", self._lib.dg_batch_blockjacobi_apply(
             self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
         return out
@@ -585,13 +594,11 @@ class Batch:
         (shape, ms, ms of the default shape), and the number of shapes tried."""
         import torch
         self._check_arr(u, 9)
-        self._check_arr(v, 9)
-        self._check_arr(m_old, 8)
-        if v.dtype != u.dtype or m_old.dtype != u.dtype:
-            raise ValueError("u, v and m_old must share a dtype")
+        self._check_arr(v, 9, like=u)
+        self._check_arr(m_old, 8, like=u)
         if work is None:
             work = torch.empty(self._shape(9), dtype=u.dtype, device=u.device)
-        self._check_arr(work, 9)
+        self._check_arr(work, 9, like=u)
         rep = DgBatchTuning()
         t, d = self._times(t_new), self._times(dt)
         _check("dg_batch_autotune", self._lib.dg_batch_autotune(

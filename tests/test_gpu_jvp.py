@@ -12,8 +12,17 @@ torch = pytest.importorskip("torch")
 # FP64: both sides are exact derivatives of the same arithmetic up to
 # rounding; cancellation between flux terms inside a row is the limit.
 TOL64 = 1e-10
-# FP32 dual numbers against the FP64 derivative.
-TOL32 = 5e-4
+# FP32 tangent against the FP64 derivative of the same FP32-rounded inputs:
+# unit roundoff 6e-8 amplified by the cancellation inside a row (the full
+# slab shows 2e-7).
+TOL32 = 1e-5
+# The full 9-field tangent at random states also carries the rows of S^2-
+# and Li2S(S), whose sources are differences of Butler-Volmer and
+# solubility exponentials near equilibrium (E4, E6, C2 with K_sp,2 = 8e-15):
+# an exponential of an argument |A| ~ 20 rounds to about |A| u32 = 1.2e-6
+# relative in FP32, and the difference of two such terms loses another
+# order (observed 1.6e-5 and 1.0e-5 on those two rows, 1e-7 elsewhere).
+TOL32_FULL = 5e-5
 
 
 def _case(shape, seed, dtype, condensed, **kw):
@@ -52,7 +61,7 @@ def test_jvp_fp64(shape, seed, condensed):
 def test_jvp_fp32(condensed):
     err = _case((12, 8, 6), 3, torch.float32, condensed)
     print("  errors", err, flush=True)
-    assert np.all(err < TOL32), err
+    assert np.all(err < (TOL32 if condensed else TOL32_FULL)), err
 
 
 def test_jvp_paper_parameters_condensed():
@@ -107,3 +116,30 @@ def test_krylov_jvp_full_slab_sampled():
     err = field_errors(jv[:, elems], ref)
     print("  sampled field errors", err, flush=True)
     assert np.all(err < TOL32), err
+
+
+@pytest.mark.parametrize("condensed", [False, True])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_jvp_at_and_below_the_concentration_floor(dtype, condensed):
+    """Tangents where S4^2- and S^2- sit at, below and across the activity
+    clamp c_min and Li+ is negative at a node: the clamped activities have
+    zero derivative on both sides, and the harmonic-mean guard switches."""
+    from tests.test_gpu_residual import _floor_state
+    P, ctx, mask = problem_and_context(6, 5, 4, mask_seed=11, param_seed=11)
+    u = _floor_state(P, mask, 33)
+    nf = 7 if condensed else 9
+    rng = np.random.default_rng(34)
+    scale = np.array([1500, 6, 6e-3, 4e-3, 2e-3, 4e-12, 3e-3, 0.2, 7e-6])[:nf]
+    v = scale[:, None, None] * rng.standard_normal((nf, P.n_elem, P.n_nodes))
+    v[:, mask.reshape(-1) == 0, :] *= np.array([1] * 7 + [0, 0])[:nf, None, None]
+    dev = torch.device("cuda:0")
+    jv = ctx.jvp(torch.tensor(u, device=dev, dtype=dtype), torch.tensor(v, device=dev, dtype=dtype),
+                 0.9, 0.05, condensed=condensed).cpu().numpy().astype(np.float64)
+    if dtype == torch.float32:
+        u = u.astype(np.float32).astype(np.float64)
+        v = v.astype(np.float32).astype(np.float64)
+    m = odg.old_mass(P, u)
+    ref = odg.jvp_condensed(P, u, v, m, 0.9, 0.05) if condensed else odg.jvp(P, u, v, m, 0.9, 0.05)
+    err = field_errors(jv, ref)
+    print(f"  {dtype} condensed={condensed} floor-state errors", err, flush=True)
+    assert np.all(err < (TOL64 if dtype == torch.float64 else (TOL32 if condensed else TOL32_FULL))), err

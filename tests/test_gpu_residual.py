@@ -112,3 +112,36 @@ def test_residual_full_slab_sampled():
     err = field_errors(rn[:, elems], ref)
     print("  sampled field errors", err, flush=True)
     assert np.all(err < TOL64), err
+
+
+def _floor_state(P, mask, seed):
+    """A random state whose trace species sit at and below the activity
+    clamp c_min: S4^2- and S^2- at exactly c_min, half of it, zero, slightly
+    negative and clearly negative at scattered nodes; Li+ negative at one
+    node (every clamp and the harmonic-mean guard take their other branch)."""
+    u = synth.random_state(P.n_elem, P.n_nodes, seed, phase=mask, phi_spread=5e-3)
+    rng = np.random.default_rng(seed)
+    cmin = P.c_min
+    vals = [cmin, 0.5 * cmin, 0.0, -1e-10, -1e-4]
+    for f in (4, 5):
+        idx = rng.choice(P.n_elem * P.n_nodes, size=40, replace=False)
+        flat = u[f].reshape(-1)
+        for j, k in enumerate(idx):
+            flat[k] = vals[j % len(vals)]
+    u[0].reshape(-1)[rng.integers(0, P.n_elem * P.n_nodes)] = -1e-6
+    return u
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_residual_at_and_below_the_concentration_floor(dtype):
+    P, ctx, mask = problem_and_context(6, 5, 4, mask_seed=11, param_seed=11)
+    u = _floor_state(P, mask, 31)
+    uo = synth.random_state(P.n_elem, P.n_nodes, 32, phase=mask)
+    dev = torch.device("cuda:0")
+    m = ctx.mass(torch.tensor(uo, device=dev, dtype=dtype))
+    r = ctx.residual(torch.tensor(u, device=dev, dtype=dtype), m, 0.7, 0.05).cpu().numpy().astype(np.float64)
+    uu = u.astype(np.float32).astype(np.float64) if dtype == torch.float32 else u
+    ref = odg.residual(P, uu, m.cpu().numpy().astype(np.float64), 0.7, 0.05)
+    err = field_errors(r, ref)
+    print(f"  {dtype} floor-state field errors", err, flush=True)
+    assert np.all(err < (TOL64 if dtype == torch.float64 else TOL32)), err
