@@ -305,6 +305,21 @@ int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts
 int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* means, double* sums,
                dg_stream stream);
 
+/* dg_outputs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results, bit for bit, with no device allocation.
+ * Its partial sums live in a library-owned static device array of
+ * 15 x 1024 + 15 doubles (123 KB), which every GPU the library runs on
+ * holds until the process ends; the array's need does not grow with the
+ * mesh (a fixed grid of 1024 blocks strides over any number of nodes), so
+ * no size limit applies beyond those of dg_outputs.  Every call on one GPU
+ * shares that GPU's array and overwrites all of it before reading it:
+ * calls that overlap on one GPU (concurrent streams or host threads) race
+ * and must be serialised by the caller.  Arguments, results and errors as
+ * dg_outputs; synchronises the stream. */
+int dg_outputs_noalloc(dg_ctx* ctx, const void* u, double t, double* U_cell, double* means, double* sums,
+                       dg_stream stream);
+
 /* Adaptive time control (Sec. 2.8). */
 typedef enum { DG_CTRL_NAIVE = 0, DG_CTRL_H211B = 1 } dg_controller_kind;
 

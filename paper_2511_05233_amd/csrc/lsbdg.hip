@@ -134,6 +134,41 @@ int check_ctx(const dg_ctx* c) {
 
 }  // namespace
 
+// Device scratch of dg_outputs_noalloc: the block partials of the outputs
+// kernel (kNumSums x kOutBlocks) and the finished sums (kNumSums), 123 KB
+// per device, held by every GPU the library runs on until the process
+// ends.  Host code never uses this name as an address: each device's own
+// copy is looked up once with hipGetSymbolAddress and used from then on.
+constexpr int kOutBlocks = 1024;
+constexpr size_t kScratchDoubles = size_t(kNumSums) * kOutBlocks + kNumSums;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Address of the current device's scratch (looked up on the first call on
+// that device, with that device current).
+int device_scratch(double** out) {
+  int dev = -1;
+  DG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return DG_OK;
+}
+
+}  // namespace
+
 namespace {
 
 template <typename S, typename N, int Mode>
@@ -1050,6 +1085,11 @@ int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params,
       const double c_theo = 16.0 * kFaraday / kMolar[0];
       c->j_el = params->f_C / 3600.0 * c_theo * kRho[0] * vol / area;
     }
+    double* scr = nullptr;
+    if (int s = device_scratch(&scr)) {
+      delete c;
+      return s;
+    }
     hipError_t err = hipMalloc(&c->d_phase, size_t(Ne));
     if (err != hipSuccess) {
       delete c;
@@ -1368,7 +1408,7 @@ int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* mea
     if (int s = check_ctx(ctx)) return s;
     if (!u) return fail(DG_EINVAL, "dg_outputs: null state");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    constexpr int nb = 1024;
+    constexpr int nb = kOutBlocks;
     SolverWork& W = ctx->work;
     hipError_t e = W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double));
     if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_outputs workspace: ") + hipGetErrorString(e));
@@ -1393,6 +1433,35 @@ int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* mea
     return fail(DG_ENOMEM, "dg_outputs: host allocation failed");
   } catch (...) {
     return fail(DG_EINVAL, "dg_outputs: unexpected exception");
+  }
+}
+
+int dg_outputs_noalloc(dg_ctx* ctx, const void* u, double t, double* U_cell, double* means, double* sums,
+                       dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (!u) return fail(DG_EINVAL, "dg_outputs_noalloc: null state");
+    double* scr = nullptr;
+    if (int s = device_scratch(&scr)) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* partial = scr;                                  // kNumSums x kOutBlocks
+    double* total = scr + size_t(kNumSums) * kOutBlocks;    // kNumSums
+    const DevParams P = make_params(ctx, t, 1.0);
+    const double RT = kGas * ctx->params.T;
+    const double q = ctx->j_el / (kFaraday * kKEanode);
+    // every partial and every sum is overwritten before it is read: nothing
+    // to clear between calls
+    hipLaunchKernelGGL(outputs_kernel, dim3(kOutBlocks), dim3(256), 0, st, static_cast<const double*>(u),
+                       ctx->d_phase, P, q, 2.0 * RT / kFaraday, partial);
+    hipLaunchKernelGGL(outputs_finish_kernel, dim3(1), dim3(64), 0, st, partial, kOutBlocks, total);
+    DG_HIP(hipGetLastError());
+    double acc[kNumSums];
+    DG_HIP(hipMemcpyAsync(acc, total, sizeof(acc), hipMemcpyDeviceToHost, st));
+    DG_HIP(hipStreamSynchronize(st));
+    outputs_from_sums(ctx, acc, U_cell, means, sums);
+    return DG_OK;
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_outputs_noalloc: unexpected exception");
   }
 }
 

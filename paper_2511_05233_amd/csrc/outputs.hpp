@@ -75,6 +75,17 @@ outputs_kernel(const double* __restrict__ U, const uint8_t* __restrict__ phase, 
   }
 }
 
+// Sum of the block partials of outputs_kernel, one thread per sum, in block
+// order (the order, and so the rounding, of the host sum of dg_outputs).
+__global__ void __launch_bounds__(64)
+outputs_finish_kernel(const double* __restrict__ partial, int nb, double* __restrict__ sums) {
+  const int j = threadIdx.x;
+  if (j >= kNumSums) return;
+  double a = 0.0;
+  for (int b = 0; b < nb; ++b) a += partial[int64_t(j) * nb + b];
+  sums[j] = a;
+}
+
 // Relative difference sums for the H211b error: partial[0] = sum (a - b)^2,
 // partial[gridDim] = sum a^2.
 __global__ void __launch_bounds__(256)

@@ -45,6 +45,8 @@ _SIGNATURES = {
                                    C.c_void_p]),
     "dg_outputs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
+    "dg_outputs_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
     "dg_controller_init": (None, [C.c_void_p, C.c_int32, C.c_double, C.c_double]),
     "dg_advance": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
@@ -419,8 +421,9 @@ class Context:
             raise err
         return rep.as_dict()
 
-    def outputs(self, u, t):
-        """U_cell [V], means (9 unknowns + c_S), sums (S, Li, electrons [mol], current [A])."""
+    def outputs(self, u, t, noalloc=False):
+        """U_cell [V], means (9 unknowns + c_S), sums (S, Li, electrons [mol], current [A]);
+        noalloc: through dg_outputs_noalloc (no device allocation)."""
         import torch
         self._check_arr(u, 9)
         if u.dtype != torch.float64:
@@ -428,8 +431,8 @@ class Context:
         U = C.c_double()
         means = (C.c_double * 10)()
         sums = (C.c_double * 4)()
-        _check("dg_outputs", self._lib.dg_outputs(self._h, _ptr(u), float(t), C.byref(U), means, sums,
-                                                  _stream()))
+        fn = "dg_outputs_noalloc" if noalloc else "dg_outputs"
+        _check(fn, getattr(self._lib, fn)(self._h, _ptr(u), float(t), C.byref(U), means, sums, _stream()))
         return {"U_cell": U.value, "means": np.array(means[:]), "sums": np.array(sums[:])}
 
     def advance(self, ctrl, t, u, inner="f32", **opts):
