@@ -25,6 +25,7 @@
 #include "model.hpp"
 #include "pointwise.hpp"
 #include "resid_q1.hpp"
+#include "brick_q1.hpp"
 #include "blockjacobi.hpp"
 #include "solver.hpp"
 #include "outputs.hpp"
@@ -191,6 +192,19 @@ void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void*
   hipLaunchKernelGGL((q1_kernel<S, N, Mode>), grid, block, 0, st, static_cast<const S*>(u),
                      static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), ctx->d_phase, P,
                      nb);
+}
+
+// Krylov operator: condensed tangent at the stored linearisation, one
+// workgroup per brick of 4 x 4 x 4 voxels (inner faces evaluated once).
+template <typename S>
+void launch_brick_jvp(const dg_ctx* ctx, const DevParams& P, const void* u, const void* v, const void* lin,
+                      void* out, hipStream_t st) {
+  const int nbx = (ctx->mesh.nx + kBE - 1) / kBE, nby = (ctx->mesh.ny + kBE - 1) / kBE;
+  const int64_t nbz = (ctx->mesh.nz + kBE - 1) / kBE;
+  const int64_t nb = (int64_t(nbx) * nby * nbz + 7) / 8 * 8;
+  hipLaunchKernelGGL(q1_brick_jvp_kernel<S>, dim3(unsigned(nb)), dim3(kBrickLanes), 0, st,
+                     static_cast<const S*>(u), static_cast<const S*>(v), static_cast<const S*>(lin),
+                     static_cast<S*>(out), ctx->d_phase, make_kp<S>(P), nbx, nby, nb);
 }
 
 // Linearisation coefficients of the condensed tangent at u (precision S).
@@ -370,9 +384,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   auto resid64 = [&](const double* uu, double* out) {
     launch_q1<double, double, kResidual>(ctx, P, uu, nullptr, m_old, out, st);
   };
-  auto jvp_cond = [&](const S* v7, S* out) {
-    launch_q1<S, Dual<S>, kJvpCondensed>(ctx, P, uS, v7, ctx->lin.p, out, st);
-  };
+  auto jvp_cond = [&](const S* v7, S* out) { launch_brick_jvp<S>(ctx, P, uS, v7, ctx->lin.p, out, st); };
   // coarse coefficients yc = E^-1 Z^T r (E = Z^T J Z, Z_f = sc on field f)
   auto coarse_coeffs = [&](const S* r) {
     hipLaunchKernelGGL(field_dot_kernel<S>, gred, blk, 0, st, sc, r, FS, partial);
@@ -1196,9 +1208,9 @@ int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const voi
       return fail(DG_ESTATE, "dg_jvp: no linearisation of this precision (dg_linearize)");
     }
     if (prec == DG_F64)
-      launch_q1<double, Dual<double>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
+      launch_brick_jvp<double>(ctx, P, u, v, ctx->lin.p, jv, st);
     else
-      launch_q1<float, Dual<float>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
+      launch_brick_jvp<float>(ctx, P, u, v, ctx->lin.p, jv, st);
   } else {
     return fail(DG_EINVAL, "dg_jvp: bad mode");
   }
