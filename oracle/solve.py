@@ -205,6 +205,68 @@ def _gmres_direction(P, u, R, m_old, t_new, dt, fields, S, blocks, rtol, restart
     return S * y.reshape(shape), count, info
 
 
+def _aggregate_index(P, edge):
+    """Aggregate of every element: cubes of edge^3 voxels, x fastest."""
+    e = np.arange(P.n_elem)
+    ix, iy, iz = e % P.nx, (e // P.nx) % P.ny, e // (P.nx * P.ny)
+    ax, ay = -(-P.nx // edge), -(-P.ny // edge)
+    return (ix // edge) + ax * ((iy // edge) + ay * (iz // edge)), ax * ay * (-(-P.nz // edge))
+
+
+class _SparseSolver:
+    """Newton directions from the probed sparse Jacobian J (kept for several
+    Newton iterations: the chord method, whose limit is the same root).
+
+    GMRES on the column-scaled system A = J diag(S), left-preconditioned by
+    the exact element-diagonal blocks of A plus an additive coarse
+    correction Z E^-1 Z^T on per-field constants over aggregates of edge^3
+    voxels (E = Z^T A Z, dense LU).  Only the speed of the linear solves
+    depends on these choices, not the root."""
+
+    def __init__(self, P, Jm, S, fields, edge=4):
+        import scipy.sparse as sp
+        import scipy.linalg as sla
+        nf, Ne, npn = len(fields), P.n_elem, P.n_nodes
+        nb = nf * npn
+        self.shape = (nf, Ne, npn)
+        A = (Jm @ sp.diags(S.reshape(-1))).tocsr()
+        self.A = A
+        # element blocks: unknown (f, e, a) -> element e, block index f npn + a
+        k = np.arange(nf * Ne * npn)
+        f_, rem = k // (Ne * npn), k % (Ne * npn)
+        e_, a_ = rem // npn, rem % npn
+        bi = f_ * npn + a_
+        C = A.tocoo()
+        same = e_[C.row] == e_[C.col]
+        blocks = np.zeros((Ne, nb, nb))
+        blocks[e_[C.row[same]], bi[C.row[same]], bi[C.col[same]]] = C.data[same]
+        self.binv = np.linalg.inv(blocks)
+        self.e_, self.bi = e_, bi
+        agg, na = _aggregate_index(P, edge)
+        cols = f_ * na + agg[e_]
+        self.Z = sp.csr_matrix((np.ones(len(k)), (k, cols)), shape=(len(k), nf * na))
+        E = (self.Z.T @ (A @ self.Z)).toarray()
+        self.lu = sla.lu_factor(E)
+        self._sla = sla
+
+    def precond(self, r):
+        Ne = self.shape[1]
+        rb = np.zeros((Ne, self.binv.shape[1]))
+        rb[self.e_, self.bi] = r
+        yb = np.einsum("eij,ej->ei", self.binv, rb)
+        y = yb[self.e_, self.bi]
+        return y + self.Z @ self._sla.lu_solve(self.lu, self.Z.T @ r)
+
+    def direction(self, R, rtol, restart):
+        n = self.A.shape[0]
+        b = -self.precond(R.reshape(-1))
+        op = spla.LinearOperator((n, n), matvec=lambda y: self.precond(self.A @ y), dtype=np.float64)
+        count = [0]
+        y, info = spla.gmres(op, b, rtol=rtol, atol=0.0, restart=restart, maxiter=10,
+                             callback=lambda _x: count.__setitem__(0, count[0] + 1), callback_type="pr_norm")
+        return y, count, info
+
+
 def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
            gmres_rtol=1e-13, restart=120, log=None, linear=None):
     """Damped Newton on the rows/columns ``fields``; other fields frozen.
@@ -215,6 +277,8 @@ def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
     plus the global coarse correction, and scaled by the unknown
     magnitudes), applies the update above and backtracks on the merit.
     Converged when a full step's largest relative update is below ``tol``.
+    linear="sparse": GMRES on the probed sparse Jacobian (see _SparseSolver),
+    re-probed when a full step fails to halve the update.
     Returns (u, info) with info = dict(iterations, gmres, update).
     """
     fields = list(fields)
@@ -234,11 +298,20 @@ def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
         return float(np.linalg.norm(block_apply_inverse(blocks0, Rv[fields]) / S0))
 
     merit = merit_of(R)
+    solver, prev_upd = None, np.inf
     for it in range(1, maxit + 1):
         if not np.all(np.isfinite(R)):
             raise NewtonFailure("non-finite residual")
         S = np.maximum(np.abs(u[fields]), _FLOOR[fields][:, None, None])
-        if linear == "direct":
+        if linear == "sparse":
+            if solver is None:
+                Jm = sparse_jacobian(P, u, m_old, t_new, dt, fields)
+                solver = _SparseSolver(P, Jm, S, fields)
+                S_solve = S
+            y, count, info = solver.direction(R[fields], gmres_rtol, restart)
+            du = (S_solve.reshape(-1) * y).reshape(shape)
+            total_gm += count[0]
+        elif linear == "direct":
             import scipy.sparse.linalg as _sl
             import scipy.sparse as _sp
             Jm = sparse_jacobian(P, u, m_old, t_new, dt, fields)
@@ -270,6 +343,9 @@ def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
         u, R, merit = ut, Rt, mt
         if lam == 1.0 and upd < tol:
             return u, {"iterations": it, "gmres": total_gm, "update": upd}
+        if linear == "sparse" and (lam < 1.0 or upd > 0.5 * prev_upd):
+            solver = None                  # chord slowed down: probe J again
+        prev_upd = upd
     raise NewtonFailure(f"no convergence after {maxit} iterations (update {upd:.3e})")
 
 

@@ -4,8 +4,10 @@ Workload: 16^3 voxels of 1 um, DG-Q1, porosity 0.6 (mask seed 0), transport
 and kinetics of parameter seed 0, 0.1C current on the separator face; the
 steady initial potential (Sec. 2.10, solved directly) and then five steps of
 dt = 0.1 s (the paper's implicit-Euler step of the time-stepping study,
-Sec. 3.3).  Every value is computed by the CPU oracle alone (``oracle/``);
-nothing here touches the HIP library.
+Sec. 3.3), each solved by the oracle's Newton iteration to a relative update
+below 1e-12 (its linear systems by GMRES on the probed sparse Jacobian).
+Every value is computed by the CPU oracle alone (``oracle/``); nothing here
+touches the HIP library.
 
 Output: ``cube16_q1_trajectory.npz`` beside this script (float64 arrays,
 no pickled objects): ``u`` of shape (6, 9, 4096, 8) -- the initial state and
@@ -52,7 +54,8 @@ def main():
     t = 0.0
     for s in range(STEPS):
         t1 = time.time()
-        u, info = osolve.be_step(P, u, t, DT, log=lambda m: print(f"[step {s + 1}]", m, flush=True))
+        u, info = osolve.be_step(P, u, t, DT, linear="sparse", gmres_rtol=1e-8, restart=60,
+                                 log=lambda m: print(f"[step {s + 1}]", m, flush=True))
         t += DT
         states.append(u)
         times.append(t)
