@@ -138,10 +138,19 @@ __device__ __forceinline__ void plane_of_slot(int q, int& d, int& j) {
   }
 }
 
+// LDS slots.  Node records: one pad word after every 32, so that the two
+// voxels of a face, 32 words apart, fall on different banks.  Face points:
+// 65 words per plane, so that the gather's reads of one voxel row from
+// several planes fall on different banks.
+__device__ __forceinline__ int rec_slot(int l) { return l + (l >> 5); }
+__device__ __forceinline__ int q_slot(int k) { return k + (k >> 6); }
+constexpr int kRecRow = kBrickLanes + kBrickLanes / 32;
+constexpr int kQRow = kFacePts + kPlanes;
+
 template <typename S>
 struct BrickLds {
-  S rec[kRec][kBrickLanes];          // node records, field-major
-  S q[7][kFacePts];                  // flux tangents of the face points
+  S rec[kRec][kRecRow];              // node records, field-major
+  S q[7][kQRow];                     // flux tangents of the face points
   int ph[kBrickVox];                 // voxel phases
 };
 
@@ -262,7 +271,8 @@ __device__ __forceinline__ void side_traces(const KP<S>& K, const S* nv, const S
 }
 
 template <typename S>
-__device__ __forceinline__ void rec_lds(const BrickLds<S>& L, int l, S* v, S* d) {
+__device__ __forceinline__ void rec_lds(const BrickLds<S>& L, int node, S* v, S* d) {
+  const int l = rec_slot(node);
 #pragma unroll
   for (int f = 0; f < 8; ++f) {
     v[f] = L.rec[f][l];
@@ -470,16 +480,17 @@ q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* _
 #pragma unroll
       for (int f = 0; f < 7; ++f) acc[f] += c * (dF[f] + xlane(dF[f], mask));
     }
+    const int sl = rec_slot(lane);
 #pragma unroll
     for (int f = 0; f < 7; ++f) {
-      L.rec[f][lane] = u[f];
-      L.rec[8 + f][lane] = v[f];
+      L.rec[f][sl] = u[f];
+      L.rec[8 + f][sl] = v[f];
     }
-    L.rec[7][lane] = u[7] + u[8];
-    L.rec[15][lane] = w0 + w1;
+    L.rec[7][sl] = u[7] + u[8];
+    L.rec[15][sl] = w0 + w1;
   } else {
 #pragma unroll
-    for (int f = 0; f < kRec; ++f) L.rec[f][lane] = S(0);
+    for (int f = 0; f < kRec; ++f) L.rec[f][rec_slot(lane)] = S(0);
   }
   if (n == 0) L.ph[vb] = ph;
   __syncthreads();
@@ -535,7 +546,7 @@ q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* _
       for (int f = 0; f < 7; ++f) q[f] = S(0);
     }
 #pragma unroll
-    for (int f = 0; f < 7; ++f) L.q[f][k] = q[f];
+    for (int f = 0; f < 7; ++f) L.q[f][q_slot(k)] = q[f];
   }
   __syncthreads();
   if (!valid) return;
@@ -554,7 +565,7 @@ q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* _
     for (int side = 0; side < 2; ++side) {
       const int s = side == 0 ? s_own : 1 - s_own;       // 1: the voxel's high face
       const S w = K.W2 * (side == 0 ? lam1 : lam0) * (s ? S(1) : S(-1));
-      const int k = plane_slot(d, c + s) * 64 + (t1 + 4 * t2) * 4 + p;
+      const int k = q_slot(plane_slot(d, c + s) * 64 + (t1 + 4 * t2) * 4 + p);
 #pragma unroll
       for (int f = 0; f < 7; ++f) acc[f] += w * L.q[f][k];
     }
