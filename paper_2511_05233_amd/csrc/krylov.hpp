@@ -471,4 +471,118 @@ solid_merit_kernel(const double* __restrict__ R, const double* __restrict__ U, i
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
+// ---- GMRES(m) control on the device ----
+//
+// The Hessenberg matrix, the Givens rotations, the rotated right side and the
+// stopping test of one restart cycle live in device memory and are updated
+// by single-workgroup kernels between the vector kernels of an iteration, so
+// an iteration needs no read-back: the host learns of convergence from a
+// flag it reads one iteration later, and the kernels of an iteration issued
+// past convergence change nothing (they test the flag).
+struct GmresState {
+  double H[kMaxDots * kMaxDots];   // H[i * kMaxDots + j], (m + 1) x m upper Hessenberg
+  double cs[kMaxDots], sn[kMaxDots], g[kMaxDots + 1];
+  double y[kMaxDots];              // solution of the cycle's least-squares problem
+  double beta0;                    // norm of the first residual of the solve
+  double rtol;                     // stopping test: |g_{j+1}| <= rtol beta0
+  double rel;                      // |g_{j+1}| / beta0 after the last column
+  double scale;                    // 1 / norm of the newest basis vector
+  int32_t done;                    // cycle finished (converged or breakdown)
+  int32_t converged;               // the stopping test held
+  int32_t cols;                    // columns of the cycle (j + 1 at the end)
+  int32_t its;                     // iterations of the whole solve
+};
+
+// Start of a cycle: beta = |r0| from block partials of its square; g = beta
+// e_1; the first basis vector is r0 / beta.  first: beta0 = beta.
+__global__ void __launch_bounds__(256)
+gmres_start_kernel(GmresState* __restrict__ st, const double* __restrict__ partial, int nb, int first,
+                   double rtol) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v += partial[b];
+  v = block_sum(v, sh);
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(v);
+  if (first) {
+    st->beta0 = beta;
+    st->its = 0;
+  }
+  st->rtol = rtol;
+  for (int i = 0; i <= kMaxDots; ++i) st->g[i] = 0.0;
+  st->g[0] = beta;
+  st->cols = 0;
+  st->rel = st->beta0 > 0.0 ? beta / st->beta0 : 0.0;
+  const bool ok = beta > 0.0 && isfinite(beta);
+  st->done = ok ? 0 : 1;
+  st->converged = ok ? 0 : 1;
+  st->scale = ok ? 1.0 / beta : 0.0;
+}
+
+// Column j of the cycle from one Gram-Schmidt step's device sums
+// gs = [|w|^2 (FP64)][h1 (kMaxDots x S)][h2 (kMaxDots x S)]: h_ij = h1_i +
+// h2_i, h_{j+1,j} = |w|; the previous rotations, a new one, the rotated
+// right side and the stopping test.  One thread (m <= 30: a few hundred
+// flops); no-op once the cycle is done.
+template <typename S>
+__global__ void __launch_bounds__(64)
+gmres_column_kernel(GmresState* __restrict__ st, const double* __restrict__ gs, int j, int m) {
+  if (threadIdx.x != 0 || st->done) return;
+  const S* h1 = reinterpret_cast<const S*>(gs + 1);
+  const S* h2 = h1 + kMaxDots;
+  double* H = st->H;
+  for (int i = 0; i <= j; ++i) H[i * kMaxDots + j] = double(h1[i]) + double(h2[i]);
+  const double hn = sqrt(gs[0]);
+  H[(j + 1) * kMaxDots + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[i * kMaxDots + j], c = H[(i + 1) * kMaxDots + j];
+    H[i * kMaxDots + j] = st->cs[i] * a + st->sn[i] * c;
+    H[(i + 1) * kMaxDots + j] = -st->sn[i] * a + st->cs[i] * c;
+  }
+  const double a = H[j * kMaxDots + j], c = H[(j + 1) * kMaxDots + j];
+  const double rr = hypot(a, c);
+  st->cs[j] = rr > 0.0 ? a / rr : 1.0;
+  st->sn[j] = rr > 0.0 ? c / rr : 0.0;
+  H[j * kMaxDots + j] = rr;
+  H[(j + 1) * kMaxDots + j] = 0.0;
+  st->g[j + 1] = -st->sn[j] * st->g[j];
+  st->g[j] = st->cs[j] * st->g[j];
+  st->rel = fabs(st->g[j + 1]) / st->beta0;
+  st->cols = j + 1;
+  st->its += 1;
+  const bool conv = st->rel <= st->rtol;
+  if (conv || !(hn > 0.0) || j + 1 == m) {
+    st->done = 1;
+    st->converged = conv ? 1 : 0;
+  } else {
+    st->scale = 1.0 / hn;
+  }
+}
+
+// y = scale * x with the scale of the state (next basis vector); no-op once
+// the cycle is done (and in place for the first vector).
+template <typename S>
+__global__ void __launch_bounds__(256)
+gmres_scale_kernel(const GmresState* __restrict__ st, const S* __restrict__ x, S* __restrict__ y, int64_t n) {
+  if (st->done && x != y) return;
+  const S a = S(st->scale);
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    y[i] = a * x[i];
+}
+
+// Back substitution H y = g on the cycle's cols x cols upper triangle; y in
+// the state (FP64) and as S for the update x += V y.
+template <typename S>
+__global__ void __launch_bounds__(64)
+gmres_solve_kernel(GmresState* __restrict__ st, S* __restrict__ ys) {
+  if (threadIdx.x != 0) return;
+  const int k = st->cols;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = st->g[i];
+    for (int c = i + 1; c < k; ++c) s -= st->H[i * kMaxDots + c] * st->y[c];
+    st->y[i] = s / st->H[i * kMaxDots + i];
+  }
+  for (int i = 0; i < k; ++i) ys[i] = S(st->y[i]);
+}
+
 }  // namespace lsbdg

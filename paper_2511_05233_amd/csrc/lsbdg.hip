@@ -64,6 +64,9 @@ struct dg_ctx {
   int lin_prec = -1;
   int* d_status = nullptr;
   SolverWork work;
+  // GMRES cycle: pinned done flags of the last two iterations and their events
+  int32_t* gm_flags = nullptr;
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -302,9 +305,14 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
                   std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8),
                   std::make_pair(&W.pc, size_t(n7) * sS), std::make_pair(&W.pc2, size_t(n7) * sS),
                   std::make_pair(&W.scc, size_t(n7) * sS),
-                  std::make_pair(&W.gsum, size_t(8) + 2 * size_t(kMaxDots) * sS)}) {
+                  std::make_pair(&W.gsum, size_t(8) + 2 * size_t(kMaxDots) * sS),
+                  std::make_pair(&W.gstate, sizeof(GmresState))}) {
     hipError_t e = pr.first->ensure(pr.second);
     if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_step workspace: ") + hipGetErrorString(e));
+  }
+  if (!ctx->gm_flags) {
+    DG_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->gm_flags), 2 * sizeof(int32_t)));
+    for (hipEvent_t& ev : ctx->gm_ev) DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   }
   DevParams P = make_params(ctx, t_n + dt, dt);
   P.active = active;
@@ -330,7 +338,6 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   double* gs = W.gsum.as<double>();             // [|w|^2 (FP64)][h1 (kMaxDots x S)][h2 (kMaxDots x S)]
   S* gs_h1 = reinterpret_cast<S*>(gs + 1);
   S* gs_h2 = gs_h1 + kMaxDots;
-  std::vector<unsigned char> gs_host(sizeof(double) + 2 * kMaxDots * sizeof(S));
   const dim3 blk{256, 1, 1};
   // Reductions run on kRedBlocks workgroups, or on fewer for small meshes:
   // no more workgroups than a Krylov vector has quads of 4 entries per 256
@@ -609,7 +616,12 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     if (!std::isfinite(merit0)) return fail(DG_ENAN, "dg_step: non-finite residual");
     if (it == 1) r.merit0 = std::sqrt(merit0);
 
-    // GMRES(m) on sc^-1 M^-1 J sc y = b, x0 = 0
+    // GMRES(m) on sc^-1 M^-1 J sc y = b, x0 = 0, with the cycle's Hessenberg
+    // matrix, rotations and stopping test on the device (GmresState): an
+    // iteration issues its kernels without waiting for the previous one;
+    // the host reads the cycle's done flag one iteration late (pinned copy
+    // and event), so at most one iteration past convergence is issued, and
+    // its kernels change nothing.
     hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), b, S(0), x, n7);
     double beta0 = 0.0;
     if (int s = sumsq(b, n7, beta0)) return s;
@@ -622,90 +634,60 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     const int maxit = near_root ? std::min(o.gmres_maxit, std::max(200, 4 * prev_its)) : o.gmres_maxit;
     double rel = 0.0;
     if (beta0 > 0.0) {
-      std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), h;
+      GmresState* gst = W.gstate.as<GmresState>();
+      int32_t* hflag = ctx->gm_flags;
+      bool first = true;
       while (its < maxit) {
         S* V0 = V;
-        if (its == 0) {
+        if (first) {
           hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), b, S(0), V0, n7);
         } else {
           opA(x, w);
           hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), b, S(-1), w, n7);
           hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), w, S(0), V0, n7);
         }
-        double beta = 0.0;
-        if (int s = sumsq(V0, n7, beta)) return s;
-        beta = std::sqrt(beta);
-        if (!(beta > 0.0)) break;
-        hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1.0 / beta), V0, S(0), V0, n7);
-        std::fill(g.begin(), g.end(), 0.0);
-        std::fill(H.begin(), H.end(), 0.0);
-        g[0] = beta;
-        int j = 0;
-        bool done = false;
-        for (; j < m && its < maxit; ++j) {
-          S* Vj1 = V + int64_t(j + 1) * n7;
-          opA(V + int64_t(j) * n7, w);
+        hipLaunchKernelGGL(sumsq_kernel<S>, gred, blk, 0, st, V0, n7, partial64);
+        hipLaunchKernelGGL(gmres_start_kernel, g1, blk, 0, st, gst, partial64, nred, first ? 1 : 0, gm_rtol);
+        hipLaunchKernelGGL(gmres_scale_kernel<S>, grid1(n7), blk, 0, st, gst, V0, V0, n7);
+        first = false;
+        DG_HIP(hipMemcpyAsync(&hflag[0], &gst->done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        DG_HIP(hipStreamSynchronize(st));
+        if (hflag[0]) break;                       // zero residual: nothing to do
+        for (int jj = 0; jj < m && its + jj < maxit; ++jj) {
+          opA(V + int64_t(jj) * n7, w);
           // classical Gram-Schmidt applied twice: with FP32 basis vectors a
           // single pass (even with a reorthogonalisation test) loses enough
           // orthogonality to slow the two-level preconditioned iteration
           // (three sweeps over the basis: projections; first update fused
           // with the second projections; second update fused with |w|^2)
-          // (the three sums stay on the device, where the updates read
-          // them, and come back to the host in one copy)
-          const dim3 gj{unsigned(j + 1), 1, 1};
-          hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, V, n7, j + 1, w, n7, partial);
+          const dim3 gj{unsigned(jj + 1), 1, 1};
+          hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, V, n7, jj + 1, w, n7, partial);
           hipLaunchKernelGGL(finish_sum_kernel<S>, gj, blk, 0, st, partial, nred, gs_h1);
-          hipLaunchKernelGGL(multi_axpy_dot_kernel<S>, gred, blk, 0, st, V, n7, j + 1, gs_h1, w, n7, partial);
+          hipLaunchKernelGGL(multi_axpy_dot_kernel<S>, gred, blk, 0, st, V, n7, jj + 1, gs_h1, w, n7, partial);
           hipLaunchKernelGGL(finish_sum_kernel<S>, gj, blk, 0, st, partial, nred, gs_h2);
-          hipLaunchKernelGGL(multi_axpy_sumsq_kernel<S>, gred, blk, 0, st, V, n7, j + 1, gs_h2, w, n7, partial64);
+          hipLaunchKernelGGL(multi_axpy_sumsq_kernel<S>, gred, blk, 0, st, V, n7, jj + 1, gs_h2, w, n7, partial64);
           hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, nred, gs);
-          DG_HIP(hipMemcpyAsync(gs_host.data(), gs, gs_host.size(), hipMemcpyDeviceToHost, st));
-          DG_HIP(hipStreamSynchronize(st));
-          double hn = 0.0;
-          std::memcpy(&hn, gs_host.data(), sizeof(double));
-          {
-            S h1[kMaxDots], h2s[kMaxDots];
-            std::memcpy(h1, gs_host.data() + sizeof(double), kMaxDots * sizeof(S));
-            std::memcpy(h2s, gs_host.data() + sizeof(double) + kMaxDots * sizeof(S), kMaxDots * sizeof(S));
-            h.assign(j + 1, 0.0);
-            for (int i = 0; i <= j; ++i) h[i] = double(h1[i]) + double(h2s[i]);
+          hipLaunchKernelGGL(gmres_column_kernel<S>, g1, dim3(64), 0, st, gst, gs, jj, m);
+          hipLaunchKernelGGL(gmres_scale_kernel<S>, grid1(n7), blk, 0, st, gst, w, V + int64_t(jj + 1) * n7, n7);
+          DG_HIP(hipMemcpyAsync(&hflag[jj & 1], &gst->done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+          DG_HIP(hipEventRecord(ctx->gm_ev[jj & 1], st));
+          if (jj >= 1) {
+            DG_HIP(hipEventSynchronize(ctx->gm_ev[(jj - 1) & 1]));
+            if (hflag[(jj - 1) & 1]) break;
           }
-          hn = std::sqrt(hn);
-          ++its;
-          for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
-          H[(j + 1) * m + j] = hn;
-          for (int i = 0; i < j; ++i) {
-            const double a = H[i * m + j], c = H[(i + 1) * m + j];
-            H[i * m + j] = cs[i] * a + sn[i] * c;
-            H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-          }
-          const double a = H[j * m + j], c = H[(j + 1) * m + j];
-          const double rr = std::hypot(a, c);
-          cs[j] = rr > 0 ? a / rr : 1.0;
-          sn[j] = rr > 0 ? c / rr : 0.0;
-          H[j * m + j] = rr;
-          H[(j + 1) * m + j] = 0.0;
-          g[j + 1] = -sn[j] * g[j];
-          g[j] = cs[j] * g[j];
-          rel = std::fabs(g[j + 1]) / beta0;
-          if (rel <= gm_rtol || !(hn > 0.0)) {
-            done = true;
-            ++j;
-            break;
-          }
-          hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1.0 / hn), w, S(0), Vj1, n7);
         }
-        // x += V_j y, H y = g (upper triangular j x j)
-        std::vector<double> y(j);
-        for (int i = j - 1; i >= 0; --i) {
-          double s = g[i];
-          for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
-          y[i] = s / H[i * m + i];
-        }
-        std::vector<S> ys(y.begin(), y.end());
-        DG_HIP(hipMemcpyAsync(hbuf, ys.data(), j * sizeof(S), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, j, hbuf, S(1), x, n7);
-        if (done) break;
+        DG_HIP(hipGetLastError());
+        // x += V y with the cycle's least-squares solution
+        GmresState hs;
+        hipLaunchKernelGGL(gmres_solve_kernel<S>, g1, dim3(64), 0, st, gst, hbuf);
+        DG_HIP(hipMemcpyAsync(&hs.rel, &gst->rel, sizeof(double) + 4 * sizeof(int32_t) + sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        DG_HIP(hipStreamSynchronize(st));
+        if (hs.cols > 0)
+          hipLaunchKernelGGL(multi_axpy_kernel<S>, grid1(n7), blk, 0, st, V, n7, hs.cols, hbuf, S(1), x, n7);
+        its = hs.its;
+        rel = hs.rel;
+        if (hs.converged || hs.cols == 0) break;
       }
     }
     r.gmres_its += its;
@@ -1132,6 +1114,9 @@ int dg_destroy(dg_ctx* ctx) {
   for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->crc2, &ctx->cpart, &ctx->cipiv, &ctx->cinfo, &ctx->bh})
     b->release();
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
+  for (hipEvent_t ev : ctx->gm_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (ctx->gm_flags) (void)hipHostFree(ctx->gm_flags);
   delete ctx;
   return DG_OK;
 }

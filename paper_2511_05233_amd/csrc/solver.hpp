@@ -61,11 +61,12 @@ struct SolverWork {
   DevBuf gsum;                                     // one Gram-Schmidt step's sums: [|w|^2][h1][h2]
   DevBuf z0, zC, zF, out_partial;                  // time controller, outputs (FP64)
   DevBuf pc, pc2, scc;                             // two-level preconditioner temporaries, scales (S)
+  DevBuf gstate;                                   // GMRES cycle state on the device (GmresState)
   int m = 0;
   void release_all() {
     for (DevBuf* d : {&m_old, &R, &Rtry, &u_try, &du, &wR, &uS, &sc, &V, &w, &t, &pJ, &rhs, &b, &x,
                       &y9, &v9, &JZ, &partial, &partial64, &dots, &yc, &Ainv, &hbuf, &z0, &zC, &zF,
-                      &out_partial, &pc, &pc2, &scc, &gsum})
+                      &out_partial, &pc, &pc2, &scc, &gsum, &gstate})
       d->release();
   }
 };
