@@ -106,15 +106,19 @@ typedef struct {
 /* Fill *p with the paper's parameters (Tab. 5) and defaults. */
 void dg_params_default(dg_params* p);
 
-/* Create a context for one voxel structure.
- *   mesh   mesh and degree (the kernels are Q1: order 1)
+/* Create a context for one voxel structure; the library allocates its
+ * device memory as it is first needed (dg_setup_ws: in a caller-owned
+ * workspace instead).
+ *   mesh   mesh and degree: order 0 (the finite-volume scheme of Eq. 48:
+ *          operators, blocks and outputs) or 1 (Q1: every entry point)
  *   phase  HOST array of nx*ny*nz bytes, x fastest: 0 = pore voxel
  *          (electrolyte only, no reactions), 1 = cathode structure voxel
  *          (Eq. 57 localisation); copied, may be freed after the call
  *   params parameters (copied)
  *   out    receives the context
- * Errors: DG_EINVAL (null pointer, non-positive size, phase not 0/1),
- * DG_EUNSUPPORTED (order), DG_ENOMEM, DG_EHIP. */
+ * Errors: DG_EINVAL (null pointer, non-positive size, phase not 0/1,
+ * order not one of 0, 1, 3), DG_EUNSUPPORTED (order 3, not built),
+ * DG_ENOMEM, DG_EHIP. */
 int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params,
              dg_ctx** out);
 
@@ -240,6 +244,50 @@ typedef struct {
 } dg_solver_opts;
 
 void dg_solver_opts_default(dg_solver_opts* o);
+
+/* ---- Caller-owned device workspace ----
+ *
+ * A context set up with dg_setup_ws takes every device buffer it will use
+ * -- phase map, linearisation, element blocks, Krylov basis, Newton
+ * vectors, coarse space, controller states, output partial sums and the
+ * rocSOLVER scratch of the coarse LU -- from one caller-owned device
+ * workspace, carved at set-up; no later call allocates device memory, and
+ * dg_destroy frees only the host object.  What the workspace must hold
+ * depends on the uses it is sized for (features, a DG_WS_* mask) and on
+ * the solver options (inner precision, restart length, coarse space,
+ * bfloat16 inverses).  A call outside those uses (an FP64 block setup on a
+ * workspace sized for FP32 inner solves, a longer restart, the H211b
+ * controller without DG_WS_H211B) returns DG_ENOMEM, and dg_last_error()
+ * says how many bytes the workspace lacks.  The batch entry points
+ * (dg_batch_*) allocate their own storage. */
+typedef enum {
+  DG_WS_OPERATORS = 1,  /* dg_mass, dg_residual, dg_jvp, dg_linearize, dg_outputs */
+  DG_WS_BLOCKS = 2,     /* dg_blockjacobi_setup/apply/export in opts->inner_prec */
+  DG_WS_STEP = 4,       /* dg_step, dg_initial_state with opts */
+  DG_WS_NAIVE = 8,      /* dg_advance, naive controller (one saved state) */
+  DG_WS_H211B = 16,     /* dg_advance, H211b (three saved states) */
+  DG_WS_ALL = 31
+} dg_workspace_use;
+
+/* Bytes of device workspace a dg_setup_ws context of this mesh needs for
+ * the uses in `features` with solver options opts (NULL: defaults).  Host
+ * call (it queries rocSOLVER for the scratch of the coarse LU).  The
+ * slab of 96 x 96 x 192 voxels with FP32 inner solves, bfloat16 inverses
+ * and the naive controller needs about 60 GB.  Errors: DG_EINVAL (null
+ * pointer, mesh, unknown feature bits, bad options). */
+int dg_workspace_bytes(const dg_mesh* mesh, const dg_params* params, const dg_solver_opts* opts,
+                       int32_t features, size_t* bytes);
+
+/* As dg_setup (Sec. 2.2-2.6 problem, Tab. 5 parameters, Eq. 57 phases),
+ * with every device buffer of the context carved from `workspace`: device
+ * memory of ws_bytes bytes, 256-byte aligned, owned by the caller, which
+ * must outlive the context and is never freed by the library.  The phase
+ * map is copied on `stream` (synchronised before return).  opts and
+ * features as for dg_workspace_bytes; the same values must be passed here.
+ * Errors: as dg_setup; DG_EINVAL for a null or misaligned workspace;
+ * DG_ENOMEM when ws_bytes is too small (the message gives the shortfall). */
+int dg_setup_ws(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params, const dg_solver_opts* opts,
+                int32_t features, void* workspace, size_t ws_bytes, dg_stream stream, dg_ctx** out);
 
 typedef struct {
   int32_t newton_its, gmres_its, line_search_cuts, status;

@@ -25,6 +25,7 @@
 #include "model.hpp"
 #include "pointwise.hpp"
 #include "resid_q1.hpp"
+#include "resid_q0.hpp"
 #include "brick_q1.hpp"
 #include "blockjacobi.hpp"
 #include "solver.hpp"
@@ -48,9 +49,9 @@ struct dg_ctx {
   int64_t Ne = 0;
   int np = 1;
   uint8_t* d_phase = nullptr;
+  DevBuf phase;                     // device phase map (d_phase points into it)
   // element block-Jacobi storage (condensed 56 x 56 inverses, column-major)
-  void* d_blocks = nullptr;
-  size_t blocks_bytes = 0;
+  DevBuf blocks;
   int blocks_prec = -1;
   // linearisation coefficients of the condensed tangent (14 x nodes)
   DevBuf lin;
@@ -61,9 +62,19 @@ struct dg_ctx {
   DevBuf bh;
   bool bh_valid = false;
   rocblas_handle blas = nullptr;
+  DevBuf blasws;                    // rocBLAS/rocSOLVER scratch (workspace contexts)
   int lin_prec = -1;
-  int* d_status = nullptr;
+  DevBuf status;                    // singular-block flag of the block setup
   SolverWork work;
+  // caller-owned workspace (dg_setup_ws): every DevBuf above is carved from it
+  Arena arena;
+  bool owns_memory = true;
+  template <typename F>
+  void for_each_buf(F f) {
+    for (DevBuf* d : {&phase, &blocks, &lin, &cE, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
+      f(*d);
+    work.for_each(f);
+  }
   // GMRES cycle: pinned done flags of the last two iterations and their events
   int32_t* gm_flags = nullptr;
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
@@ -76,6 +87,16 @@ thread_local std::string g_last_error;
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
+}
+
+// Device memory for `what` (need bytes) was not available: from the
+// caller's workspace of a dg_setup_ws context (the message says how much
+// it lacks), or from hipMalloc.
+int fail_mem(const dg_ctx* ctx, const std::string& what, size_t need) {
+  if (!ctx->owns_memory)
+    return fail(DG_ENOMEM, what + ": the caller's workspace lacks " + std::to_string(ctx->arena.short_by) +
+                               " bytes (size it with dg_workspace_bytes for this use)");
+  return fail(DG_ENOMEM, what + ": device allocation of " + std::to_string(need) + " bytes failed");
 }
 
 #define DG_HIP(call)                                                              \
@@ -111,8 +132,12 @@ DevParams make_params(const dg_ctx* c, double t_eval, double dt) {
   const double h = c->mesh.h;
   P.sig_h = c->sigma / h;
   P.sq3_h = std::sqrt(3.0) / h;
-  P.W3 = (h / 2) * (h / 2) * (h / 2);
-  P.W2 = (h / 2) * (h / 2);
+  // nodal weights: (h/2)^3 w_a w_b w_c with the Gauss-Legendre weights of
+  // the order (1 for the two-point rule of Q1, 2 for the one-point rule of
+  // k = 0), and (h/2)^2 w w on faces
+  const double wgl = c->mesh.order == 0 ? 2.0 : 1.0;
+  P.W3 = (h / 2) * (h / 2) * (h / 2) * wgl * wgl * wgl;
+  P.W2 = (h / 2) * (h / 2) * wgl * wgl;
   P.jel = c->j_el;
   P.TH = p.use_TH ? 0.5 * (1.0 + std::tanh(6.0 * (t_eval - 1.0))) : 1.0;
   P.inv_dt = dt > 0 ? 1.0 / dt : 0.0;
@@ -127,12 +152,22 @@ DevParams make_params(const dg_ctx* c, double t_eval, double dt) {
   P.ny = c->mesh.ny;
   P.nz = c->mesh.nz;
   P.Ne = c->Ne;
+  P.np = c->np;
   P.active = kAllFields;
   return P;
 }
 
 int check_ctx(const dg_ctx* c) {
   if (!c) return fail(DG_EINVAL, "null context");
+  return DG_OK;
+}
+
+// Entry points built for Q1 only: at k = 0 the library provides the
+// operators (mass, residual, tangents, linearisation).
+int check_q1(const dg_ctx* c, const char* fn) {
+  if (c->mesh.order != 1)
+    return fail(DG_EUNSUPPORTED, std::string(fn) + ": order " + std::to_string(c->mesh.order) +
+                                     " provides the operators only (mass, residual, tangents, linearisation)");
   return DG_OK;
 }
 
@@ -178,6 +213,12 @@ namespace {
 template <typename S, typename N, int Mode>
 void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void* v, const void* m,
                void* out, hipStream_t st) {
+  if (ctx->np == 1) {                          // k = 0: one lane per voxel
+    const int64_t nb = std::min<int64_t>((ctx->Ne + 255) / 256, 16384);
+    hipLaunchKernelGGL((q0_kernel<S, N, Mode>), dim3(unsigned(nb)), dim3(256), 0, st, static_cast<const S*>(u),
+                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), ctx->d_phase, P);
+    return;
+  }
   const int64_t threads = ctx->Ne * 8;
   if constexpr (std::is_same<S, float>::value && Mode != kResidual) {
     // the FP32 tangent (two waves per SIMD) in workgroups of one wave, the
@@ -214,8 +255,8 @@ void launch_brick_jvp(const dg_ctx* ctx, const DevParams& P, const void* u, cons
 template <typename S>
 int linearize(dg_ctx* ctx, const DevParams& P, const S* u, hipStream_t st) {
   const int64_t FS = ctx->Ne * ctx->np;
-  hipError_t e = ctx->lin.ensure(size_t(14) * FS * sizeof(S));
-  if (e != hipSuccess) return fail(DG_ENOMEM, std::string("linearisation storage: ") + hipGetErrorString(e));
+  const size_t lin_bytes = size_t(14) * FS * sizeof(S);
+  if (ctx->lin.ensure(lin_bytes) != hipSuccess) return fail_mem(ctx, "linearisation storage", lin_bytes);
   int64_t nb = (FS + 255) / 256;
   if (nb > 8192) nb = 8192;
   hipLaunchKernelGGL(solid_tangent_kernel<S>, dim3(unsigned(nb)), dim3(256), 0, st, u, ctx->lin.as<S>(),
@@ -237,41 +278,31 @@ namespace {
 template <typename S>
 int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st, bool bf16_only = false) {
   const size_t need = size_t(ctx->Ne) * 56 * 56 * sizeof(S);
-  if (ctx->blocks_bytes < need) {
-    if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
-    ctx->d_blocks = nullptr;
-    ctx->blocks_bytes = 0;
-    hipError_t err = hipMalloc(&ctx->d_blocks, need);
-    if (err != hipSuccess)
-      return fail(DG_ENOMEM, std::string("block storage: ") + hipGetErrorString(err));
-    ctx->blocks_bytes = need;
-  }
-  if (!ctx->d_status) {
-    hipError_t err = hipMalloc(&ctx->d_status, sizeof(int));
-    if (err != hipSuccess) return fail(DG_ENOMEM, "status allocation");
-  }
-  DG_HIP(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+  if (ctx->blocks.ensure(need) != hipSuccess) return fail_mem(ctx, "block storage", need);
+  if (ctx->status.ensure(sizeof(int)) != hipSuccess) return fail_mem(ctx, "status flag", sizeof(int));
+  int* d_status = ctx->status.as<int>();
+  DG_HIP(hipMemsetAsync(d_status, 0, sizeof(int), st));
   int64_t nb = (ctx->Ne * 8 + 255) / 256;
   nb = (nb + 7) / 8 * 8;
   const dim3 grid{unsigned(nb), 1, 1}, block{256, 1, 1};
   const dim3 grid_w{unsigned((ctx->Ne + 3) / 4), 1, 1};
   hipLaunchKernelGGL((q1_block_kernel<S, kJvpCondensed>), grid, block, 0, st, uS, ctx->lin.as<S>(),
-                     static_cast<S*>(ctx->d_blocks), ctx->d_phase, P, nb);
+                     ctx->blocks.as<S>(), ctx->d_phase, P, nb);
   ctx->bh_valid = false;
   if constexpr (std::is_same<S, float>::value) {
     if (bf16_only) {
-      hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * 56 * 56 * 2);
-      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("bf16 blocks: ") + hipGetErrorString(e));
+      if (ctx->bh.ensure(size_t(ctx->Ne) * 56 * 56 * 2) != hipSuccess)
+        return fail_mem(ctx, "bf16 blocks", size_t(ctx->Ne) * 56 * 56 * 2);
       hipLaunchKernelGGL((invert_blocks_kernel<float, 56, true>), grid_w, block, 0, st,
-                         static_cast<float*>(ctx->d_blocks), ctx->Ne, ctx->d_status, ctx->bh.as<uint16_t>());
+                         ctx->blocks.as<float>(), ctx->Ne, ctx->status.as<int>(), ctx->bh.as<uint16_t>());
     }
   }
   if (!bf16_only)
-    hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), grid_w, block, 0, st, static_cast<S*>(ctx->d_blocks),
-                       ctx->Ne, ctx->d_status, nullptr);
+    hipLaunchKernelGGL((invert_blocks_kernel<S, 56>), grid_w, block, 0, st, ctx->blocks.as<S>(),
+                       ctx->Ne, ctx->status.as<int>(), nullptr);
   DG_HIP(hipGetLastError());
   int h_status = 0;
-  DG_HIP(hipMemcpyAsync(&h_status, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipMemcpyAsync(&h_status, ctx->status.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
   DG_HIP(hipStreamSynchronize(st));
   if (bf16_only) {
     ctx->blocks_prec = -1;                     // FP32 storage holds no inverses
@@ -283,6 +314,122 @@ int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st, b
   return DG_OK;
 }
 
+// Pinned done flags and events of the GMRES cycle (made once per context).
+int gmres_host_state(dg_ctx* ctx) {
+  if (ctx->gm_flags) return DG_OK;
+  DG_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->gm_flags), 2 * sizeof(int32_t)));
+  for (hipEvent_t& ev : ctx->gm_ev) DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  return DG_OK;
+}
+
+// Device buffers of the Newton-GMRES step solve with inner precision of
+// sS bytes, with their sizes (the solve ensures exactly these).
+std::vector<std::pair<DevBuf*, size_t>> solver_buffers(dg_ctx* ctx, const dg_solver_opts& o, size_t sS) {
+  const int64_t FS = ctx->Ne * ctx->np, n7 = 7 * FS, n9 = 9 * FS;
+  const int m = o.gmres_restart;
+  SolverWork& W = ctx->work;
+  const bool global_coarse = o.coarse == 1 || o.coarse == 2;
+  return {std::make_pair(&W.m_old, size_t(8 * FS) * 8), std::make_pair(&W.R, size_t(n9) * 8),
+          std::make_pair(&W.Rtry, size_t(n9) * 8), std::make_pair(&W.u_try, size_t(n9) * 8),
+          std::make_pair(&W.du, size_t(n9) * 8), std::make_pair(&W.wR, size_t(2 * FS) * 8),
+          std::make_pair(&W.uS, size_t(n9) * sS), std::make_pair(&W.sc, size_t(n7) * sS),
+          std::make_pair(&W.V, size_t(m + 1) * n7 * sS), std::make_pair(&W.w, size_t(n7) * sS),
+          std::make_pair(&W.t, size_t(n7) * sS), std::make_pair(&W.pJ, size_t(n7) * sS),
+          std::make_pair(&W.rhs, size_t(n7) * sS), std::make_pair(&W.b, size_t(n7) * sS),
+          std::make_pair(&W.x, size_t(n7) * sS), std::make_pair(&W.y9, size_t(n9) * sS),
+          std::make_pair(&W.v9, size_t(n9) * sS),
+          std::make_pair(&W.JZ, global_coarse ? size_t(7) * n7 * sS : size_t(0)),
+          std::make_pair(&W.partial, size_t(kMaxDots) * kRedBlocks * sS),
+          std::make_pair(&W.partial64, size_t(kRedBlocks) * 8),
+          std::make_pair(&W.dots, size_t(kMaxDots) * 8), std::make_pair(&W.yc, size_t(8) * 8),
+          std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8),
+          std::make_pair(&W.pc, size_t(n7) * sS), std::make_pair(&W.pc2, size_t(n7) * sS),
+          std::make_pair(&W.scc, size_t(n7) * sS),
+          std::make_pair(&W.gsum, size_t(8) + 2 * size_t(kMaxDots) * sS),
+          std::make_pair(&W.gstate, sizeof(GmresState))};
+}
+
+// Aggregates of the two-level coarse space: opts.coarse_agg voxels per
+// edge, or the smallest edge >= 4 with at most 8192 coarse unknowns.
+AggGrid coarse_grid(const dg_mesh& mesh, const dg_solver_opts& o) {
+  AggGrid G{};
+  const int nx = mesh.nx, ny = mesh.ny, nz = mesh.nz;
+  auto naggs = [&](int a) { return int64_t((nx + a - 1) / a) * ((ny + a - 1) / a) * ((nz + a - 1) / a); };
+  int A = o.coarse_agg;
+  if (A <= 0) {
+    A = 4;
+    while (7 * naggs(A) > 8192) ++A;
+  }
+  G.nx = nx; G.ny = ny; G.nz = nz; G.A = A;
+  G.nax = (nx + A - 1) / A; G.nay = (ny + A - 1) / A; G.naz = (nz + A - 1) / A;
+  G.na = naggs(A);
+  return G;
+}
+
+std::vector<std::pair<DevBuf*, size_t>> coarse_buffers(dg_ctx* ctx, int64_t nc) {
+  return {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cd, size_t(nc) * 8),
+          std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->crc2, size_t(nc) * 8),
+          std::make_pair(&ctx->cpart, size_t(kCoarseChunks) * nc * 8),
+          std::make_pair(&ctx->cipiv, size_t(nc) * 4), std::make_pair(&ctx->cinfo, size_t(4))};
+}
+
+// Device scratch rocSOLVER needs for the LU and the inverse of an nc x nc
+// FP64 matrix (a size query: nothing runs).  false if the query failed.
+bool rocsolver_scratch_bytes(rocblas_handle h, int64_t nc, size_t& bytes) {
+  double dummy_d = 0.0;
+  rocblas_int dummy_i = 0;
+  double* A = &dummy_d;                 // not dereferenced in a size query
+  rocblas_int* ip = &dummy_i;
+  bytes = 0;
+  if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) return false;
+  (void)rocsolver_dgetrf(h, rocblas_int(nc), rocblas_int(nc), A, rocblas_int(nc), ip, ip);
+  (void)rocsolver_dgetri(h, rocblas_int(nc), A, rocblas_int(nc), ip, ip);
+  return rocblas_stop_device_memory_size_query(h, &bytes) == rocblas_status_success;
+}
+
+// Hands the handle a scratch of `bytes` from buffer b (carved from the
+// context's workspace): rocBLAS then allocates nothing itself.
+int give_blas_scratch(dg_ctx* ctx, size_t bytes) {
+  if (ctx->blasws.ensure(bytes > 0 ? bytes : 1) != hipSuccess) return fail_mem(ctx, "rocSOLVER scratch", bytes);
+  if (rocblas_set_workspace(ctx->blas, ctx->blasws.p, bytes) != rocblas_status_success)
+    return fail(DG_EHIP, "rocblas_set_workspace failed");
+  return DG_OK;
+}
+
+// Every device buffer a context needs for the uses in `features` (a
+// DG_WS_* mask) with solver options o, in carve order.  *rocsolver: the
+// LU scratch in bytes (0 without the aggregation coarse space).
+std::vector<std::pair<DevBuf*, size_t>> plan_workspace(dg_ctx* ctx, const dg_solver_opts& o, int features,
+                                                       bool& need_rocsolver, int64_t& nc) {
+  const int64_t FS = ctx->Ne * ctx->np;
+  const size_t sS = o.inner_prec == DG_F32 ? 4 : 8;
+  std::vector<std::pair<DevBuf*, size_t>> out = {
+      std::make_pair(&ctx->phase, size_t(ctx->Ne)), std::make_pair(&ctx->status, sizeof(int)),
+      std::make_pair(&ctx->lin, size_t(14) * FS * 8),
+      std::make_pair(&ctx->work.out_partial, size_t(kNumSums) * kOutBlocks * 8)};
+  const bool step = features & (DG_WS_STEP | DG_WS_NAIVE | DG_WS_H211B);
+  if (step || (features & DG_WS_BLOCKS)) {
+    out.push_back(std::make_pair(&ctx->blocks, size_t(ctx->Ne) * 56 * 56 * sS));
+    if (sS == 4 && o.block_bf16) out.push_back(std::make_pair(&ctx->bh, size_t(ctx->Ne) * 56 * 56 * 2));
+  }
+  need_rocsolver = false;
+  nc = 0;
+  if (step) {
+    for (const auto& pr : solver_buffers(ctx, o, sS)) out.push_back(pr);
+    if (o.coarse == 3 || o.coarse == 4) {
+      nc = 7 * coarse_grid(ctx->mesh, o).na;
+      for (const auto& pr : coarse_buffers(ctx, nc)) out.push_back(pr);
+      need_rocsolver = true;
+    }
+  }
+  if (features & (DG_WS_NAIVE | DG_WS_H211B)) out.push_back(std::make_pair(&ctx->work.z0, size_t(9) * FS * 8));
+  if (features & DG_WS_H211B) {
+    out.push_back(std::make_pair(&ctx->work.zC, size_t(9) * FS * 8));
+    out.push_back(std::make_pair(&ctx->work.zF, size_t(9) * FS * 8));
+  }
+  return out;
+}
+
 template <typename S>
 int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_opts& o,
                  dg_step_report* rep, hipStream_t st, int active = kAllFields) {
@@ -290,30 +437,9 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   const int m = o.gmres_restart;
   SolverWork& W = ctx->work;
   const size_t sS = sizeof(S);
-  for (auto pr : {std::make_pair(&W.m_old, size_t(8 * FS) * 8), std::make_pair(&W.R, size_t(n9) * 8),
-                  std::make_pair(&W.Rtry, size_t(n9) * 8), std::make_pair(&W.u_try, size_t(n9) * 8),
-                  std::make_pair(&W.du, size_t(n9) * 8), std::make_pair(&W.wR, size_t(2 * FS) * 8),
-                  std::make_pair(&W.uS, size_t(n9) * sS), std::make_pair(&W.sc, size_t(n7) * sS),
-                  std::make_pair(&W.V, size_t(m + 1) * n7 * sS), std::make_pair(&W.w, size_t(n7) * sS),
-                  std::make_pair(&W.t, size_t(n7) * sS), std::make_pair(&W.pJ, size_t(n7) * sS),
-                  std::make_pair(&W.rhs, size_t(n7) * sS), std::make_pair(&W.b, size_t(n7) * sS),
-                  std::make_pair(&W.x, size_t(n7) * sS), std::make_pair(&W.y9, size_t(n9) * sS),
-                  std::make_pair(&W.v9, size_t(n9) * sS), std::make_pair(&W.JZ, size_t(7) * n7 * sS),
-                  std::make_pair(&W.partial, size_t(kMaxDots) * kRedBlocks * sS),
-                  std::make_pair(&W.partial64, size_t(kRedBlocks) * 8),
-                  std::make_pair(&W.dots, size_t(kMaxDots) * 8), std::make_pair(&W.yc, size_t(8) * 8),
-                  std::make_pair(&W.Ainv, size_t(49) * 8), std::make_pair(&W.hbuf, size_t(kMaxDots) * 8),
-                  std::make_pair(&W.pc, size_t(n7) * sS), std::make_pair(&W.pc2, size_t(n7) * sS),
-                  std::make_pair(&W.scc, size_t(n7) * sS),
-                  std::make_pair(&W.gsum, size_t(8) + 2 * size_t(kMaxDots) * sS),
-                  std::make_pair(&W.gstate, sizeof(GmresState))}) {
-    hipError_t e = pr.first->ensure(pr.second);
-    if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_step workspace: ") + hipGetErrorString(e));
-  }
-  if (!ctx->gm_flags) {
-    DG_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->gm_flags), 2 * sizeof(int32_t)));
-    for (hipEvent_t& ev : ctx->gm_ev) DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  }
+  for (const auto& pr : solver_buffers(ctx, o, sS))
+    if (pr.first->ensure(pr.second) != hipSuccess) return fail_mem(ctx, "dg_step workspace", pr.second);
+  if (int s = gmres_host_state(ctx)) return s;
   DevParams P = make_params(ctx, t_n + dt, dt);
   P.active = active;
   const double phi_floor = kGas * ctx->params.T / kFaraday;
@@ -353,31 +479,21 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   int64_t nc = 0;
   const bool agg = (o.coarse == 3 || o.coarse == 4);
   if (agg) {
-    const int nx = ctx->mesh.nx, ny = ctx->mesh.ny, nz = ctx->mesh.nz;
-    int A = o.coarse_agg;
-    auto naggs = [&](int a) {
-      return int64_t((nx + a - 1) / a) * ((ny + a - 1) / a) * ((nz + a - 1) / a);
-    };
-    if (A <= 0) {
-      A = 4;
-      while (7 * naggs(A) > 8192) ++A;
-    }
-    G.nx = nx; G.ny = ny; G.nz = nz; G.A = A;
-    G.nax = (nx + A - 1) / A; G.nay = (ny + A - 1) / A; G.naz = (nz + A - 1) / A;
-    G.na = naggs(A);
+    G = coarse_grid(ctx->mesh, o);
     nc = 7 * G.na;
     if (nc > (int64_t(1) << 20)) return fail(DG_EINVAL, "dg_step: coarse space too large (raise coarse_agg)");
-    for (auto pr : {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cd, size_t(nc) * 8),
-                    std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->crc2, size_t(nc) * 8),
-                    std::make_pair(&ctx->cpart, size_t(kCoarseChunks) * nc * 8),
-                    std::make_pair(&ctx->cipiv, size_t(nc) * 4),
-                    std::make_pair(&ctx->cinfo, size_t(4))}) {
-      hipError_t e = pr.first->ensure(pr.second);
-      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("coarse space: ") + hipGetErrorString(e));
-    }
+    for (const auto& pr : coarse_buffers(ctx, nc))
+      if (pr.first->ensure(pr.second) != hipSuccess) return fail_mem(ctx, "coarse space", pr.second);
     if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success)
       return fail(DG_EHIP, "rocblas_create_handle failed");
     if (rocblas_set_stream(ctx->blas, st) != rocblas_status_success) return fail(DG_EHIP, "rocblas_set_stream failed");
+    if (!ctx->owns_memory && ctx->blasws.bytes == 0) {
+      // the LU's scratch from the caller's workspace too
+      size_t need = 0;
+      if (!rocsolver_scratch_bytes(ctx->blas, nc, need))
+        return fail(DG_EHIP, "dg_step: rocSOLVER scratch size query failed");
+      if (int s = give_blas_scratch(ctx, need)) return s;
+    }
   }
   double* cE = ctx->cE.as<double>();
   double* cd = ctx->cd.as<double>();
@@ -429,10 +545,10 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
           hipLaunchKernelGGL((apply_blocks_bf16_kernel<7>), gw, blk, 0, st, ctx->bh.as<const uint16_t>(), pc2,
                              out, ctx->Ne);
         else
-          hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks),
+          hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, ctx->blocks.as<const S>(),
                              pc2, out, ctx->Ne);
       } else {
-        hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), pc2,
+        hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, ctx->blocks.as<const S>(), pc2,
                            out, ctx->Ne);
       }
       hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), pc, S(1), out, n7);
@@ -444,10 +560,10 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
         hipLaunchKernelGGL((apply_blocks_bf16_kernel<7>), gw, blk, 0, st, ctx->bh.as<const uint16_t>(), r, out,
                            ctx->Ne);
       else
-        hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), r,
+        hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, ctx->blocks.as<const S>(), r,
                            out, ctx->Ne);
     } else {
-      hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, static_cast<const S*>(ctx->d_blocks), r,
+      hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, ctx->blocks.as<const S>(), r,
                          out, ctx->Ne);
     }
     if (o.coarse == 1) {
@@ -1032,66 +1148,87 @@ void dg_params_default(dg_params* p) {
   p->use_TH = 1;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checked host side of a context: mesh, phase map and parameters, and what
+// derives from them (Tab. InitialState, Eq. 57 localisation, App. C
+// current).  No device work.
+int make_context(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params, const char* fn,
+                 dg_ctx** out) {
+  if (!mesh || !phase || !params || !out) return fail(DG_EINVAL, std::string(fn) + ": null argument");
+  *out = nullptr;
+  if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0 || !(mesh->h > 0))
+    return fail(DG_EINVAL, std::string(fn) + ": mesh sizes and h must be positive");
+  if (mesh->order != 0 && mesh->order != 1 && mesh->order != 3)
+    return fail(DG_EINVAL, std::string(fn) + ": order " + std::to_string(mesh->order) + " is not one of 0, 1, 3");
+  if (mesh->order == 3)
+    return fail(DG_EUNSUPPORTED, std::string(fn) + ": order 3 is not implemented (supported: 0, 1)");
+  if (!(params->T > 0)) return fail(DG_EINVAL, std::string(fn) + ": temperature must be positive");
+  const int64_t Ne = int64_t(mesh->nx) * mesh->ny * mesh->nz;
+  int64_t n_struct = 0;
+  for (int64_t e = 0; e < Ne; ++e) {
+    if (phase[e] > 1) return fail(DG_EINVAL, std::string(fn) + ": phase values must be 0 or 1");
+    n_struct += phase[e];
+  }
+  dg_ctx* c = new dg_ctx;
+  c->mesh = *mesh;
+  c->params = *params;
+  c->Ne = Ne;
+  const int K = mesh->order + 1;
+  c->np = K * K * K;
+  c->eq = equilibrium(params->T);
+  const double pore_frac = 1.0 - double(n_struct) / double(Ne);
+  c->eps_struct = params->eps_struct > 0 ? params->eps_struct : 1.0 - pore_frac;
+  c->sigma = params->sigma > 0 ? params->sigma : (mesh->order == 0 ? 1.0 : double(K * K));
+  const double inv = c->eps_struct > 0 ? 1.0 / c->eps_struct : 0.0;
+  PhaseTable& t = c->phase_tab;
+  std::memset(&t, 0, sizeof(t));
+  t.epsCBD[1] = (kXcathode - kXsulfur) * inv;
+  t.aV0[1] = kAV0 * inv;
+  t.epsS8init[1] = kEpsS8init * inv;
+  t.epsLi2Sinit[1] = kEpsLi2Sinit * inv;
+  t.s8ref[1] = 1.2 * t.epsS8init[1];
+  t.pass[1] = kPassA * std::exp(-kPassBh * params->f_C) * inv;
+  t.react[1] = 1.0;
+  if (params->j_el >= 0) {
+    c->j_el = params->j_el;
+  } else {
+    // App. C: j_el = f_C c_theo m_A, c_theo = 16 F / M_S8, m_A = rho_S8 *
+    // (initial S8 volume) / (separator area)
+    const double h = mesh->h;
+    const double vol = double(n_struct) * t.epsS8init[1] * h * h * h;
+    const double area = double(mesh->ny) * mesh->nz * h * h;
+    const double c_theo = 16.0 * kFaraday / kMolar[0];
+    c->j_el = params->f_C / 3600.0 * c_theo * kRho[0] * vol / area;
+  }
+  *out = c;
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params, dg_ctx** out) {
   try {
-    if (!mesh || !phase || !params || !out) return fail(DG_EINVAL, "dg_setup: null argument");
-    *out = nullptr;
-    if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0 || !(mesh->h > 0))
-      return fail(DG_EINVAL, "dg_setup: mesh sizes and h must be positive");
-    if (mesh->order != 1)
-      return fail(DG_EUNSUPPORTED, "dg_setup: order " + std::to_string(mesh->order) +
-                                       " not implemented (supported: 1)");
-    if (!(params->T > 0)) return fail(DG_EINVAL, "dg_setup: temperature must be positive");
-    const int64_t Ne = int64_t(mesh->nx) * mesh->ny * mesh->nz;
-    int64_t n_struct = 0;
-    for (int64_t e = 0; e < Ne; ++e) {
-      if (phase[e] > 1) return fail(DG_EINVAL, "dg_setup: phase values must be 0 or 1");
-      n_struct += phase[e];
-    }
-    dg_ctx* c = new dg_ctx;
-    c->mesh = *mesh;
-    c->params = *params;
-    c->Ne = Ne;
-    const int K = mesh->order + 1;
-    c->np = K * K * K;
-    c->eq = equilibrium(params->T);
-    const double pore_frac = 1.0 - double(n_struct) / double(Ne);
-    c->eps_struct = params->eps_struct > 0 ? params->eps_struct : 1.0 - pore_frac;
-    c->sigma = params->sigma > 0 ? params->sigma : (mesh->order == 0 ? 1.0 : double(K * K));
-    const double inv = c->eps_struct > 0 ? 1.0 / c->eps_struct : 0.0;
-    PhaseTable& t = c->phase_tab;
-    std::memset(&t, 0, sizeof(t));
-    t.epsCBD[1] = (kXcathode - kXsulfur) * inv;
-    t.aV0[1] = kAV0 * inv;
-    t.epsS8init[1] = kEpsS8init * inv;
-    t.epsLi2Sinit[1] = kEpsLi2Sinit * inv;
-    t.s8ref[1] = 1.2 * t.epsS8init[1];
-    t.pass[1] = kPassA * std::exp(-kPassBh * params->f_C) * inv;
-    t.react[1] = 1.0;
-    if (params->j_el >= 0) {
-      c->j_el = params->j_el;
-    } else {
-      // App. C: j_el = f_C c_theo m_A, c_theo = 16 F / M_S8, m_A = rho_S8 *
-      // (initial S8 volume) / (separator area)
-      const double h = mesh->h;
-      const double vol = double(n_struct) * t.epsS8init[1] * h * h * h;
-      const double area = double(mesh->ny) * mesh->nz * h * h;
-      const double c_theo = 16.0 * kFaraday / kMolar[0];
-      c->j_el = params->f_C / 3600.0 * c_theo * kRho[0] * vol / area;
-    }
+    dg_ctx* c = nullptr;
+    if (int s = make_context(mesh, phase, params, "dg_setup", &c)) return s;
     double* scr = nullptr;
     if (int s = device_scratch(&scr)) {
       delete c;
       return s;
     }
-    hipError_t err = hipMalloc(&c->d_phase, size_t(Ne));
+    hipError_t err = c->phase.ensure(size_t(c->Ne));
     if (err != hipSuccess) {
       delete c;
       return fail(DG_ENOMEM, std::string("dg_setup: hipMalloc: ") + hipGetErrorString(err));
     }
-    err = hipMemcpy(c->d_phase, phase, size_t(Ne), hipMemcpyHostToDevice);
+    c->d_phase = c->phase.as<uint8_t>();
+    err = hipMemcpy(c->d_phase, phase, size_t(c->Ne), hipMemcpyHostToDevice);
     if (err != hipSuccess) {
-      (void)hipFree(c->d_phase);
+      c->phase.release();
       delete c;
       return fail(DG_EHIP, std::string("dg_setup: hipMemcpy: ") + hipGetErrorString(err));
     }
@@ -1104,15 +1241,126 @@ int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params,
   }
 }
 
+int dg_workspace_bytes(const dg_mesh* mesh, const dg_params* params, const dg_solver_opts* opts, int32_t features,
+                       size_t* bytes) {
+  try {
+    if (!mesh || !params || !bytes) return fail(DG_EINVAL, "dg_workspace_bytes: null argument");
+    if (features & ~int32_t(DG_WS_ALL)) return fail(DG_EINVAL, "dg_workspace_bytes: unknown feature bits");
+    *bytes = 0;
+    dg_solver_opts o;
+    if (int s = normalize_opts(opts, o, "dg_workspace_bytes")) return s;
+    // a host-only context of the mesh (an all-structure map: the sizes do
+    // not depend on the phases)
+    const int64_t Ne = int64_t(mesh->nx) * mesh->ny * mesh->nz;
+    if (mesh->nx <= 0 || mesh->ny <= 0 || mesh->nz <= 0) return fail(DG_EINVAL, "dg_workspace_bytes: mesh sizes");
+    std::vector<uint8_t> ones(size_t(Ne), 1);
+    dg_ctx* c = nullptr;
+    if (int s = make_context(mesh, ones.data(), params, "dg_workspace_bytes", &c)) return s;
+    if (c->mesh.order != 1 && (features & ~int32_t(DG_WS_OPERATORS))) {
+      delete c;
+      return fail(DG_EUNSUPPORTED, "dg_workspace_bytes: order 0 provides the operators only (DG_WS_OPERATORS)");
+    }
+    bool need_rs = false;
+    int64_t nc = 0;
+    size_t total = 0;
+    for (const auto& pr : plan_workspace(c, o, features, need_rs, nc)) total = Arena::aligned(total) + pr.second;
+    delete c;
+    if (need_rs) {
+      rocblas_handle h = nullptr;
+      if (rocblas_create_handle(&h) != rocblas_status_success)
+        return fail(DG_EHIP, "dg_workspace_bytes: rocblas_create_handle failed");
+      size_t rs = 0;
+      const bool ok = rocsolver_scratch_bytes(h, nc, rs);
+      (void)rocblas_destroy_handle(h);
+      if (!ok) return fail(DG_EHIP, "dg_workspace_bytes: rocSOLVER scratch size query failed");
+      total = Arena::aligned(total) + (rs > 0 ? rs : 1);
+    }
+    *bytes = Arena::aligned(total);
+    return DG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_workspace_bytes: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_workspace_bytes: unexpected exception");
+  }
+}
+
+int dg_setup_ws(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params, const dg_solver_opts* opts,
+                int32_t features, void* workspace, size_t ws_bytes, dg_stream stream, dg_ctx** out) {
+  try {
+    if (!workspace) return fail(DG_EINVAL, "dg_setup_ws: null workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(DG_EINVAL, "dg_setup_ws: the workspace must be 256-byte aligned");
+    if (features & ~int32_t(DG_WS_ALL)) return fail(DG_EINVAL, "dg_setup_ws: unknown feature bits");
+    dg_solver_opts o;
+    if (int s = normalize_opts(opts, o, "dg_setup_ws")) return s;
+    dg_ctx* c = nullptr;
+    if (int s = make_context(mesh, phase, params, "dg_setup_ws", &c)) return s;
+    if (c->mesh.order != 1 && (features & ~int32_t(DG_WS_OPERATORS))) {
+      delete c;
+      return fail(DG_EUNSUPPORTED, "dg_setup_ws: order 0 provides the operators only (DG_WS_OPERATORS)");
+    }
+    double* scr = nullptr;
+    if (int s = device_scratch(&scr)) {
+      delete c;
+      return s;
+    }
+    c->owns_memory = false;
+    c->arena.base = static_cast<unsigned char*>(workspace);
+    c->arena.size = ws_bytes;
+    c->for_each_buf([c](DevBuf& b) { b.arena = &c->arena; });
+    bool need_rs = false;
+    int64_t nc = 0;
+    for (const auto& pr : plan_workspace(c, o, features, need_rs, nc)) {
+      if (pr.first->ensure(pr.second) != hipSuccess) {
+        const int s = fail_mem(c, "dg_setup_ws", pr.second);
+        delete c;
+        return s;
+      }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (need_rs) {
+      if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        delete c;
+        return fail(DG_EHIP, "dg_setup_ws: rocblas_create_handle failed");
+      }
+      size_t rs = 0;
+      int s = rocsolver_scratch_bytes(c->blas, nc, rs) ? give_blas_scratch(c, rs)
+                                                       : fail(DG_EHIP, "dg_setup_ws: rocSOLVER scratch size query failed");
+      if (s) {
+        (void)rocblas_destroy_handle(c->blas);
+        delete c;
+        return s;
+      }
+    }
+    if (features & (DG_WS_STEP | DG_WS_NAIVE | DG_WS_H211B)) {
+      if (int s = gmres_host_state(c)) {
+        if (c->blas) (void)rocblas_destroy_handle(c->blas);
+        delete c;
+        return s;
+      }
+    }
+    c->d_phase = c->phase.as<uint8_t>();
+    hipError_t err = hipMemcpyAsync(c->d_phase, phase, size_t(c->Ne), hipMemcpyHostToDevice, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);    // the host phase map may go after return
+    if (err != hipSuccess) {
+      if (c->blas) (void)rocblas_destroy_handle(c->blas);
+      delete c;
+      return fail(DG_EHIP, std::string("dg_setup_ws: hipMemcpyAsync: ") + hipGetErrorString(err));
+    }
+    *out = c;
+    return DG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ENOMEM, "dg_setup_ws: host allocation failed");
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_setup_ws: unexpected exception");
+  }
+}
+
 int dg_destroy(dg_ctx* ctx) {
   if (!ctx) return DG_OK;
-  if (ctx->d_phase) (void)hipFree(ctx->d_phase);
-  if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
-  if (ctx->d_status) (void)hipFree(ctx->d_status);
-  ctx->work.release_all();
-  ctx->lin.release();
-  for (DevBuf* b : {&ctx->cE, &ctx->cd, &ctx->crc, &ctx->crc2, &ctx->cpart, &ctx->cipiv, &ctx->cinfo, &ctx->bh})
-    b->release();
+  // buffers carved from a caller's workspace are the caller's: release()
+  // only forgets them
+  ctx->for_each_buf([](DevBuf& b) { b.release(); });
   if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
   for (hipEvent_t ev : ctx->gm_ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -1192,10 +1440,16 @@ int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const voi
     } else if (ctx->lin_prec != int(prec)) {
       return fail(DG_ESTATE, "dg_jvp: no linearisation of this precision (dg_linearize)");
     }
-    if (prec == DG_F64)
+    if (ctx->np == 1) {
+      if (prec == DG_F64)
+        launch_q1<double, Dual<double>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
+      else
+        launch_q1<float, Dual<float>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
+    } else if (prec == DG_F64) {
       launch_brick_jvp<double>(ctx, P, u, v, ctx->lin.p, jv, st);
-    else
+    } else {
       launch_brick_jvp<float>(ctx, P, u, v, ctx->lin.p, jv, st);
+    }
   } else {
     return fail(DG_EINVAL, "dg_jvp: bad mode");
   }
@@ -1220,27 +1474,16 @@ constexpr int kNB = 56;   // condensed Q1 block size: 7 fields x 8 nodes
 int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt,
                          dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
+  if (int s = check_q1(ctx, "dg_blockjacobi_setup")) return s;
   if (!u) return fail(DG_EINVAL, "dg_blockjacobi_setup: null array");
   if (!(dt > 0)) return fail(DG_EINVAL, "dg_blockjacobi_setup: dt must be positive");
   if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_blockjacobi_setup: bad precision");
   const size_t esz = prec == DG_F64 ? sizeof(double) : sizeof(float);
   const size_t need = size_t(ctx->Ne) * kNB * kNB * esz;
-  if (ctx->blocks_bytes < need) {
-    if (ctx->d_blocks) (void)hipFree(ctx->d_blocks);
-    ctx->d_blocks = nullptr;
-    ctx->blocks_bytes = 0;
-    hipError_t err = hipMalloc(&ctx->d_blocks, need);
-    if (err != hipSuccess)
-      return fail(DG_ENOMEM, std::string("dg_blockjacobi_setup: hipMalloc of ") +
-                                 std::to_string(need) + " bytes: " + hipGetErrorString(err));
-    ctx->blocks_bytes = need;
-  }
-  if (!ctx->d_status) {
-    hipError_t err = hipMalloc(&ctx->d_status, sizeof(int));
-    if (err != hipSuccess) return fail(DG_ENOMEM, "dg_blockjacobi_setup: status allocation");
-  }
+  if (ctx->blocks.ensure(need) != hipSuccess) return fail_mem(ctx, "dg_blockjacobi_setup: block storage", need);
+  if (ctx->status.ensure(sizeof(int)) != hipSuccess) return fail_mem(ctx, "dg_blockjacobi_setup: status flag", 4);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  DG_HIP(hipMemsetAsync(ctx->d_status, 0, sizeof(int), st));
+  DG_HIP(hipMemsetAsync(ctx->status.p, 0, sizeof(int), st));
   const DevParams P = make_params(ctx, t_new, dt);
   int64_t nb = (ctx->Ne * 8 + 255) / 256;
   nb = (nb + 7) / 8 * 8;
@@ -1251,20 +1494,20 @@ int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new,
     return s;
   if (prec == DG_F64) {
     hipLaunchKernelGGL((q1_block_kernel<double, kJvpCondensed>), grid, block, 0, st,
-                       static_cast<const double*>(u), ctx->lin.as<double>(), static_cast<double*>(ctx->d_blocks),
+                       static_cast<const double*>(u), ctx->lin.as<double>(), ctx->blocks.as<double>(),
                        ctx->d_phase, P, nb);
     hipLaunchKernelGGL((invert_blocks_kernel<double, kNB>), grid_w, block, 0, st,
-                       static_cast<double*>(ctx->d_blocks), ctx->Ne, ctx->d_status);
+                       ctx->blocks.as<double>(), ctx->Ne, ctx->status.as<int>());
   } else {
     hipLaunchKernelGGL((q1_block_kernel<float, kJvpCondensed>), grid, block, 0, st,
-                       static_cast<const float*>(u), ctx->lin.as<float>(), static_cast<float*>(ctx->d_blocks),
+                       static_cast<const float*>(u), ctx->lin.as<float>(), ctx->blocks.as<float>(),
                        ctx->d_phase, P, nb);
     hipLaunchKernelGGL((invert_blocks_kernel<float, kNB>), grid_w, block, 0, st,
-                       static_cast<float*>(ctx->d_blocks), ctx->Ne, ctx->d_status);
+                       ctx->blocks.as<float>(), ctx->Ne, ctx->status.as<int>());
   }
   DG_HIP(hipGetLastError());
   int h_status = 0;
-  DG_HIP(hipMemcpyAsync(&h_status, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipMemcpyAsync(&h_status, ctx->status.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
   DG_HIP(hipStreamSynchronize(st));
   ctx->blocks_prec = int(prec);
   ctx->bh_valid = false;
@@ -1274,6 +1517,7 @@ int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new,
 
 int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
+  if (int s = check_q1(ctx, "dg_blockjacobi_apply")) return s;
   if (!x || !y) return fail(DG_EINVAL, "dg_blockjacobi_apply: null array");
   if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_apply: no setup yet");
   if (int(prec) != ctx->blocks_prec)
@@ -1282,11 +1526,11 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
   const dim3 grid{unsigned((ctx->Ne + 3) / 4), 1, 1}, block{256, 1, 1};
   if (prec == DG_F64)
     hipLaunchKernelGGL((apply_blocks_kernel<double, 7>), grid, block, 0, st,
-                       static_cast<const double*>(ctx->d_blocks), static_cast<const double*>(x),
+                       ctx->blocks.as<const double>(), static_cast<const double*>(x),
                        static_cast<double*>(y), ctx->Ne);
   else
     hipLaunchKernelGGL((apply_blocks_kernel<float, 7>), grid, block, 0, st,
-                       static_cast<const float*>(ctx->d_blocks), static_cast<const float*>(x),
+                       ctx->blocks.as<const float>(), static_cast<const float*>(x),
                        static_cast<float*>(y), ctx->Ne);
   DG_HIP(hipGetLastError());
   return DG_OK;
@@ -1294,15 +1538,16 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
 
 int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
+  if (int s = check_q1(ctx, "dg_blockjacobi_apply_bf16")) return s;
   if (!x || !y) return fail(DG_EINVAL, "dg_blockjacobi_apply_bf16: null array");
   if (!ctx->bh_valid && ctx->blocks_prec != DG_F32)
     return fail(DG_ESTATE, "dg_blockjacobi_apply_bf16: no FP32 setup");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!ctx->bh_valid) {
-    hipError_t e = ctx->bh.ensure(size_t(ctx->Ne) * kNB * kNB * 2);
-    if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_blockjacobi_apply_bf16: ") + hipGetErrorString(e));
+    if (ctx->bh.ensure(size_t(ctx->Ne) * kNB * kNB * 2) != hipSuccess)
+      return fail_mem(ctx, "dg_blockjacobi_apply_bf16", size_t(ctx->Ne) * kNB * kNB * 2);
     hipLaunchKernelGGL((blocks_to_bf16_kernel<kNB>), dim3(8192), dim3(256), 0, st,
-                       static_cast<const float*>(ctx->d_blocks), ctx->bh.as<uint16_t>(), ctx->Ne);
+                       ctx->blocks.as<const float>(), ctx->bh.as<uint16_t>(), ctx->Ne);
     DG_HIP(hipGetLastError());
     ctx->bh_valid = true;
   }
@@ -1329,10 +1574,10 @@ int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ctx->blocks_prec == DG_F64)
     hipLaunchKernelGGL((export_blocks_kernel<double, kNB>), dim3(4096), dim3(256), 0, st,
-                       static_cast<const double*>(ctx->d_blocks), static_cast<double*>(out), ctx->Ne);
+                       ctx->blocks.as<const double>(), static_cast<double*>(out), ctx->Ne);
   else
     hipLaunchKernelGGL((export_blocks_kernel<float, kNB>), dim3(4096), dim3(256), 0, st,
-                       static_cast<const float*>(ctx->d_blocks), static_cast<float*>(out), ctx->Ne);
+                       ctx->blocks.as<const float>(), static_cast<float*>(out), ctx->Ne);
   DG_HIP(hipGetLastError());
   return DG_OK;
 }
@@ -1359,6 +1604,7 @@ int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* o
   try {
     if (int s = check_ctx(ctx)) return s;
     if (!u) return fail(DG_EINVAL, "dg_step: null state");
+    if (int s = check_q1(ctx, "dg_step")) return s;
     if (!(dt > 0)) return fail(DG_EINVAL, "dg_step: dt must be positive");
     dg_solver_opts o;
     if (int s = normalize_opts(opts, o, "dg_step")) return s;
@@ -1376,6 +1622,7 @@ int dg_initial_state(dg_ctx* ctx, double t0, void* u, const dg_solver_opts* opts
   try {
     if (int s = check_ctx(ctx)) return s;
     if (!u) return fail(DG_EINVAL, "dg_initial_state: null state");
+    if (int s = check_q1(ctx, "dg_initial_state")) return s;
     dg_solver_opts o;
     if (int s = normalize_opts(opts, o, "dg_initial_state")) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1404,11 +1651,12 @@ int dg_outputs(dg_ctx* ctx, const void* u, double t, double* U_cell, double* mea
   try {
     if (int s = check_ctx(ctx)) return s;
     if (!u) return fail(DG_EINVAL, "dg_outputs: null state");
+    if (int s = check_q1(ctx, "dg_outputs")) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     constexpr int nb = kOutBlocks;
     SolverWork& W = ctx->work;
-    hipError_t e = W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double));
-    if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_outputs workspace: ") + hipGetErrorString(e));
+    if (W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double)) != hipSuccess)
+      return fail_mem(ctx, "dg_outputs workspace", size_t(kNumSums) * nb * sizeof(double));
     const DevParams P = make_params(ctx, t, 1.0);
     const double RT = kGas * ctx->params.T;
     const double q = ctx->j_el / (kFaraday * kKEanode);
@@ -1438,6 +1686,7 @@ int dg_outputs_noalloc(dg_ctx* ctx, const void* u, double t, double* U_cell, dou
   try {
     if (int s = check_ctx(ctx)) return s;
     if (!u) return fail(DG_EINVAL, "dg_outputs_noalloc: null state");
+    if (int s = check_q1(ctx, "dg_outputs_noalloc")) return s;
     double* scr = nullptr;
     if (int s = device_scratch(&scr)) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1482,6 +1731,7 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
   try {
     if (int s = check_ctx(ctx)) return s;
     if (!c || !t || !u_) return fail(DG_EINVAL, "dg_advance: null argument");
+    if (int s = check_q1(ctx, "dg_advance")) return s;
     if (!(c->dt > 0) || !(c->dt_max > 0)) return fail(DG_EINVAL, "dg_advance: step sizes must be positive");
     if (c->kind != DG_CTRL_NAIVE && c->kind != DG_CTRL_H211B) return fail(DG_EINVAL, "dg_advance: controller kind");
     if (c->kind == DG_CTRL_H211B && !(c->tol > 0)) return fail(DG_EINVAL, "dg_advance: H211b needs tol > 0");
@@ -1494,8 +1744,7 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
     SolverWork& W = ctx->work;
     for (DevBuf* b : {&W.z0, &W.zC, &W.zF}) {
       if (b != &W.z0 && c->kind != DG_CTRL_H211B) continue;
-      hipError_t e = b->ensure(bytes);
-      if (e != hipSuccess) return fail(DG_ENOMEM, std::string("dg_advance workspace: ") + hipGetErrorString(e));
+      if (b->ensure(bytes) != hipSuccess) return fail_mem(ctx, "dg_advance workspace", bytes);
     }
     double* z0 = W.z0.as<double>();
     DG_HIP(hipMemcpyAsync(z0, u, bytes, hipMemcpyDeviceToDevice, st));
@@ -1544,8 +1793,8 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
       double* zF = W.zF.as<double>();
       double lim = 0.0, err = HUGE_VAL, dt = c->dt;
       constexpr int nb = 1024;
-      hipError_t e = W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double));
-      if (e != hipSuccess) return fail(DG_ENOMEM, "dg_advance workspace");
+      if (W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double)) != hipSuccess)
+        return fail_mem(ctx, "dg_advance workspace", size_t(kNumSums) * nb * sizeof(double));
       while (lim < 0.9 || err > 1.02 * c->tol) {
         dt = c->dt;
         ++r.trials;
@@ -1643,6 +1892,9 @@ int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phase
     for (int s = 0; s < n; ++s) {
       if (!phases[s])
         return abandon(fail(DG_EINVAL, "dg_batch_setup: null phase map of structure " + std::to_string(s)));
+      if (meshes[s].order != 1)
+        return abandon(fail(DG_EUNSUPPORTED, "dg_batch_setup: structure " + std::to_string(s) +
+                                                 ": batches are built for order 1"));
       dg_ctx* c = nullptr;
       if (int code = dg_setup(&meshes[s], phases[s], &params[s], &c)) {
         const std::string why = g_last_error;

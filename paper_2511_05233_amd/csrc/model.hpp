@@ -114,6 +114,7 @@ struct DevParams {
   // fields, bit 7 for the solid fractions.  Inactive rows of a tangent are
   // zero and inactive solid fractions stay frozen (kAllFields: all active).
   int32_t active;
+  int32_t np;          // nodes per voxel, (k + 1)^3
   int64_t Ne;
 };
 

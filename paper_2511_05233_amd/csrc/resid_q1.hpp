@@ -179,9 +179,9 @@ template <typename S>
 __global__ void __launch_bounds__(256)
 solid_tangent_kernel(const S* __restrict__ U, S* __restrict__ Cw, const uint8_t* __restrict__ phase,
                      DevParams P) {
-  const int64_t FS = P.Ne * 8;
+  const int64_t FS = P.Ne * P.np;
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256)
-    solid_tangent_node(U, Cw, int(phase[k >> 3]), P, k, FS);
+    solid_tangent_node(U, Cw, int(phase[k / P.np]), P, k, FS);
 }
 
 // Load the nine unknowns of one node as operator numbers (Cw: the

@@ -33,13 +33,39 @@
 
 namespace lsbdg {
 
+// A caller-owned device workspace: buffers are carved from it in order,
+// 256-byte aligned, and never freed or moved (a carved buffer cannot grow).
+struct Arena {
+  unsigned char* base = nullptr;
+  size_t size = 0, used = 0;
+  size_t short_by = 0;              // bytes missing at the last failed request
+  static size_t aligned(size_t n) { return (n + 255) & ~size_t(255); }
+};
+
+// Device buffer: hipMalloc'd by the library, or carved from an Arena.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Arena* arena = nullptr;
   template <typename T>
   T* as() const { return static_cast<T*>(p); }
   hipError_t ensure(size_t n) {
     if (bytes >= n) return hipSuccess;
+    if (arena) {
+      if (p) {                      // sized once; a different size means another use than planned
+        arena->short_by = n - bytes;
+        return hipErrorOutOfMemory;
+      }
+      const size_t off = Arena::aligned(arena->used);
+      if (off + n > arena->size) {
+        arena->short_by = off + n - arena->size;
+        return hipErrorOutOfMemory;
+      }
+      p = arena->base + off;
+      arena->used = off + n;
+      bytes = n;
+      return hipSuccess;
+    }
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
@@ -48,7 +74,7 @@ struct DevBuf {
     return e;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !arena) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -63,6 +89,13 @@ struct SolverWork {
   DevBuf pc, pc2, scc;                             // two-level preconditioner temporaries, scales (S)
   DevBuf gstate;                                   // GMRES cycle state on the device (GmresState)
   int m = 0;
+  template <typename F>
+  void for_each(F f) {
+    for (DevBuf* d : {&m_old, &R, &Rtry, &u_try, &du, &wR, &uS, &sc, &V, &w, &t, &pJ, &rhs, &b, &x,
+                      &y9, &v9, &JZ, &partial, &partial64, &dots, &yc, &Ainv, &hbuf, &z0, &zC, &zF,
+                      &out_partial, &pc, &pc2, &scc, &gsum, &gstate})
+      f(*d);
+  }
   void release_all() {
     for (DevBuf* d : {&m_old, &R, &Rtry, &u_try, &du, &wR, &uS, &sc, &V, &w, &t, &pJ, &rhs, &b, &x,
                       &y9, &v9, &JZ, &partial, &partial64, &dots, &yc, &Ainv, &hbuf, &z0, &zC, &zF,

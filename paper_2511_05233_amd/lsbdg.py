@@ -25,6 +25,9 @@ _SIGNATURES = {
     "dg_params_default": (None, [C.c_void_p]),
     "dg_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "dg_destroy": (C.c_int, [C.c_void_p]),
+    "dg_workspace_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)]),
+    "dg_setup_ws": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
+                              C.c_void_p, C.POINTER(C.c_void_p)]),
     "dg_info": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5),
     "dg_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
@@ -120,6 +123,7 @@ class DgBatchTuning(C.Structure):
 
 
 DG_CTRL_NAIVE, DG_CTRL_H211B = 0, 1
+DG_WS_OPERATORS, DG_WS_BLOCKS, DG_WS_STEP, DG_WS_NAIVE, DG_WS_H211B, DG_WS_ALL = 1, 2, 4, 8, 16, 31
 
 
 class DgController(C.Structure):
@@ -262,11 +266,30 @@ def make_params(D0=None, kE=None, f_C=None, j_el=None, eps_struct=None, sigma=No
     return p
 
 
+def workspace_bytes(nx, ny, nz, h, order, features, inner="f32", params=None, **opts):
+    """dg_workspace_bytes: device bytes a workspace context needs for the
+    uses in `features` (DG_WS_* mask) with these solver options."""
+    lib = load()
+    mesh = DgMesh(int(nx), int(ny), int(nz), int(order), float(h))
+    p = params if params is not None else default_params()
+    o = _solver_opts(inner, opts)
+    n = C.c_size_t()
+    _check("dg_workspace_bytes", lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), C.byref(o), int(features),
+                                                        C.byref(n)))
+    return int(n.value)
+
+
 class Context:
-    """One voxel structure: mesh, phase map and parameters on the device."""
+    """One voxel structure: mesh, phase map and parameters on the device.
+
+    workspace: a device tensor (uint8, contiguous) the context takes all its
+    device memory from (dg_setup_ws), sized for `features` and the solver
+    options `ws_opts` (inner precision "ws_inner"); kept alive by the
+    context."""
 
     def __init__(self, nx, ny, nz, h, order, phase, D0=None, kE=None, f_C=None, j_el=None,
-                 eps_struct=None, sigma=None, use_TH=None, T=None):
+                 eps_struct=None, sigma=None, use_TH=None, T=None, workspace=None, features=0, ws_inner="f32",
+                 ws_opts=None):
         lib = load()
         self.nx, self.ny, self.nz, self.h, self.order = int(nx), int(ny), int(nz), float(h), int(order)
         self.n_elem = self.nx * self.ny * self.nz
@@ -279,8 +302,18 @@ class Context:
         self.params = p
         mesh = DgMesh(self.nx, self.ny, self.nz, self.order, self.h)
         handle = C.c_void_p()
-        _check("dg_setup", lib.dg_setup(C.byref(mesh), ph.ctypes.data_as(C.c_void_p),
-                                        C.byref(p), C.byref(handle)))
+        self._ws = workspace
+        if workspace is None:
+            _check("dg_setup", lib.dg_setup(C.byref(mesh), ph.ctypes.data_as(C.c_void_p),
+                                            C.byref(p), C.byref(handle)))
+        else:
+            import torch
+            if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("the workspace is a contiguous uint8 device tensor")
+            o = _solver_opts(ws_inner, ws_opts or {})
+            _check("dg_setup_ws", lib.dg_setup_ws(C.byref(mesh), ph.ctypes.data_as(C.c_void_p), C.byref(p),
+                                                  C.byref(o), int(features), C.c_void_p(workspace.data_ptr()),
+                                                  workspace.numel(), _stream(), C.byref(handle)))
         self._h = handle
         self._lib = lib
 

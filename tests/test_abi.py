@@ -120,9 +120,33 @@ def test_binding_constants_match_the_header_enums():
     for body in re.findall(r"typedef\s+enum\s*\w*\s*\{(.*?)\}", src, flags=re.S):
         for name, val in re.findall(r"\b(DG_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
             enums[name] = int(val)
-    assert len(enums) == 18, sorted(enums)   # status 8, precision 2, JVP 3, controller 2, batch op 3
+    assert len(enums) == 24, sorted(enums)   # status 8, precision 2, JVP 3, controller 2, batch op 3, workspace 6
     for name, val in enums.items():
         if hasattr(lsbdg, name):
             assert getattr(lsbdg, name) == val, name
         else:
             assert lsbdg._STATUS[val] == name, name
+
+
+def test_orders_and_workspace_sizes_are_checked_on_the_host(lib):
+    """Orders outside {0, 1, 3} are invalid and order 3 is not built; the
+    workspace of the operator entry points holds the phase map, the
+    status flag, the FP64 linearisation (14 values per node) and the output
+    partial sums, each 256-byte aligned."""
+    import ctypes as C
+    p = lsbdg.default_params()
+    ph = (C.c_uint8 * 8)(*([1] * 8))
+    out = C.c_void_p()
+    for order, code in ((2, -1), (-1, -1), (3, -7)):
+        mesh = lsbdg.DgMesh(2, 2, 2, order, 1e-6)
+        assert lib.dg_setup(C.byref(mesh), ph, C.byref(p), C.byref(out)) == code, order
+    mesh = lsbdg.DgMesh(96, 96, 192, 1, 1e-6)
+    n = C.c_size_t()
+    assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, 64, C.byref(n)) == -1
+    assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, lsbdg.DG_WS_OPERATORS, C.byref(n)) == 0
+    al = lambda x: (x + 255) // 256 * 256
+    Ne = 96 * 96 * 192
+    expect = al(al(al(Ne) + 4) + 14 * Ne * 8 * 8) + 15 * 1024 * 8
+    assert n.value == al(expect), (n.value, expect)
+    mesh0 = lsbdg.DgMesh(4, 4, 4, 0, 1e-6)
+    assert lib.dg_workspace_bytes(C.byref(mesh0), C.byref(p), None, lsbdg.DG_WS_STEP, C.byref(n)) == -7
