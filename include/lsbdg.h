@@ -547,6 +547,14 @@ int dg_batch_initial_state(dg_batch* b, const double* t0, void* u, const dg_solv
 int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, const dg_solver_opts* opts,
                   dg_step_report* reports, int32_t workers, dg_stream stream);
 
+/* Measurement: the STREAM triad out[i] = a[i] + s b[i] (McCalpin's
+ * bandwidth benchmark) for i < n, on device arrays of doubles, enqueued on
+ * `stream`.  It moves 24 bytes per element through HBM, so its rate bounds
+ * what a streaming kernel of this library can reach.  The arrays must be
+ * 16-byte aligned and n even (DG_EINVAL otherwise); out must not overlap
+ * a or b.  n = 0 is a no-op. */
+int dg_triad(double* out, const double* a, const double* b, double s, int64_t n, dg_stream stream);
+
 /* Human-readable description of the last error on this thread. */
 const char* dg_last_error(void);
 

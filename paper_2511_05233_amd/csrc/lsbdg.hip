@@ -1131,6 +1131,25 @@ void outputs_from_sums(const dg_ctx* ctx, const double* acc, double* U_cell, dou
 
 }  // namespace
 
+// STREAM triad out = a + s b over n2 pairs of doubles (16-byte accesses,
+// grid-stride, two pairs per lane per pass so that each wave keeps four
+// loads in flight).
+__global__ void __launch_bounds__(256)
+triad_kernel(double2* __restrict__ out, const double2* __restrict__ a, const double2* __restrict__ b, double s,
+             int64_t n2) {
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  for (; i + stride < n2; i += 2 * stride) {
+    const double2 a0 = a[i], b0 = b[i], a1 = a[i + stride], b1 = b[i + stride];
+    out[i] = make_double2(a0.x + s * b0.x, a0.y + s * b0.y);
+    out[i + stride] = make_double2(a1.x + s * b1.x, a1.y + s * b1.y);
+  }
+  if (i < n2) {
+    const double2 a0 = a[i], b0 = b[i];
+    out[i] = make_double2(a0.x + s * b0.x, a0.y + s * b0.y);
+  }
+}
+
 extern "C" {
 
 void dg_params_default(dg_params* p) {
@@ -2305,6 +2324,29 @@ int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, con
     return fail(DG_ENOMEM, "dg_batch_step: host allocation failed");
   } catch (...) {
     return fail(DG_EINVAL, "dg_batch_step: unexpected exception");
+  }
+}
+
+int dg_triad(double* out, const double* a, const double* b, double s, int64_t n, dg_stream stream) {
+  try {
+    if (n < 0) return fail(DG_EINVAL, "dg_triad: negative length");
+    if (n == 0) return DG_OK;
+    if (!out || !a || !b) return fail(DG_EINVAL, "dg_triad: null array");
+    if ((n & 1) || ((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(a) |
+                     reinterpret_cast<uintptr_t>(b)) & 15))
+      return fail(DG_EINVAL, "dg_triad: arrays must be 16-byte aligned and of even length");
+    const int64_t n2 = n / 2;
+    // 8 workgroups of 256 lanes per compute unit, each lane two 16-byte
+    // pairs in flight per iteration
+    const int64_t want = (n2 + 511) / 512;
+    const unsigned nb = unsigned(want < 2048 ? want : 2048);
+    hipLaunchKernelGGL(triad_kernel, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       reinterpret_cast<double2*>(out), reinterpret_cast<const double2*>(a),
+                       reinterpret_cast<const double2*>(b), s, n2);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_triad: unexpected exception");
   }
 }
 

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "dg_batch_get_shape": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p]),
     "dg_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dg_triad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int64, C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
 
@@ -277,6 +278,17 @@ def workspace_bytes(nx, ny, nz, h, order, features, inner="f32", params=None, **
     _check("dg_workspace_bytes", lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), C.byref(o), int(features),
                                                         C.byref(n)))
     return int(n.value)
+
+
+def triad(out, a, b, s):
+    """dg_triad: out = a + s b on FP64 device arrays of one length (STREAM
+    triad, 24 bytes per element), on the current stream."""
+    import torch
+    lib = load()
+    for t in (out, a, b):
+        if t.dtype != torch.float64 or t.numel() != out.numel():
+            raise ValueError("triad: FP64 arrays of one length")
+    _check("dg_triad", lib.dg_triad(_ptr(out), _ptr(a), _ptr(b), float(s), int(out.numel()), _stream()))
 
 
 class Context:

@@ -150,3 +150,11 @@ def test_orders_and_workspace_sizes_are_checked_on_the_host(lib):
     assert n.value == al(expect), (n.value, expect)
     mesh0 = lsbdg.DgMesh(4, 4, 4, 0, 1e-6)
     assert lib.dg_workspace_bytes(C.byref(mesh0), C.byref(p), None, lsbdg.DG_WS_STEP, C.byref(n)) == -7
+
+
+def test_triad_rejects_bad_arguments_on_the_host(lib):
+    """dg_triad refuses a negative length and null arrays, and n = 0 is a
+    no-op, all before any device call."""
+    assert lib.dg_triad(None, None, None, 1.0, 0, None) == 0
+    assert lib.dg_triad(None, None, None, 1.0, -2, None) == -1
+    assert lib.dg_triad(None, None, None, 1.0, 4, None) == -1
