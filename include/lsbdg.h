@@ -241,6 +241,13 @@ typedef struct {
                             every coarse_every iterates (0:
                             default 3; 1: every iterate); the element blocks
                             are rebuilt at every iterate */
+  int32_t limiter;       /* 1: every converged step's root (and, with H211b,
+                            the extrapolated state) is limited by dg_limit;
+                            the multiplicative Newton update is then capped
+                            from above only, so that a concentration can fall
+                            to zero and continue additively (roots with
+                            negative nodal values are reached before
+                            limiting).  0 (default): no limiter */
 } dg_solver_opts;
 
 void dg_solver_opts_default(dg_solver_opts* o);
@@ -266,7 +273,8 @@ typedef enum {
   DG_WS_STEP = 4,       /* dg_step, dg_initial_state with opts */
   DG_WS_NAIVE = 8,      /* dg_advance, naive controller (one saved state) */
   DG_WS_H211B = 16,     /* dg_advance, H211b (three saved states) */
-  DG_WS_ALL = 31
+  DG_WS_LIMITER = 32,   /* dg_limit (implied for steps when opts->limiter = 1) */
+  DG_WS_ALL = 63
 } dg_workspace_use;
 
 /* Bytes of device workspace a dg_setup_ws context of this mesh needs for
@@ -546,6 +554,23 @@ int dg_batch_initial_state(dg_batch* b, const double* t0, void* u, const dg_solv
  * dg_step, for the first failing structure; DG_EINVAL for dt[s] <= 0. */
 int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, const dg_solver_opts* opts,
                   dg_step_report* reports, int32_t workers, dg_stream stream);
+
+/* Vertex-based slope limiter of the Q1 state u (device, FP64, 9 fields),
+ * in place: Kuzmin's limiter, which the paper's DG1 runs use (App. B.1,
+ * B.2), applied to the conserved densities m_i = eps_L c_i of the six
+ * dissolved species so that every voxel keeps the amount of each species.
+ * Each voxel's deviation from its mean of m_i is scaled by the largest
+ * alpha in [0, 1] that keeps the corner values of its trilinear polynomial
+ * between the smallest and largest voxel mean at each corner vertex; then
+ * c_i = m_i / eps_L.  Every limited nodal value lies within the means of
+ * the voxels around it, so non-negative means give a non-negative state
+ * (the positivity-preserving p = 1 scheme of the paper's outlook, Sec. 4).
+ * Phi_L and the solid fractions are not changed.  alpha: optional device
+ * array (FP64, 6 x n_elem, species-major) that receives the factors, or
+ * NULL.  Order 0: no-op.  Enqueued on `stream`; device workspace of
+ * 48 bytes per voxel, allocated on first use and kept (DG_WS_LIMITER on a
+ * workspace context). */
+int dg_limit(dg_ctx* ctx, void* u, void* alpha, dg_stream stream);
 
 /* Measurement: the STREAM triad out[i] = a[i] + s b[i] (McCalpin's
  * bandwidth benchmark) for i < n, on device arrays of doubles, enqueued on

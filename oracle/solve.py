@@ -374,7 +374,13 @@ def initial_state(P, t0=0.0, **kw):
     return u, info
 
 
-def be_step(P, u_n, t_n, dt, **kw):
-    """One backward-Euler step from (t_n, u_n) to t_n + dt (Eq. 50)."""
+def be_step(P, u_n, t_n, dt, limiter=False, **kw):
+    """One backward-Euler step from (t_n, u_n) to t_n + dt (Eq. 50).
+    limiter=True: the Newton root is then limited by the vertex-based
+    limiter of oracle/limiter.py."""
     m_old = dg.old_mass(P, u_n)
-    return newton(P, u_n, m_old, t_n + dt, dt, **kw)
+    u, info = newton(P, u_n, m_old, t_n + dt, dt, **kw)
+    if limiter:
+        from . import limiter as lim
+        u = lim.limit(P, u)[0]
+    return u, info

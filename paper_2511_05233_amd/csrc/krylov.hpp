@@ -401,10 +401,16 @@ solid_delta_kernel(const double* __restrict__ U, const double* __restrict__ du7,
 // u_out = u (+) lam du: positive unknowns multiplicatively, x exp(lam du/x)
 // with the exponent clamped to [-ln 10, ln 10] (at most a factor 10 per
 // iteration either way, so no unknown collapses to zero or to the scale
-// floor in one step); Phi_L and non-positive entries additively.  Also returns per-block maxima of |du|/scale (full step).
+// floor in one step); Phi_L and non-positive entries additively.  With
+// cross = 1 (steps whose root is limited afterwards) the exponent is
+// clamped from above only: an unknown may then fall to zero in one
+// iteration (exp underflows) and continue additively, so that the
+// iteration can reach a root with negative nodal values.  Also returns
+// per-block maxima of |du|/scale (full step).
 __global__ void __launch_bounds__(256)
 newton_update_kernel(const double* __restrict__ U, const double* __restrict__ dU, double lam,
-                     double* __restrict__ Uout, int64_t FS, double phi_floor, double* __restrict__ partial) {
+                     double* __restrict__ Uout, int64_t FS, double phi_floor, double* __restrict__ partial,
+                     int cross) {
   __shared__ double sh[4];
   double mx = 0.0;
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < 9 * FS; k += int64_t(gridDim.x) * 256) {
@@ -420,7 +426,7 @@ newton_update_kernel(const double* __restrict__ U, const double* __restrict__ dU
     } else {
       double ex = lam * d / x;
       ex = ex < 2.302585092994046 ? ex : 2.302585092994046;
-      ex = ex > -2.302585092994046 ? ex : -2.302585092994046;
+      if (!cross) ex = ex > -2.302585092994046 ? ex : -2.302585092994046;
       y = x * exp(ex);
     }
     Uout[k] = y;

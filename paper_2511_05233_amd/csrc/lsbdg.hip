@@ -30,6 +30,7 @@
 #include "blockjacobi.hpp"
 #include "solver.hpp"
 #include "outputs.hpp"
+#include "limiter.hpp"
 #include "coarse.hpp"
 #include "batch.hpp"
 
@@ -422,6 +423,8 @@ std::vector<std::pair<DevBuf*, size_t>> plan_workspace(dg_ctx* ctx, const dg_sol
       need_rocsolver = true;
     }
   }
+  if ((features & DG_WS_LIMITER) || (step && o.limiter))
+    out.push_back(std::make_pair(&ctx->work.lmean, size_t(6) * ctx->Ne * 8));
   if (features & (DG_WS_NAIVE | DG_WS_H211B)) out.push_back(std::make_pair(&ctx->work.z0, size_t(9) * FS * 8));
   if (features & DG_WS_H211B) {
     out.push_back(std::make_pair(&ctx->work.zC, size_t(9) * FS * 8));
@@ -847,7 +850,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     double lam = 1.0, upd = 0.0, mt = 0.0;
     bool found = false;
     for (int ls = 0; ls <= (near_root ? 3 : 40); ++ls) {
-      hipLaunchKernelGGL(newton_update_kernel, gred, blk, 0, st, u, du, lam, u_try, FS, phi_floor, partial64);
+      hipLaunchKernelGGL(newton_update_kernel, gred, blk, 0, st, u, du, lam, u_try, FS, phi_floor, partial64,
+                         o.limiter);
       std::vector<double> pm(nred);
       DG_HIP(hipMemcpyAsync(pm.data(), partial64, nred * sizeof(double), hipMemcpyDeviceToHost, st));
       resid64(u_try, Rtry);
@@ -931,13 +935,34 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
   if (o.coarse > 4) return fail(DG_EINVAL, std::string(fn) + ": coarse must be -1..4");
   if (o.coarse_every == 0) o.coarse_every = 3;
   if (o.coarse_every < 0) return fail(DG_EINVAL, std::string(fn) + ": coarse_every must be >= 0");
+  if (o.limiter != 0 && o.limiter != 1) return fail(DG_EINVAL, std::string(fn) + ": limiter must be 0 or 1");
+  return DG_OK;
+}
+
+// Vertex-based limiter of the Q1 state u in place (limiter.hpp); alpha:
+// optional device array of the factors (6 x Ne).  Order 0 has nothing to
+// limit.
+int limit_state(dg_ctx* ctx, double* u, double* alpha, hipStream_t st) {
+  if (ctx->np == 1) return DG_OK;
+  const size_t need = size_t(6) * ctx->Ne * sizeof(double);
+  if (ctx->work.lmean.ensure(need) != hipSuccess) return fail_mem(ctx, "limiter workspace", need);
+  const DevParams P = make_params(ctx, 0.0, 1.0);
+  double* mb = ctx->work.lmean.as<double>();
+  hipLaunchKernelGGL(limit_means_kernel, grid1(ctx->Ne), dim3(256), 0, st, u, ctx->d_phase, P, mb);
+  hipLaunchKernelGGL(limit_apply_kernel, grid1(ctx->Ne), dim3(256), 0, st, u, ctx->d_phase, P,
+                     static_cast<const double*>(mb), alpha);
+  DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
 int solve_once(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_opts& o, dg_step_report* rep,
                hipStream_t st, int active = kAllFields) {
-  if (o.inner_prec == DG_F32) return newton_solve<float>(ctx, t_n, dt, u, o, rep, st, active);
-  return newton_solve<double>(ctx, t_n, dt, u, o, rep, st, active);
+  const int s = o.inner_prec == DG_F32 ? newton_solve<float>(ctx, t_n, dt, u, o, rep, st, active)
+                                       : newton_solve<double>(ctx, t_n, dt, u, o, rep, st, active);
+  if (s != DG_OK || !o.limiter || active != kAllFields) return s;
+  if (int e = limit_state(ctx, u, nullptr, st)) return e;
+  DG_HIP(hipStreamSynchronize(st));
+  return DG_OK;
 }
 
 }  // namespace
@@ -1858,6 +1883,8 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
       }
       hipLaunchKernelGGL(richardson_kernel, grid1(n9), dim3(256), 0, st, zF, zC, u, n9);
       DG_HIP(hipGetLastError());
+      if (o.limiter)                  // the extrapolated state is limited as each step's root is
+        if (int s = limit_state(ctx, u, nullptr, st)) return s;
       DG_HIP(hipStreamSynchronize(st));
       c->err_prev = err;
       c->dt_prev = dt;
@@ -2327,6 +2354,16 @@ int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, con
   }
 }
 
+int dg_limit(dg_ctx* ctx, void* u, void* alpha, dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (!u) return fail(DG_EINVAL, "dg_limit: null state");
+    return limit_state(ctx, static_cast<double*>(u), static_cast<double*>(alpha), static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_limit: unexpected exception");
+  }
+}
+
 int dg_triad(double* out, const double* a, const double* b, double s, int64_t n, dg_stream stream) {
   try {
     if (n < 0) return fail(DG_EINVAL, "dg_triad: negative length");
@@ -2336,10 +2373,9 @@ int dg_triad(double* out, const double* a, const double* b, double s, int64_t n,
                      reinterpret_cast<uintptr_t>(b)) & 15))
       return fail(DG_EINVAL, "dg_triad: arrays must be 16-byte aligned and of even length");
     const int64_t n2 = n / 2;
-    // 8 workgroups of 256 lanes per compute unit, each lane two 16-byte
-    // pairs in flight per iteration
+    // one pass of the grid where possible: each lane two 16-byte pairs
     const int64_t want = (n2 + 511) / 512;
-    const unsigned nb = unsigned(want < 2048 ? want : 2048);
+    const unsigned nb = unsigned(want < (int64_t(1) << 20) ? want : (int64_t(1) << 20));
     hipLaunchKernelGGL(triad_kernel, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream),
                        reinterpret_cast<double2*>(out), reinterpret_cast<const double2*>(a),
                        reinterpret_cast<const double2*>(b), s, n2);

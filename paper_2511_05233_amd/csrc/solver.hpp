@@ -88,18 +88,19 @@ struct SolverWork {
   DevBuf z0, zC, zF, out_partial;                  // time controller, outputs (FP64)
   DevBuf pc, pc2, scc;                             // two-level preconditioner temporaries, scales (S)
   DevBuf gstate;                                   // GMRES cycle state on the device (GmresState)
+  DevBuf lmean;                                    // limiter: voxel means of eps_L c_i (FP64, 6 x Ne)
   int m = 0;
   template <typename F>
   void for_each(F f) {
     for (DevBuf* d : {&m_old, &R, &Rtry, &u_try, &du, &wR, &uS, &sc, &V, &w, &t, &pJ, &rhs, &b, &x,
                       &y9, &v9, &JZ, &partial, &partial64, &dots, &yc, &Ainv, &hbuf, &z0, &zC, &zF,
-                      &out_partial, &pc, &pc2, &scc, &gsum, &gstate})
+                      &out_partial, &pc, &pc2, &scc, &gsum, &gstate, &lmean})
       f(*d);
   }
   void release_all() {
     for (DevBuf* d : {&m_old, &R, &Rtry, &u_try, &du, &wR, &uS, &sc, &V, &w, &t, &pJ, &rhs, &b, &x,
                       &y9, &v9, &JZ, &partial, &partial64, &dots, &yc, &Ainv, &hbuf, &z0, &zC, &zF,
-                      &out_partial, &pc, &pc2, &scc, &gsum, &gstate})
+                      &out_partial, &pc, &pc2, &scc, &gsum, &gstate, &lmean})
       d->release();
   }
 };

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "dg_batch_get_shape": (C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.c_void_p]),
     "dg_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dg_limit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_triad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int64, C.c_void_p]),
     "dg_last_error": (C.c_char_p, []),
 }
@@ -95,7 +96,7 @@ class DgSolverOpts(C.Structure):
                 ("newton_maxit", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_rtol_final", C.c_double),
                 ("newton_tol", C.c_double),
                 ("coarse", C.c_int32), ("coarse_agg", C.c_int32), ("block_bf16", C.c_int32),
-                ("verbose", C.c_int32), ("coarse_every", C.c_int32)]
+                ("verbose", C.c_int32), ("coarse_every", C.c_int32), ("limiter", C.c_int32)]
 
 
 class DgStepReport(C.Structure):
@@ -124,7 +125,8 @@ class DgBatchTuning(C.Structure):
 
 
 DG_CTRL_NAIVE, DG_CTRL_H211B = 0, 1
-DG_WS_OPERATORS, DG_WS_BLOCKS, DG_WS_STEP, DG_WS_NAIVE, DG_WS_H211B, DG_WS_ALL = 1, 2, 4, 8, 16, 31
+DG_WS_OPERATORS, DG_WS_BLOCKS, DG_WS_STEP, DG_WS_NAIVE, DG_WS_H211B, DG_WS_LIMITER = 1, 2, 4, 8, 16, 32
+DG_WS_ALL = 63
 
 
 class DgController(C.Structure):
@@ -479,6 +481,17 @@ class Context:
         fn = "dg_outputs_noalloc" if noalloc else "dg_outputs"
         _check(fn, getattr(self._lib, fn)(self._h, _ptr(u), float(t), C.byref(U), means, sums, _stream()))
         return {"U_cell": U.value, "means": np.array(means[:]), "sums": np.array(sums[:])}
+
+    def limit(self, u, alpha=False):
+        """dg_limit: the vertex-based limiter on state u (FP64, 9 fields) in
+        place; alpha=True also returns the factors (6, n_elem)."""
+        import torch
+        self._check_arr(u, 9)
+        if u.dtype != torch.float64:
+            raise ValueError("the state is FP64")
+        a = torch.empty((6, self.n_elem), dtype=torch.float64, device=u.device) if alpha else None
+        _check("dg_limit", self._lib.dg_limit(self._h, _ptr(u), _ptr(a) if alpha else None, _stream()))
+        return a
 
     def advance(self, ctrl, t, u, inner="f32", **opts):
         """One accepted controller step from t (u in place); returns (t_new, report)."""
