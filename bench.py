@@ -361,9 +361,12 @@ def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
             "rel_l2_mixed_vs_f64": [float(f"{x:.2e}") for x in rel]}
 
 
-def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9, max_steps=5000):
+def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9, max_steps=5000, limiter=0,
+              max_wall=None):
     """Full galvanostatic discharge under the naive controller (Sec. 2.8):
-    from the initial state until U_cell <= cutoff or t >= 3600 / f_C."""
+    from the initial state until U_cell <= cutoff or t >= 3600 / f_C
+    (limiter = 1: every step's root limited, dg_limit; max_wall: stop after
+    that many seconds, reported as ended_by "wall")."""
     import torch
     import synth
     from paper_2511_05233_amd import lsbdg
@@ -379,7 +382,9 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
     U = ctx.outputs(u, t)["U_cell"]
     curve = [(0.0, U)]
     while t < t_end and U > cutoff and tot["steps"] < max_steps:
-        t, rep = ctx.advance(ctrl, t, u, inner=inner, coarse=coarse, coarse_agg=coarse_agg)
+        if max_wall is not None and time.perf_counter() - w0 > max_wall:
+            break
+        t, rep = ctx.advance(ctrl, t, u, inner=inner, coarse=coarse, coarse_agg=coarse_agg, limiter=limiter)
         for k in ("trials", "halvings", "newton_its", "gmres_its"):
             tot[k] += rep[k]
         tot["steps"] += 1
@@ -392,7 +397,9 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
     soc = 1.0 - t / t_end
     return {"workload": f"{workload} at {f_C}C", "s_per_discharge": round(wall, 2), "t_end_s": round(t, 3),
             "U_end_V": round(U, 5), "soc_end": round(soc, 4), **tot,
-            "ended_by": "cutoff" if U <= cutoff else ("time" if t >= t_end else "step limit"),
+            "limiter": limiter,
+            "ended_by": "cutoff" if U <= cutoff else ("time" if t >= t_end else
+                                                      ("step limit" if tot["steps"] >= max_steps else "wall")),
             "curve_tU": [(round(a, 3), round(b, 6)) for a, b in curve[:: max(1, len(curve) // 40)]],
             "_curve": curve}
 
@@ -647,6 +654,8 @@ def main(argv=None):
                     help="run one full discharge of WORKLOAD (naive controller, cutoff 1.9 V) and print "
                          "its wall time instead of the benchmark line")
     ap.add_argument("--discharge-rate", type=float, default=1.0, help="C-rate of --discharge")
+    ap.add_argument("--limiter", action="store_true", help="--discharge: limit every step's root (dg_limit)")
+    ap.add_argument("--max-wall", type=float, default=None, help="--discharge: stop after this many seconds")
     ap.add_argument("--batch", action="store_true",
                     help="the 64-structure batch workload in full (operators, block preconditioner, "
                          "side-by-side solves) and print that record only")
@@ -681,7 +690,8 @@ def main(argv=None):
         print(json.dumps(batch_throughput(torch.device("cuda:0"), log)), flush=True)
         return 0
     if args.discharge:
-        out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log)
+        out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log,
+                        limiter=int(args.limiter), max_wall=args.max_wall)
         out.pop("_curve")
         print(json.dumps(out), flush=True)
         return 0

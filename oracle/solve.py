@@ -217,11 +217,15 @@ class _SparseSolver:
     """Newton directions from the probed sparse Jacobian J (kept for several
     Newton iterations: the chord method, whose limit is the same root).
 
-    GMRES on the column-scaled system A = J diag(S), left-preconditioned by
-    the exact element-diagonal blocks of A plus an additive coarse
-    correction Z E^-1 Z^T on per-field constants over aggregates of edge^3
-    voxels (E = Z^T A Z, dense LU).  Only the speed of the linear solves
-    depends on these choices, not the root."""
+    GMRES on the equilibrated system A = D_r J diag(S) (columns scaled by
+    the unknown magnitudes, rows by their largest entry), right-
+    preconditioned by the exact element-diagonal blocks of A plus an
+    additive coarse correction Z E^-1 Z^T on per-field constants over
+    aggregates of edge^3 voxels (E = Z^T A Z, dense LU).  Right
+    preconditioning makes GMRES minimise the residual of the equilibrated
+    system itself, so its tolerance bounds the error of the direction.
+    Only the speed of the linear solves depends on these choices, not the
+    root."""
 
     def __init__(self, P, Jm, S, fields, edge=4):
         import scipy.sparse as sp
@@ -230,6 +234,8 @@ class _SparseSolver:
         nb = nf * npn
         self.shape = (nf, Ne, npn)
         A = (Jm @ sp.diags(S.reshape(-1))).tocsr()
+        self.rs = 1.0 / np.maximum(abs(A).max(axis=1).toarray().ravel(), 1e-300)
+        A = (sp.diags(self.rs) @ A).tocsr()
         self.A = A
         # element blocks: unknown (f, e, a) -> element e, block index f npn + a
         k = np.arange(nf * Ne * npn)
@@ -258,13 +264,14 @@ class _SparseSolver:
         return y + self.Z @ self._sla.lu_solve(self.lu, self.Z.T @ r)
 
     def direction(self, R, rtol, restart):
+        """y with A y = -D_r R to relative residual rtol (du = S y)."""
         n = self.A.shape[0]
-        b = -self.precond(R.reshape(-1))
-        op = spla.LinearOperator((n, n), matvec=lambda y: self.precond(self.A @ y), dtype=np.float64)
+        b = -self.rs * R.reshape(-1)
+        op = spla.LinearOperator((n, n), matvec=lambda z: self.A @ self.precond(z), dtype=np.float64)
         count = [0]
-        y, info = spla.gmres(op, b, rtol=rtol, atol=0.0, restart=restart, maxiter=10,
+        z, info = spla.gmres(op, b, rtol=rtol, atol=0.0, restart=restart, maxiter=10,
                              callback=lambda _x: count.__setitem__(0, count[0] + 1), callback_type="pr_norm")
-        return y, count, info
+        return self.precond(z), count, info
 
 
 def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
