@@ -109,16 +109,18 @@ void dg_params_default(dg_params* p);
 /* Create a context for one voxel structure; the library allocates its
  * device memory as it is first needed (dg_setup_ws: in a caller-owned
  * workspace instead).
- *   mesh   mesh and degree: order 0 (the finite-volume scheme of Eq. 48:
- *          operators, blocks and outputs) or 1 (Q1: every entry point)
+ *   mesh   mesh and degree: order 1 (Q1: every entry point); order 0
+ *          (the finite-volume scheme of Eq. 48) and order 3 (tricubic,
+ *          4 x 4 x 4 Gauss nodes per voxel, Eq. 43-47 with sigma = 16): the
+ *          operators dg_mass, dg_residual, dg_linearize and dg_jvp; the
+ *          other entry points return DG_EUNSUPPORTED for them
  *   phase  HOST array of nx*ny*nz bytes, x fastest: 0 = pore voxel
  *          (electrolyte only, no reactions), 1 = cathode structure voxel
  *          (Eq. 57 localisation); copied, may be freed after the call
  *   params parameters (copied)
  *   out    receives the context
  * Errors: DG_EINVAL (null pointer, non-positive size, phase not 0/1,
- * order not one of 0, 1, 3), DG_EUNSUPPORTED (order 3, not built),
- * DG_ENOMEM, DG_EHIP. */
+ * order not one of 0, 1, 3), DG_ENOMEM, DG_EHIP. */
 int dg_setup(const dg_mesh* mesh, const uint8_t* phase, const dg_params* params,
              dg_ctx** out);
 
@@ -567,7 +569,9 @@ int dg_batch_step(dg_batch* b, const double* t_n, const double* dt, void* u, con
  * (the positivity-preserving p = 1 scheme of the paper's outlook, Sec. 4).
  * Phi_L and the solid fractions are not changed.  alpha: optional device
  * array (FP64, 6 x n_elem, species-major) that receives the factors, or
- * NULL.  Order 0: no-op.  Enqueued on `stream`; device workspace of
+ * NULL.  Order 0: no-op; order 3: DG_EUNSUPPORTED (Kuzmin's hierarchical
+ * form for degree above 1 is not implemented).  Enqueued on `stream`;
+ * device workspace of
  * 48 bytes per voxel, allocated on first use and kept (DG_WS_LIMITER on a
  * workspace context). */
 int dg_limit(dg_ctx* ctx, void* u, void* alpha, dg_stream stream);

@@ -151,6 +151,13 @@ agg_prolong_add_kernel(const S* __restrict__ sc, const double* __restrict__ y, A
 // (grid: row tiles of 256 x kCoarseChunks), pass 2 sums the chunks.
 constexpr int kCoarseChunks = 32;
 
+// X = identity (n x n, column-major), grid-stride.
+__global__ void __launch_bounds__(256) identity_kernel(double* __restrict__ X, int64_t n) {
+  const int64_t nn = n * n;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < nn; k += int64_t(gridDim.x) * 256)
+    X[k] = (k % n == k / n) ? 1.0 : 0.0;
+}
+
 __global__ void __launch_bounds__(256)
 coarse_gemv_partial_kernel(const double* __restrict__ A, int64_t nc, const double* __restrict__ x,
                            const double* __restrict__ d, int64_t chunk, double* __restrict__ part) {

@@ -26,6 +26,7 @@
 #include "pointwise.hpp"
 #include "resid_q1.hpp"
 #include "resid_q0.hpp"
+#include "resid_q3.hpp"
 #include "brick_q1.hpp"
 #include "blockjacobi.hpp"
 #include "solver.hpp"
@@ -59,6 +60,7 @@ struct dg_ctx {
   // aggregation coarse space: LU of the equilibrated coarse operator,
   // equilibration, pivots, a coarse vector, LAPACK status
   DevBuf cE, cd, crc, crc2, cipiv, cinfo, cpart;
+  DevBuf cX;                        // E^-1 (solve of the LU factors against the identity)
   // bfloat16 copy of FP32 block inverses (block_bf16), current while bh_valid
   DevBuf bh;
   bool bh_valid = false;
@@ -72,7 +74,7 @@ struct dg_ctx {
   bool owns_memory = true;
   template <typename F>
   void for_each_buf(F f) {
-    for (DevBuf* d : {&phase, &blocks, &lin, &cE, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
+    for (DevBuf* d : {&phase, &blocks, &lin, &cE, &cX, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
       f(*d);
     work.for_each(f);
   }
@@ -154,6 +156,7 @@ DevParams make_params(const dg_ctx* c, double t_eval, double dt) {
   P.nz = c->mesh.nz;
   P.Ne = c->Ne;
   P.np = c->np;
+  P.two_h = 2.0 / h;
   P.active = kAllFields;
   return P;
 }
@@ -217,6 +220,12 @@ void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void*
   if (ctx->np == 1) {                          // k = 0: one lane per voxel
     const int64_t nb = std::min<int64_t>((ctx->Ne + 255) / 256, 16384);
     hipLaunchKernelGGL((q0_kernel<S, N, Mode>), dim3(unsigned(nb)), dim3(256), 0, st, static_cast<const S*>(u),
+                       static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), ctx->d_phase, P);
+    return;
+  }
+  if (ctx->np == 64) {                         // k = 3: one wavefront per voxel, four per workgroup
+    const int64_t nb = std::min<int64_t>((ctx->Ne + 3) / 4, 65536);
+    hipLaunchKernelGGL((q3_kernel<S, N, Mode>), dim3(unsigned(nb)), dim3(256), 0, st, static_cast<const S*>(u),
                        static_cast<const S*>(v), static_cast<const S*>(m), static_cast<S*>(out), ctx->d_phase, P);
     return;
   }
@@ -368,7 +377,8 @@ AggGrid coarse_grid(const dg_mesh& mesh, const dg_solver_opts& o) {
 }
 
 std::vector<std::pair<DevBuf*, size_t>> coarse_buffers(dg_ctx* ctx, int64_t nc) {
-  return {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cd, size_t(nc) * 8),
+  return {std::make_pair(&ctx->cE, size_t(nc) * nc * 8), std::make_pair(&ctx->cX, size_t(nc) * nc * 8),
+          std::make_pair(&ctx->cd, size_t(nc) * 8),
           std::make_pair(&ctx->crc, size_t(nc) * 8), std::make_pair(&ctx->crc2, size_t(nc) * 8),
           std::make_pair(&ctx->cpart, size_t(kCoarseChunks) * nc * 8),
           std::make_pair(&ctx->cipiv, size_t(nc) * 4), std::make_pair(&ctx->cinfo, size_t(4))};
@@ -384,7 +394,8 @@ bool rocsolver_scratch_bytes(rocblas_handle h, int64_t nc, size_t& bytes) {
   bytes = 0;
   if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) return false;
   (void)rocsolver_dgetrf(h, rocblas_int(nc), rocblas_int(nc), A, rocblas_int(nc), ip, ip);
-  (void)rocsolver_dgetri(h, rocblas_int(nc), A, rocblas_int(nc), ip, ip);
+  (void)rocsolver_dgetrs(h, rocblas_operation_none, rocblas_int(nc), rocblas_int(nc), A, rocblas_int(nc), ip, A,
+                         rocblas_int(nc));
   return rocblas_stop_device_memory_size_query(h, &bytes) == rocblas_status_success;
 }
 
@@ -499,6 +510,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     }
   }
   double* cE = ctx->cE.as<double>();
+  double* cX = ctx->cX.as<double>();
   double* cd = ctx->cd.as<double>();
   double* crc = ctx->crc.as<double>();
   double* crc2 = ctx->crc2.as<double>();
@@ -531,7 +543,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
     const int64_t chunk = (nc + kCoarseChunks - 1) / kCoarseChunks;
     hipLaunchKernelGGL(coarse_gemv_partial_kernel, dim3(unsigned((nc + 255) / 256), kCoarseChunks, 1), blk, 0, st,
-                       cE, nc, crc, cd, chunk, cgemv);
+                       cX, nc, crc, cd, chunk, cgemv);
     hipLaunchKernelGGL(coarse_gemv_finish_kernel, grid1(nc), blk, 0, st, cgemv, nc, cd, crc2);
     if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
     hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(FS), blk, 0, st, scc, crc2, G, FS, out);
@@ -680,11 +692,12 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
       DG_HIP(hipStreamSynchronize(st));
       if (hinfo != 0) return fail(DG_ENAN, "dg_step: singular aggregation coarse operator");
-      if (rocsolver_dgetri(ctx->blas, rocblas_int(nc), cE, rocblas_int(nc), cipiv, cinfo) != rocblas_status_success)
-        return fail(DG_EHIP, "dg_step: rocsolver_dgetri failed");
-      DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
-      DG_HIP(hipStreamSynchronize(st));
-      if (hinfo != 0) return fail(DG_ENAN, "dg_step: singular aggregation coarse operator");
+      // E^-1 = the solve of the LU factors against the identity: level-3
+      // triangular solves (an in-place inverse runs on latency-bound panels)
+      hipLaunchKernelGGL(identity_kernel, dim3(8192), blk, 0, st, cX, nc);
+      if (rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), rocblas_int(nc), cE,
+                           rocblas_int(nc), cipiv, cX, rocblas_int(nc)) != rocblas_status_success)
+        return fail(DG_EHIP, "dg_step: rocsolver_dgetrs failed");
     }
     // coarse operator Ac[g][f] = sum_g sc_g (J Z_f)_g
     if (o.coarse == 1 || o.coarse == 2) {
@@ -944,6 +957,7 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
 // limit.
 int limit_state(dg_ctx* ctx, double* u, double* alpha, hipStream_t st) {
   if (ctx->np == 1) return DG_OK;
+  if (ctx->np != 8) return fail(DG_EUNSUPPORTED, "dg_limit: the vertex-based limiter is for orders 0 and 1");
   const size_t need = size_t(6) * ctx->Ne * sizeof(double);
   if (ctx->work.lmean.ensure(need) != hipSuccess) return fail_mem(ctx, "limiter workspace", need);
   const DevParams P = make_params(ctx, 0.0, 1.0);
@@ -1207,8 +1221,6 @@ int make_context(const dg_mesh* mesh, const uint8_t* phase, const dg_params* par
     return fail(DG_EINVAL, std::string(fn) + ": mesh sizes and h must be positive");
   if (mesh->order != 0 && mesh->order != 1 && mesh->order != 3)
     return fail(DG_EINVAL, std::string(fn) + ": order " + std::to_string(mesh->order) + " is not one of 0, 1, 3");
-  if (mesh->order == 3)
-    return fail(DG_EUNSUPPORTED, std::string(fn) + ": order 3 is not implemented (supported: 0, 1)");
   if (!(params->T > 0)) return fail(DG_EINVAL, std::string(fn) + ": temperature must be positive");
   const int64_t Ne = int64_t(mesh->nx) * mesh->ny * mesh->nz;
   int64_t n_struct = 0;
@@ -1302,7 +1314,7 @@ int dg_workspace_bytes(const dg_mesh* mesh, const dg_params* params, const dg_so
     if (int s = make_context(mesh, ones.data(), params, "dg_workspace_bytes", &c)) return s;
     if (c->mesh.order != 1 && (features & ~int32_t(DG_WS_OPERATORS))) {
       delete c;
-      return fail(DG_EUNSUPPORTED, "dg_workspace_bytes: order 0 provides the operators only (DG_WS_OPERATORS)");
+      return fail(DG_EUNSUPPORTED, "dg_workspace_bytes: orders 0 and 3 provide the operators only (DG_WS_OPERATORS)");
     }
     bool need_rs = false;
     int64_t nc = 0;
@@ -1341,7 +1353,7 @@ int dg_setup_ws(const dg_mesh* mesh, const uint8_t* phase, const dg_params* para
     if (int s = make_context(mesh, phase, params, "dg_setup_ws", &c)) return s;
     if (c->mesh.order != 1 && (features & ~int32_t(DG_WS_OPERATORS))) {
       delete c;
-      return fail(DG_EUNSUPPORTED, "dg_setup_ws: order 0 provides the operators only (DG_WS_OPERATORS)");
+      return fail(DG_EUNSUPPORTED, "dg_setup_ws: orders 0 and 3 provide the operators only (DG_WS_OPERATORS)");
     }
     double* scr = nullptr;
     if (int s = device_scratch(&scr)) {
@@ -1484,7 +1496,7 @@ int dg_jvp(dg_ctx* ctx, dg_prec prec, dg_jvp_mode mode, const void* u, const voi
     } else if (ctx->lin_prec != int(prec)) {
       return fail(DG_ESTATE, "dg_jvp: no linearisation of this precision (dg_linearize)");
     }
-    if (ctx->np == 1) {
+    if (ctx->np != 8) {
       if (prec == DG_F64)
         launch_q1<double, Dual<double>, kJvpCondensed>(ctx, P, u, v, ctx->lin.p, jv, st);
       else

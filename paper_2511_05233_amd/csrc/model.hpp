@@ -115,6 +115,7 @@ struct DevParams {
   // zero and inactive solid fractions stay frozen (kAllFields: all active).
   int32_t active;
   int32_t np;          // nodes per voxel, (k + 1)^3
+  double two_h;        // 2/h: d xi / dx
   int64_t Ne;
 };
 

@@ -129,19 +129,24 @@ def test_binding_constants_match_the_header_enums():
 
 
 def test_orders_and_workspace_sizes_are_checked_on_the_host(lib):
-    """Orders outside {0, 1, 3} are invalid and order 3 is not built; the
-    workspace of the operator entry points holds the phase map, the
-    status flag, the FP64 linearisation (14 values per node) and the output
-    partial sums, each 256-byte aligned."""
+    """Orders outside {0, 1, 3} are invalid, and orders 0 and 3 provide the
+    operators only; the workspace of the operator entry points holds the
+    phase map, the status flag, the FP64 linearisation (14 values per node)
+    and the output partial sums, each 256-byte aligned."""
     import ctypes as C
     p = lsbdg.default_params()
     ph = (C.c_uint8 * 8)(*([1] * 8))
     out = C.c_void_p()
-    for order, code in ((2, -1), (-1, -1), (3, -7)):
+    for order in (2, -1, 4):
         mesh = lsbdg.DgMesh(2, 2, 2, order, 1e-6)
-        assert lib.dg_setup(C.byref(mesh), ph, C.byref(p), C.byref(out)) == code, order
-    mesh = lsbdg.DgMesh(96, 96, 192, 1, 1e-6)
+        assert lib.dg_setup(C.byref(mesh), ph, C.byref(p), C.byref(out)) == -1, order
     n = C.c_size_t()
+    mesh3 = lsbdg.DgMesh(3, 2, 2, 3, 1e-6)
+    assert lib.dg_workspace_bytes(C.byref(mesh3), C.byref(p), None, lsbdg.DG_WS_STEP, C.byref(n)) == -7
+    assert lib.dg_workspace_bytes(C.byref(mesh3), C.byref(p), None, lsbdg.DG_WS_OPERATORS, C.byref(n)) == 0
+    al = lambda x: (x + 255) // 256 * 256
+    assert n.value == al(al(al(al(12) + 4) + 14 * 12 * 64 * 8) + 15 * 1024 * 8)
+    mesh = lsbdg.DgMesh(96, 96, 192, 1, 1e-6)
     assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, 64, C.byref(n)) == -1
     assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, lsbdg.DG_WS_OPERATORS, C.byref(n)) == 0
     al = lambda x: (x + 255) // 256 * 256

@@ -1,0 +1,85 @@
+"""The k = 3 operators on the GPU (tricubic, one wavefront per voxel, sum
+factorised on the Gauss nodes) against the oracle at k = 3: old mass,
+residual in FP64 and FP32, and the full, condensed and linearised tangents,
+element by element (GPU).  The oracle at k = 3 is pinned on the CPU by
+fourth-order manufactured rates (species, migration and charge rows) and
+its tangent by central differences.  Meshes of 60 and 84 voxels (15 and 21
+workgroups of four voxels, one of them ragged) with structure and pore
+voxels and the separator face.  Entry points beyond the operators refuse
+order 3."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dg as odg
+from tests.helpers import field_errors, problem_and_context
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL64, TOL32, TOLJ64, TOLJ32 = 1e-12, 2e-5, 1e-10, 1e-5
+
+
+def _case(shape, seed, **kw):
+    nx, ny, nz = shape
+    print(f"[q3] mesh {shape} seed {seed}", flush=True)
+    P, ctx, mask = problem_and_context(nx, ny, nz, k=3, mask_seed=seed, param_seed=seed, **kw)
+    u = synth.random_state(P.n_elem, 64, 710 + seed, phase=mask, phi_spread=5e-3)
+    uo = synth.random_state(P.n_elem, 64, 810 + seed, phase=mask)
+    return P, ctx, mask, u, uo
+
+
+@pytest.mark.parametrize("shape,seed", [((5, 4, 3), 0), ((7, 4, 3), 1)])
+def test_q3_residual_and_mass(shape, seed):
+    P, ctx, mask, u, uo = _case(shape, seed)
+    dev = torch.device("cuda:0")
+    m = ctx.mass(torch.tensor(uo, device=dev))
+    r = ctx.residual(torch.tensor(u, device=dev), m, 0.7, 0.05).cpu().numpy()
+    m_ref = odg.old_mass(P, uo)
+    assert np.all(field_errors(m.cpu().numpy(), m_ref) < 1e-15)
+    ref = odg.residual(P, u, m_ref, 0.7, 0.05)
+    err = field_errors(r, ref)
+    print("  residual errors", err, flush=True)
+    assert np.all(err < TOL64), err
+    r32 = ctx.residual(torch.tensor(u, device=dev, dtype=torch.float32), m.float(), 0.7, 0.05)
+    ref32 = odg.residual(P, u.astype(np.float32).astype(np.float64),
+                         m.float().double().cpu().numpy(), 0.7, 0.05)
+    err32 = field_errors(r32.double().cpu().numpy(), ref32)
+    print("  FP32 residual errors", err32, flush=True)
+    assert np.all(err32 < TOL32), err32
+
+
+@pytest.mark.parametrize("mode,dtype", [("full", "f64"), ("condensed", "f64"), ("linearized", "f64"),
+                                        ("linearized", "f32")])
+def test_q3_tangents(mode, dtype):
+    P, ctx, mask, u, _ = _case((5, 4, 3), 2)
+    nf = 9 if mode == "full" else 7
+    rng = np.random.default_rng(902)
+    scale = np.array([1500, 6, 6e-3, 4e-3, 2e-3, 4e-12, 3e-3, 0.2, 7e-6])[:nf]
+    v = scale[:, None, None] * rng.standard_normal((nf, P.n_elem, 64))
+    v[:, mask.reshape(-1) == 0, :] *= np.array([1] * 7 + [0, 0])[:nf, None, None]
+    S = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        u = u.astype(np.float32).astype(np.float64)
+        v = v.astype(np.float32).astype(np.float64)
+    dev = torch.device("cuda:0")
+    ut, vt = torch.tensor(u, device=dev, dtype=S), torch.tensor(v, device=dev, dtype=S)
+    if mode == "linearized":
+        ctx.linearize(ut, 0.9, 0.05)
+    jv = ctx.jvp(ut, vt, 0.9, 0.05, condensed=mode == "condensed", linearized=mode == "linearized")
+    m = odg.old_mass(P, u)
+    ref = odg.jvp(P, u, v, m, 0.9, 0.05) if mode == "full" else odg.jvp_condensed(P, u, v, m, 0.9, 0.05)
+    err = field_errors(jv.double().cpu().numpy(), ref)
+    print(f"  {mode} {dtype} tangent errors", err, flush=True)
+    assert np.all(err < (TOLJ64 if dtype == "f64" else TOLJ32)), err
+
+
+def test_q3_entry_points_beyond_the_operators_say_so():
+    from paper_2511_05233_amd import lsbdg
+    P, ctx, mask, u, _ = _case((3, 2, 2), 4)
+    ut = torch.tensor(u, device="cuda:0")
+    for call in (lambda: ctx.step(ut, 0.0, 0.1), lambda: ctx.outputs(ut, 0.0),
+                 lambda: ctx.blockjacobi_setup(ut, 0.1, 0.1), lambda: ctx.limit(ut)):
+        with pytest.raises(lsbdg.DgError) as ei:
+            call()
+        assert ei.value.code == -7
