@@ -149,7 +149,9 @@ class NewtonFailure(RuntimeError):
 _MAXLOG = np.log(10.0)
 
 
-def _apply_update(u, du, lam, fields):
+def _apply_update(u, du, lam, fields, two_sided=False):
+    """two_sided: the exponent is also capped from below at -ln 10 (no
+    unknown falls by more than a factor 10 in one iteration)."""
     out = u.copy()
     for fi, f in enumerate(fields):
         x = u[f]
@@ -158,7 +160,7 @@ def _apply_update(u, du, lam, fields):
             out[f] = x + d
             continue
         pos = x > 0
-        ex = np.clip(np.where(pos, d / np.where(pos, x, 1.0), 0.0), -np.inf, _MAXLOG)
+        ex = np.clip(np.where(pos, d / np.where(pos, x, 1.0), 0.0), -_MAXLOG if two_sided else -np.inf, _MAXLOG)
         out[f] = np.where(pos, x * np.exp(ex), x + d)
     return out
 
@@ -275,7 +277,7 @@ class _SparseSolver:
 
 
 def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
-           gmres_rtol=1e-13, restart=120, log=None, linear=None):
+           gmres_rtol=1e-13, restart=120, log=None, linear=None, two_sided=False):
     """Damped Newton on the rows/columns ``fields``; other fields frozen.
 
     Each iteration solves J du = -R, either directly (sparse LU of the
@@ -285,7 +287,9 @@ def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
     magnitudes), applies the update above and backtracks on the merit.
     Converged when a full step's largest relative update is below ``tol``.
     linear="sparse": GMRES on the probed sparse Jacobian (see _SparseSolver),
-    re-probed when a full step fails to halve the update.
+    re-probed when a full step fails to halve the update.  two_sided: the
+    multiplicative update is capped at a factor 10 both ways (the default
+    caps growth only); the path differs, the root does not.
     Returns (u, info) with info = dict(iterations, gmres, update).
     """
     fields = list(fields)
@@ -338,7 +342,7 @@ def newton(P, u0, m_old, t_new, dt, fields=tuple(range(9)), tol=1e-12, maxit=80,
         upd = float(np.max(np.abs(du) / S))
         lam = 1.0
         for _ in range(40):
-            ut = _apply_update(u, du, lam, fields)
+            ut = _apply_update(u, du, lam, fields, two_sided)
             Rt = dg.residual(P, ut, m_old, t_new, dt)
             mt = merit_of(Rt) if np.all(np.isfinite(Rt)) else np.inf
             if mt < merit or (lam == 1.0 and upd < 1e-8):

@@ -5,7 +5,8 @@ and kinetics of parameter seed 0, 0.1C current on the separator face; the
 steady initial potential (Sec. 2.10, solved directly) and then five steps of
 dt = 0.1 s (the paper's implicit-Euler step of the time-stepping study,
 Sec. 3.3), each solved by the oracle's Newton iteration to a relative update
-below 1e-12 (its linear systems by GMRES on the probed sparse Jacobian).
+below 1e-12 (its linear systems by GMRES on the probed sparse Jacobian,
+its multiplicative update capped at a factor 10 both ways).
 Every value is computed by the CPU oracle alone (``oracle/``); nothing here
 touches the HIP library.
 
@@ -54,7 +55,7 @@ def main():
     t = 0.0
     for s in range(STEPS):
         t1 = time.time()
-        u, info = osolve.be_step(P, u, t, DT, linear="sparse", gmres_rtol=1e-8, restart=60,
+        u, info = osolve.be_step(P, u, t, DT, linear="sparse", gmres_rtol=1e-8, restart=60, two_sided=True, maxit=150,
                                  log=lambda m: print(f"[step {s + 1}]", m, flush=True))
         t += DT
         states.append(u)
