@@ -227,12 +227,14 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     ms_lin = time_launches(lambda: ctx.linearize(uS, t, dt), stream, 5)
     ms_jvp = time_launches(lambda: ctx.jvp(uS, v7, t, dt, out=y7, linearized=True), stream, reps)
     ms_res = time_launches(lambda: ctx.residual(u, m8, t, dt, out=r9), stream, reps)
-    ctx.blockjacobi_setup(uS, t, dt)
-    ms_apply = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7), stream, reps)
-    ms_apply_h = None
-    if S == torch.float32:
-        ms_apply_h = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7, bf16=True), stream, reps)
-    ms_setup = time_launches(lambda: ctx.blockjacobi_setup(uS, t, dt), stream, 3)
+    q1 = ctx.n_nodes == 8                                   # the block preconditioner is Q1's
+    if q1:
+        ctx.blockjacobi_setup(uS, t, dt)
+        ms_apply = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7), stream, reps)
+        ms_apply_h = None
+        if S == torch.float32:
+            ms_apply_h = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7, bf16=True), stream, reps)
+        ms_setup = time_launches(lambda: ctx.blockjacobi_setup(uS, t, dt), stream, 3)
 
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9
@@ -250,11 +252,12 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
         "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp,
                           "linearisation_bytes_not_counted": b_lin},
         "residual_f64": {"ms": ms_res, "GB/s": gbs(b_res, ms_res), "bytes": b_res},
-        "block_apply": {"ms": ms_apply, "GB/s": gbs(b_apply, ms_apply), "bytes": b_apply},
-        "block_setup": {"ms": ms_setup},
         "linearize": {"ms": ms_lin},
     }
-    if ms_apply_h is not None:
+    if q1:
+        kernels["block_apply"] = {"ms": ms_apply, "GB/s": gbs(b_apply, ms_apply), "bytes": b_apply}
+        kernels["block_setup"] = {"ms": ms_setup}
+    if q1 and ms_apply_h is not None:
         kernels["block_apply_bf16"] = {"ms": ms_apply_h, "GB/s": gbs(b_apply_h, ms_apply_h), "bytes": b_apply_h}
     for k in kernels.values():
         if "GB/s" in k:
@@ -362,11 +365,12 @@ def mixed_vs_f64(coarse, log, steps=5, dt=0.1):
 
 
 def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9, max_steps=5000, limiter=0,
-              max_wall=None):
+              max_wall=None, t_stop=None):
     """Full galvanostatic discharge under the naive controller (Sec. 2.8):
     from the initial state until U_cell <= cutoff or t >= 3600 / f_C
     (limiter = 1: every step's root limited, dg_limit; max_wall: stop after
-    that many seconds, reported as ended_by "wall")."""
+    that many seconds, reported as ended_by "wall"; t_stop: stop once the
+    simulated time reaches it, ended_by "t_stop")."""
     import torch
     import synth
     from paper_2511_05233_amd import lsbdg
@@ -380,18 +384,20 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
     t, t_end = 0.0, 3600.0 / f_C
     tot = {"steps": 0, "trials": 0, "halvings": 0, "newton_its": 0, "gmres_its": 0}
     U = ctx.outputs(u, t)["U_cell"]
-    curve = [(0.0, U)]
+    curve = [(0.0, U, time.perf_counter() - w0)]
     while t < t_end and U > cutoff and tot["steps"] < max_steps:
         if max_wall is not None and time.perf_counter() - w0 > max_wall:
+            break
+        if t_stop is not None and t >= t_stop:
             break
         t, rep = ctx.advance(ctrl, t, u, inner=inner, coarse=coarse, coarse_agg=coarse_agg, limiter=limiter)
         for k in ("trials", "halvings", "newton_its", "gmres_its"):
             tot[k] += rep[k]
         tot["steps"] += 1
         U = ctx.outputs(u, t)["U_cell"]
-        curve.append((t, U))
+        curve.append((t, U, time.perf_counter() - w0))
         log(f"[discharge] step {tot['steps']}: t = {t:.4g} s, dt = {rep['dt']:.3g} s, U_cell = {U:.5f} V, "
-            f"{rep['newton_its']} Newton, {rep['gmres_its']} GMRES")
+            f"{rep['newton_its']} Newton, {rep['gmres_its']} GMRES, wall {curve[-1][2]:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     soc = 1.0 - t / t_end
@@ -399,8 +405,9 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
             "U_end_V": round(U, 5), "soc_end": round(soc, 4), **tot,
             "limiter": limiter,
             "ended_by": "cutoff" if U <= cutoff else ("time" if t >= t_end else
-                                                      ("step limit" if tot["steps"] >= max_steps else "wall")),
-            "curve_tU": [(round(a, 3), round(b, 6)) for a, b in curve[:: max(1, len(curve) // 40)]],
+                                                      ("t_stop" if t_stop is not None and t >= t_stop else
+                                                       ("step limit" if tot["steps"] >= max_steps else "wall"))),
+            "curve_tU": [(round(a, 3), round(b, 6)) for a, b, _ in curve[:: max(1, len(curve) // 40)]],
             "_curve": curve}
 
 
@@ -412,8 +419,8 @@ def discharge_mixed_vs_f64(workload, f_C, coarse, coarse_agg, log):
     for inner in ("f64", "f32"):
         runs[inner] = discharge(workload, f_C, inner, coarse, coarse_agg, log)
         log(f"[bench] discharge {workload} {inner}: {runs[inner]['s_per_discharge']} s")
-    c64 = np.array(runs["f64"]["_curve"])
-    c32 = np.array(runs["f32"]["_curve"])
+    c64 = np.array(runs["f64"]["_curve"])[:, :2]
+    c32 = np.array(runs["f32"]["_curve"])[:, :2]
     t_hi = min(c64[-1, 0], c32[-1, 0])
     sel = c64[:, 0] <= t_hi
     dU = np.abs(np.interp(c64[sel, 0], c32[:, 0], c32[:, 1]) - c64[sel, 1])
@@ -656,6 +663,7 @@ def main(argv=None):
     ap.add_argument("--discharge-rate", type=float, default=1.0, help="C-rate of --discharge")
     ap.add_argument("--limiter", action="store_true", help="--discharge: limit every step's root (dg_limit)")
     ap.add_argument("--max-wall", type=float, default=None, help="--discharge: stop after this many seconds")
+    ap.add_argument("--t-stop", type=float, default=None, help="--discharge: stop at this simulated time [s]")
     ap.add_argument("--batch", action="store_true",
                     help="the 64-structure batch workload in full (operators, block preconditioner, "
                          "side-by-side solves) and print that record only")
@@ -691,8 +699,8 @@ def main(argv=None):
         return 0
     if args.discharge:
         out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log,
-                        limiter=int(args.limiter), max_wall=args.max_wall)
-        out.pop("_curve")
+                        limiter=int(args.limiter), max_wall=args.max_wall, t_stop=args.t_stop)
+        out["curve_tUw"] = [(round(a, 4), round(b, 7), round(c, 2)) for a, b, c in out.pop("_curve")]
         print(json.dumps(out), flush=True)
         return 0
     w = synth.WORKLOADS[args.workload]
