@@ -153,6 +153,28 @@ def recorded_traffic(workload, kernel):
     return None
 
 
+def recorded_valu(workload, kernel):
+    """Vector-ALU instructions per launch of `kernel` (rocprofv3 SQ_INSTS_VALU,
+    summed over its wavefronts) from the committed counter summary, or None
+    when absent or taken on other kernel sources."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    want = source_hash()
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"\s*valu\s+(\S+)\s+insts_per_launch=(\d+)\s+waves_per_launch=(\d+)\s+source=(\w+)", line)
+            if m and m.group(1) == kernel and m.group(4) == want:
+                return int(m.group(2)), int(m.group(3))
+    return None
+
+
+# One wave64 vector-ALU instruction occupies a SIMD for 4 cycles; MI355X has
+# 256 compute units of 4 SIMDs at 2.4 GHz.
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+
+
 def copy_probe(dev):
     """Three STREAM triads (dg_triad) over 1 GiB arrays: 2 GiB read and
     1 GiB written per launch (reference for the HBM byte counters)."""
@@ -179,6 +201,19 @@ def triad_bandwidth(dev, stream, reps=10):
     ok = bool(torch.all(c == 1.5))
     del a, b, c
     return {"GB/s": round(24 * (1 << 27) / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4), "checked": ok}
+
+
+def valu_view(workload, kernel, ms):
+    """The kernel against the vector-ALU issue rate: recorded instructions
+    per launch, the time they need at full issue, and that time over the
+    measured one (None without a current counter summary)."""
+    rec = recorded_valu(workload, kernel)
+    if rec is None:
+        return None
+    insts, waves = rec
+    t_issue = insts / VALU_ISSUE_PER_S * 1e3
+    return {"insts_per_launch": insts, "waves_per_launch": waves, "insts_per_wave": round(insts / waves, 1),
+            "ms_at_full_issue": round(t_issue, 4), "frac_of_issue": round(t_issue / ms, 4)}
 
 
 def time_launches(fn, stream, reps):
@@ -809,7 +844,8 @@ def main(argv=None):
                      "bytes_per_dof": round(b_op / n_dof, 2),
                      "achievable_triad": triad,
                      "frac_of_triad": round(achieved / triad["GB/s"], 4),
-                     "residual_f64": {k: kernels["residual_f64"][k] for k in ("ms", "GB/s", "frac", "bytes")}},
+                     "residual_f64": {k: kernels["residual_f64"][k] for k in ("ms", "GB/s", "frac", "bytes")},
+                     "valu": valu_view(w.name, k_op, ms_op)},
         "kernels": kernels,
     }
     if args.compare_f64 and args.inner == "f32":
