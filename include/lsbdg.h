@@ -420,7 +420,9 @@ typedef struct {
  * lim < 0.9; on acceptance u = 2 z_F - z_C and the next dt is
  * min(lim dt, dt_max).  A failed solve inside a trial halves dt.
  * Non-convergence and non-finite residuals count as failed solves; after
- * more than max_halvings in one call: DG_ENOCONV with u and *t unchanged.
+ * more than max_halvings in one call, or (H211b) more than 100 trials
+ * rejected by their error (an error estimate whose floor lies above tol):
+ * DG_ENOCONV with u and *t unchanged (c->dt keeps the last trial size).
  * Device workspace: up to three extra FP64 states, kept.  Synchronises the
  * stream. */
 int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u, const dg_solver_opts* opts,

@@ -79,8 +79,9 @@ def h211b_limiter(err, err_prev, dt, dt_prev, tol):
 
 
 class H211b:
-    def __init__(self, dt0, tol, dt_max=100.0, max_halvings=30, err_floor=1e-300):
+    def __init__(self, dt0, tol, dt_max=100.0, max_halvings=30, err_floor=1e-300, max_rejections=100):
         self.dt = dt0
+        self.max_rejections = max_rejections
         self.tol = tol
         self.dt_max = dt_max
         self.max_halvings = max_halvings
@@ -94,6 +95,7 @@ class H211b:
         lim = 0.0
         err = math.inf
         halvings = 0
+        rejections = 0
         while lim < 0.9 or err > 1.02 * self.tol:
             dt = self.dt
             self.trials += 1
@@ -112,6 +114,11 @@ class H211b:
             lim = h211b_limiter(err, self.err_prev, dt, self.dt_prev, self.tol)
             if lim < 0.9 or err > 1.02 * self.tol:
                 self.dt = min(lim, 0.9) * dt
+                # an error estimate with a floor above tol (the solver's
+                # attainable accuracy) would otherwise shrink dt forever
+                rejections += 1
+                if rejections > self.max_rejections:
+                    raise ControllerAbort("more than %d trials rejected by their error" % self.max_rejections)
         z_new = 2.0 * zF - zC
         self.err_prev = err
         self.dt_prev = dt

@@ -1782,6 +1782,15 @@ void dg_controller_init(dg_controller* c, int32_t kind, double dt0, double tol) 
   c->dt_prev = dt0;
 }
 
+}  // extern "C"
+
+namespace {
+// H211b trials rejected by their error in one dg_advance call before DG_ENOCONV.
+constexpr int kMaxH211bRejections = 100;
+}  // namespace
+
+extern "C" {
+
 int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solver_opts* opts,
                dg_advance_report* report, dg_stream stream) {
   try {
@@ -1848,6 +1857,7 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
       double* zC = W.zC.as<double>();
       double* zF = W.zF.as<double>();
       double lim = 0.0, err = HUGE_VAL, dt = c->dt;
+      int rejections = 0;
       constexpr int nb = 1024;
       if (W.out_partial.ensure(size_t(kNumSums) * nb * sizeof(double)) != hipSuccess)
         return fail_mem(ctx, "dg_advance workspace", size_t(kNumSums) * nb * sizeof(double));
@@ -1891,7 +1901,16 @@ int dg_advance(dg_ctx* ctx, dg_controller* c, double* t, void* u_, const dg_solv
         const double rho = std::pow(c->tol / err, 0.25) * std::pow(c->tol / c->err_prev, 0.25) *
                            std::pow(dt / c->dt_prev, -0.25);
         lim = 1.0 + std::atan(rho - 1.0);
-        if (lim < 0.9 || err > 1.02 * c->tol) c->dt = std::min(lim, 0.9) * dt;
+        if (lim < 0.9 || err > 1.02 * c->tol) {
+          c->dt = std::min(lim, 0.9) * dt;
+          // an error estimate with a floor above the tolerance (the inner
+          // solve's attainable accuracy) would otherwise shrink dt forever
+          if (++rejections > kMaxH211bRejections) {
+            if (report) *report = r;
+            return fail(DG_ENOCONV, "dg_advance: H211b rejected more than " +
+                                        std::to_string(kMaxH211bRejections) + " trials by their error");
+          }
+        }
       }
       hipLaunchKernelGGL(richardson_kernel, grid1(n9), dim3(256), 0, st, zF, zC, u, n9);
       DG_HIP(hipGetLastError());

@@ -132,6 +132,27 @@ def test_h211b_meets_tolerance_and_richardson_is_second_order():
     assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4
 
 
+def test_h211b_gives_up_on_an_error_floor_above_tol():
+    """A solver whose steps carry an error floor (here 1e-7 relative, as an
+    inner solve stalled at its attainable accuracy) cannot meet tol = 1e-9
+    at any dt: the controller stops after 100 error rejections instead of
+    shrinking dt forever."""
+    lam = -2.0
+    calls = [0]
+
+    def step(z, t, dt):
+        calls[0] += 1
+        # backward Euler plus a deterministic 1e-7 perturbation that differs
+        # between the coarse and the fine solves (an error floor)
+        return z / (1.0 - lam * dt) * (1.0 + 1e-7 * (-1) ** calls[0])
+
+    ctl = C.H211b(0.01, 1e-9, dt_max=1.0)
+    with pytest.raises(C.ControllerAbort):
+        ctl.advance(step, 1.0, 0.0)
+    assert ctl.trials == 101
+    assert ctl.dt < 0.01 * 0.9 ** 100 * 1.0001
+
+
 def test_h211b_limiter_formula():
     """Eq. 51-52 with equal history: rho = (tol/err)^(1/2) and lim = 1 + atan(rho - 1)."""
     lim = C.h211b_limiter(1e-6, 1e-6, 1.0, 1.0, 4e-6)
