@@ -16,7 +16,9 @@
  * are the Tradeoff Chemistry of Tab. 3 with Butler-Volmer kinetics
  * (Eq. 05-06, 18-24).  Space: interior-penalty DG with harmonic-mean
  * coefficients (Eq. 43-47) on tensor-product Gauss-Legendre nodes of degree
- * k = 1 per axis (Q1, 8 nodes per voxel); time: backward Euler (Eq. 50).  The separator face
+ * k per axis: k = 1 (Q1, 8 nodes per voxel) for every entry point, k = 0
+ * (Eq. 48) and k = 3 (64 nodes) for the operators; time: backward Euler
+ * (Eq. 50).  The separator face
  * x = L_x receives the Li+ flux j_el/F and the ionic current j_el; all other
  * faces are no-flux (Eq. 47 with the paper's galvanostatic condition).
  *
@@ -149,8 +151,10 @@ int dg_residual(dg_ctx* ctx, dg_prec prec, const void* u, const void* m_old,
                 double t_new, double dt, void* r, dg_stream stream);
 
 /* Jacobian-vector product of dg_residual at (u, t_new, dt) in direction v:
- * the exact derivative of the same arithmetic (forward-mode dual numbers),
- * with zero derivative where a clamp is active.  The old mass does not
+ * the exact derivative of the same arithmetic (forward-mode dual numbers;
+ * the Q1 product at a stored linearisation, DG_JVP_LINEARIZED7, has its
+ * tangents written out by hand), with zero derivative where a clamp is
+ * active.  The old mass does not
  * enter.  u: device, 9 fields; v and jv: device, 9 fields (DG_JVP_FULL9) or
  * 7 fields (condensed modes); all in the precision prec.  DG_ESTATE:
  * DG_JVP_LINEARIZED7 without a linearisation of that precision. */
@@ -320,7 +324,8 @@ typedef struct {
  * correction (opts.coarse), in the inner precision of opts (NULL:
  * defaults).  The operator and the element blocks are rebuilt at every
  * Newton iterate, the aggregation coarse operator every opts.coarse_every
- * iterates.  Device workspace is allocated on first use and kept.
+ * iterates.  Device workspace is allocated on first use and kept (a
+ * context of dg_setup_ws takes it from the caller's workspace).
  * Converged when a full step changes no unknown by more than newton_tol,
  * or, once an update below 1e-7 has been reached (the attainable accuracy
  * of the iterative solve; report.stalled = 1), when three full steps in a
