@@ -467,7 +467,7 @@ def discharge_mixed_vs_f64(workload, f_C, coarse, coarse_agg, log):
             "f64": strip(runs["f64"]), "mixed": strip(runs["f32"])}
 
 
-def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
+def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True, solves=False):
     """Batching on the batch workload: n cubic structures with
     edges ~ U{24..64} voxels and porosities ~ U(0.4, 0.75) (seeded), each
     with its own kinetics draw.  Every operator runs as one launch over all
@@ -582,7 +582,7 @@ def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
     torch.cuda.empty_cache()
     del u64
     torch.cuda.empty_cache()
-    solve = batch_solves(structs, dof, log) if full else None
+    solve = batch_solves(structs, dof, log) if (full or solves) else None
     res = {
         "workload": f"{n} cubic structures, edges U{{24..64}} voxels, porosity U(0.4, 0.75), DG-Q1, "
                     f"{E} voxels, {dof} DoF, {B.n_tiles} work items of 32 voxels",
@@ -604,7 +604,7 @@ def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True):
         "implicit_step": solve,
     }
     if not full:
-        for k in ("block_setup_f32_ms", "block_apply_f32", "implicit_step"):
+        for k in ("block_setup_f32_ms", "block_apply_f32") + (() if solves else ("implicit_step",)):
             res.pop(k)
     log(f"[bench] batch: JVP {ms_jvp_b:.3f} ms batched, {ms_jvp_s:.3f} ms per structure, "
         f"{ms_jvp_g:.3f} ms per structure from a graph")
@@ -873,7 +873,7 @@ def main(argv=None):
     if not args.no_batch:
         ctx.close()
         torch.cuda.empty_cache()
-        out["batch_operators"] = batch_throughput(dev, log, full=False)
+        out["batch_operators"] = batch_throughput(dev, log, full=False, solves=True)
     if args.copy_probe:
         out["copy_probe_bytes"] = copy_probe(dev)
     if not args.no_cpu_baseline:
