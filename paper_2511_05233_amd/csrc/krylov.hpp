@@ -150,9 +150,9 @@ multi_axpy_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restr
 
 // One sweep of classical Gram-Schmidt applied twice: w -= sum_i h[i] V_i
 // (the first pass's update), then partial sums of V_i . w for the updated w
-// (the second pass's projections).  Each thread re-reads its quads of the
-// basis right after using them, from cache, so the basis streams from HBM
-// once for both; the arithmetic per entry is that of multi_axpy_kernel and
+// (the second pass's projections).  Each thread holds its quads of the
+// basis in registers between the two, so the basis streams from HBM once
+// for both; the arithmetic per entry is that of multi_axpy_kernel and
 // multi_dot_kernel.  Launch with the grid of multi_dot_kernel.
 template <typename S>
 __global__ void __launch_bounds__(256)
@@ -165,15 +165,20 @@ multi_axpy_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __r
   for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
   const int64_t n4 = n >> 2;
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    Q vq[kMaxDots];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) vq[i] = reinterpret_cast<const Q*>(V + i * ldv)[k];
     Q s{S(0), S(0), S(0), S(0)};
-    for (int i = 0; i < nv; ++i) {
-      const S hi = h[i];
-      const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
-      s.a += hi * v.a;
-      s.b += hi * v.b;
-      s.c += hi * v.c;
-      s.d += hi * v.d;
-    }
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) {
+        const S hi = h[i];
+        s.a += hi * vq[i].a;
+        s.b += hi * vq[i].b;
+        s.c += hi * vq[i].c;
+        s.d += hi * vq[i].d;
+      }
     Q wk = reinterpret_cast<Q*>(w)[k];
     wk.a += S(-1) * s.a;
     wk.b += S(-1) * s.b;
@@ -182,10 +187,7 @@ multi_axpy_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __r
     reinterpret_cast<Q*>(w)[k] = wk;
 #pragma unroll
     for (int i = 0; i < kMaxDots; ++i)
-      if (i < nv) {
-        const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
-        acc[i] += v.a * wk.a + v.b * wk.b + v.c * wk.c + v.d * wk.d;
-      }
+      if (i < nv) acc[i] += vq[i].a * wk.a + vq[i].b * wk.b + vq[i].c * wk.c + vq[i].d * wk.d;
   }
   store_block_sums(acc, nv, sh, partial);
 }
