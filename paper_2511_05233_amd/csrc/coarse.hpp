@@ -133,14 +133,19 @@ agg_restrict_kernel(const S* __restrict__ sc, const S* __restrict__ r, AggGrid G
 
 // Prolongation out += Z y: out[g][node] += sc[g][node] y[g * na + agg(node)];
 // one thread per node finds its aggregate once for the seven fields.
+// div (optional): the sum is then divided entrywise by div (the unknown
+// scales of the Krylov system), in the same pass.
 template <typename S>
 __global__ void __launch_bounds__(256)
 agg_prolong_add_kernel(const S* __restrict__ sc, const double* __restrict__ y, AggGrid G, int64_t FS,
-                       S* __restrict__ out) {
+                       S* __restrict__ out, const S* __restrict__ div) {
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
     const int64_t a = agg_of_voxel(G, k >> 3);
 #pragma unroll
-    for (int g = 0; g < 7; ++g) out[g * FS + k] += sc[g * FS + k] * S(y[int64_t(g) * G.na + a]);
+    for (int g = 0; g < 7; ++g) {
+      const S v = out[g * FS + k] + sc[g * FS + k] * S(y[int64_t(g) * G.na + a]);
+      out[g * FS + k] = div ? v / div[g * FS + k] : v;
+    }
   }
 }
 

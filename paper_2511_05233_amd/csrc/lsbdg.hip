@@ -539,16 +539,19 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // out = Z E^-1 Z^T r (aggregation coarse space): E^-1 = D Einv D with the
   // explicit inverse Einv of the equilibrated operator, applied as one dense
   // GEMV (triangular solves with the LU factors run far below HBM speed)
-  auto coarse_solve_into = [&](const S* r, S* out, bool add) {
+  auto coarse_solve_into = [&](const S* r, S* out, bool add, const S* div = nullptr) {
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
     const int64_t chunk = (nc + kCoarseChunks - 1) / kCoarseChunks;
     hipLaunchKernelGGL(coarse_gemv_partial_kernel, dim3(unsigned((nc + 255) / 256), kCoarseChunks, 1), blk, 0, st,
                        cX, nc, crc, cd, chunk, cgemv);
     hipLaunchKernelGGL(coarse_gemv_finish_kernel, grid1(nc), blk, 0, st, cgemv, nc, cd, crc2);
     if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
-    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(FS), blk, 0, st, scc, crc2, G, FS, out);
+    hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(FS), blk, 0, st, scc, crc2, G, FS, out, div);
   };
+  // out = M^-1 r, divided entrywise by the unknown scales sc (fused into the
+  // coarse prolongation when the coarse space is additive on aggregates)
   auto precond = [&](S* r, S* out) {
+    auto unscale = [&]() { hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, out, out, n7); };
     if (o.coarse == 4) {
       // multiplicative two-level: coarse solve, then the element blocks on
       // the remaining residual: out = c + B^-1 (r - J c), c = Z E^-1 Z^T r
@@ -567,6 +570,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
                            out, ctx->Ne);
       }
       hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), pc, S(1), out, n7);
+      unscale();
       return;
     }
     deflate(r);
@@ -584,15 +588,17 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     if (o.coarse == 1) {
       coarse_coeffs(r);
       hipLaunchKernelGGL(coarse_add_kernel<S>, grid1(n7), blk, 0, st, sc, yc, out, FS);
+      unscale();
     } else if (o.coarse == 3) {
-      coarse_solve_into(r, out, true);      // additive: out += Z E^-1 Z^T r
+      coarse_solve_into(r, out, true, sc);  // additive: out += Z E^-1 Z^T r, then / sc
+    } else {
+      unscale();
     }
   };
   auto opA = [&](const S* v, S* out) {           // out = sc^-1 M^-1 J (sc v)
     hipLaunchKernelGGL((emul_kernel<S, false>), grid1(n7), blk, 0, st, sc, v, t, n7);
     jvp_cond(t, pJ);
     precond(pJ, out);
-    hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, out, out, n7);
   };
   // out <- the sum of the FP64 block partials in partial64
   auto finish_sumsq = [&](double& out) -> int {
@@ -627,7 +633,6 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       DG_HIP(hipStreamSynchronize(st));
       for (int f = 0; f < 7; ++f) cpart += double(hy[f]) * double(hy[f]);
     }
-    hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, pJ, pJ, n7);
     double a = 0.0;
     if (int s = sumsq(pJ, n7, a)) return s;
     hipLaunchKernelGGL(solid_merit_kernel, gred, blk, 0, st, Rv, u, FS, P, partial64);
@@ -742,7 +747,6 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipLaunchKernelGGL(condensed_rhs_kernel<S>, grid1(n7), blk, 0, st, R, rs, y9, rhs, FS, active);
     hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), rhs, S(0), w, n7);
     precond(w, b);
-    hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, b, b, n7);
     double merit0 = 0.0;
     if (int s = merit(R, merit0)) return s;
     if (!std::isfinite(merit0)) return fail(DG_ENAN, "dg_step: non-finite residual");
