@@ -23,7 +23,24 @@ def test_recorded_traffic_is_tied_to_the_kernel_sources():
         got = bench.recorded_traffic("slab96_q1", kernel)
         assert got == (nbytes if src == bench.source_hash() else None), kernel
     assert bench.recorded_traffic("slab96_q1", "no_such_kernel") is None
-    assert bench.recorded_traffic("no_such_workload", "apply_blocks_kernel") is None
+    assert bench.recorded_traffic("no_such_workload", "apply_blocks_kernel<float,7>") is None
+
+
+def test_recorded_valu_is_tied_to_the_kernel_sources():
+    """The committed VALU counter summary likewise: instructions and
+    wavefronts per launch while the source hash matches, else nothing; the
+    bench's view derives the full-issue time from them."""
+    path = os.path.join(bench.ROOT, "profiles", "valu_slab96_q1.txt")
+    lines = [ln for ln in open(path) if ln.strip().startswith("valu ")]
+    assert lines, "no machine-readable VALU lines"
+    for ln in lines:
+        _, kernel, ins, waves, src = ln.split()
+        want = (int(ins.split("=")[1]), int(waves.split("=")[1]))
+        got = bench.recorded_valu("slab96_q1", kernel)
+        assert got == (want if src.split("=")[1] == bench.source_hash() else None), kernel
+        if got is not None:
+            view = bench.valu_view("slab96_q1", kernel, 1.0)
+            assert abs(view["ms_at_full_issue"] - want[0] / (256 * 4 * 2.4e9 / 4) * 1e3) < 1e-3
 
 
 def _profiles_current():
@@ -36,7 +53,9 @@ def test_committed_profiles_agree_with_each_other():
     the current ones the benchmark's roofline carries measured traffic."""
     if not _profiles_current():
         pytest.skip("profiles taken on other kernel sources")
-    assert bench.recorded_traffic("slab96_q1", "apply_blocks_bf16_kernel") is not None
+    assert bench.recorded_traffic("slab96_q1", "apply_blocks_bf16_kernel<7>") is not None
+    assert bench.recorded_traffic("slab96_q1", bench.JVP_KERNEL["f32"]) is not None
+    assert bench.recorded_valu("slab96_q1", bench.JVP_KERNEL["f32"]) is not None
 
 
 def test_recorded_bytes_match_the_algorithmic_bytes_of_the_block_apply():
@@ -46,8 +65,8 @@ def test_recorded_bytes_match_the_algorithmic_bytes_of_the_block_apply():
         pytest.skip("profiles taken on other kernel sources")
     w = synth.WORKLOADS["slab96_q1"]
     ne = w.nx * w.ny * w.nz
-    alg = {"apply_blocks_kernel": ne * (56 * 56 + 2 * 56) * 4,
-           "apply_blocks_bf16_kernel": ne * (56 * 56 * 2 + 2 * 56 * 4)}
+    alg = {"apply_blocks_kernel<float,7>": ne * (56 * 56 + 2 * 56) * 4,
+           "apply_blocks_bf16_kernel<7>": ne * (56 * 56 * 2 + 2 * 56 * 4)}
     for kernel, nbytes in alg.items():
         got = bench.recorded_traffic("slab96_q1", kernel)
         assert got is not None and abs(got / nbytes - 1.0) < 1e-3, (kernel, got, nbytes)
