@@ -655,6 +655,74 @@ def batch_solves(structs, dof, log, dt=0.1, iters=2):
             "side_by_side_equals_sequential": bool(same)}
 
 
+def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64"):
+    """The time-stepping comparison of Sec. 3.3 on a one-dimensional
+    homogenised cathode: nx voxels of 1 um, every voxel structure (the
+    porous cathode of Tab. 5 through Eq. 57), the paper's parameters, the
+    current on the separator face.  Strategies: backward Euler with a fixed
+    dt = 0.1 s (halving only on a failed solve), the naive controller, and
+    H211b at tol = 1e-8 and 1e-5; each from the initial state to the 1.9 V
+    cutoff, the end of the nominal discharge or max_wall seconds.  Reports
+    wall time, step, Newton and GMRES counts, the device workspace each
+    strategy needs (dg_workspace_bytes: one or three saved states), and the
+    largest cell-voltage difference to the naive run at common times."""
+    import torch
+    from paper_2511_05233_amd import lsbdg
+    mask = np.ones((1, 1, nx), np.uint8)
+    kinds = [("backward_euler_dt0.1", "naive", None), ("naive", "naive", None),
+             ("h211b_tol1e-8", "h211b", 1e-8), ("h211b_tol1e-5", "h211b", 1e-5)]
+    out = {"workload": f"{nx}x1x1 voxels of 1 um, all structure (homogenised), DG-Q1, paper parameters, "
+                       f"{f_C}C, inner {inner}", "strategies": {}}
+    curves = {}
+    t_end = 3600.0 / f_C
+    for name, kind, tol in kinds:
+        ctx = lsbdg.Context(nx, 1, 1, 1e-6, 1, mask, f_C=f_C)
+        feats = lsbdg.DG_WS_STEP | (lsbdg.DG_WS_H211B if kind == "h211b" else lsbdg.DG_WS_NAIVE)
+        ws = lsbdg.workspace_bytes(nx, 1, 1, 1e-6, 1, feats, inner=inner)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        u, _ = ctx.initial_state(inner=inner)
+        c = lsbdg.controller(kind, dt0=0.1, tol=tol if tol else 1e-5)
+        if name.startswith("backward_euler"):
+            c.successes = 2 ** 30                 # dt never grows
+        t, U = 0.0, ctx.outputs(u, 0.0)["U_cell"]
+        tot = {"steps": 0, "trials": 0, "halvings": 0, "newton_its": 0, "gmres_its": 0}
+        curve = [(0.0, U)]
+        ended = "wall"
+        while time.perf_counter() - w0 < max_wall:
+            if U <= cutoff:
+                ended = "cutoff"
+                break
+            if t >= t_end:
+                ended = "time"
+                break
+            try:
+                t, rep = ctx.advance(c, t, u, inner=inner)
+            except lsbdg.DgError as e:
+                ended = f"failed ({e.code})"
+                break
+            for k in ("trials", "halvings", "newton_its", "gmres_its"):
+                tot[k] += rep[k]
+            tot["steps"] += 1
+            U = ctx.outputs(u, t)["U_cell"]
+            curve.append((t, U))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ctx.close()
+        curves[name] = np.array(curve)
+        out["strategies"][name] = {"wall_s": round(wall, 2), "t_end_s": round(t, 3), "U_end_V": round(U, 5),
+                                   "ended_by": ended, "workspace_bytes": ws, **tot}
+        log(f"[study] {name}: {tot['steps']} steps to t = {t:.4g} s in {wall:.1f} s ({ended})")
+    ref = curves["naive"]
+    for name, cv in curves.items():
+        hi = min(cv[-1, 0], ref[-1, 0])
+        sel = (cv[:, 0] > 0) & (cv[:, 0] <= hi)
+        if sel.any():
+            dU = np.abs(cv[sel, 1] - np.interp(cv[sel, 0], ref[:, 0], ref[:, 1]))
+            out["strategies"][name]["max_abs_dU_vs_naive_V"] = float(f"{dU.max():.3e}")
+    return out
+
+
 def run_steps(ctx, ctrl, u, t, n, inner, log, verbose=0, coarse=0, coarse_agg=0):
     """n accepted steps of the naive controller (halving on failed solves)."""
     tot = {"newton_its": 0, "gmres_its": 0, "trials": 0, "halvings": 0}
@@ -699,6 +767,9 @@ def main(argv=None):
     ap.add_argument("--limiter", action="store_true", help="--discharge: limit every step's root (dg_limit)")
     ap.add_argument("--max-wall", type=float, default=None, help="--discharge: stop after this many seconds")
     ap.add_argument("--t-stop", type=float, default=None, help="--discharge: stop at this simulated time [s]")
+    ap.add_argument("--controller-study", nargs=2, metavar=("NX", "F_C"), default=None,
+                    help="the time-stepping comparison (backward Euler, naive, H211b at 1e-8 and 1e-5) on an "
+                         "NX x 1 x 1 homogenised cathode at F_C (per hour); --max-wall caps each strategy")
     ap.add_argument("--batch", action="store_true",
                     help="the 64-structure batch workload in full (operators, block preconditioner, "
                          "side-by-side solves) and print that record only")
@@ -731,6 +802,10 @@ def main(argv=None):
 
     if args.batch:
         print(json.dumps(batch_throughput(torch.device("cuda:0"), log)), flush=True)
+        return 0
+    if args.controller_study:
+        nx, fc = args.controller_study
+        print(json.dumps(controller_study(int(nx), float(fc), log, max_wall=args.max_wall or 240.0)), flush=True)
         return 0
     if args.discharge:
         out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log,
