@@ -689,7 +689,11 @@ def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64"):
         tot = {"steps": 0, "trials": 0, "halvings": 0, "newton_its": 0, "gmres_its": 0}
         curve = [(0.0, U)]
         ended = "wall"
+        last_log = time.perf_counter()
         while time.perf_counter() - w0 < max_wall:
+            if time.perf_counter() - last_log > 30.0:
+                log(f"[study] {name}: {tot['steps']} steps, t = {t:.4g} s, U_cell = {U:.4f} V")
+                last_log = time.perf_counter()
             if U <= cutoff:
                 ended = "cutoff"
                 break
