@@ -655,7 +655,7 @@ def batch_solves(structs, dof, log, dt=0.1, iters=2):
             "side_by_side_equals_sequential": bool(same)}
 
 
-def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64"):
+def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64", limiter=0, only=None):
     """The time-stepping comparison of Sec. 3.3 on a one-dimensional
     homogenised cathode: nx voxels of 1 um, every voxel structure (the
     porous cathode of Tab. 5 through Eq. 57), the paper's parameters, the
@@ -675,7 +675,10 @@ def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64"):
                        f"{f_C}C, inner {inner}", "strategies": {}}
     curves = {}
     t_end = 3600.0 / f_C
+    out["limiter"] = limiter
     for name, kind, tol in kinds:
+        if only and name not in only:
+            continue
         ctx = lsbdg.Context(nx, 1, 1, 1e-6, 1, mask, f_C=f_C)
         feats = lsbdg.DG_WS_STEP | (lsbdg.DG_WS_H211B if kind == "h211b" else lsbdg.DG_WS_NAIVE)
         ws = lsbdg.workspace_bytes(nx, 1, 1, 1e-6, 1, feats, inner=inner)
@@ -701,7 +704,7 @@ def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64"):
                 ended = "time"
                 break
             try:
-                t, rep = ctx.advance(c, t, u, inner=inner)
+                t, rep = ctx.advance(c, t, u, inner=inner, limiter=limiter)
             except lsbdg.DgError as e:
                 ended = f"failed ({e.code})"
                 break
@@ -717,8 +720,10 @@ def controller_study(nx, f_C, log, max_wall=240.0, cutoff=1.9, inner="f64"):
         out["strategies"][name] = {"wall_s": round(wall, 2), "t_end_s": round(t, 3), "U_end_V": round(U, 5),
                                    "ended_by": ended, "workspace_bytes": ws, **tot}
         log(f"[study] {name}: {tot['steps']} steps to t = {t:.4g} s in {wall:.1f} s ({ended})")
-    ref = curves["naive"]
+    ref = curves.get("naive")
     for name, cv in curves.items():
+        if ref is None:
+            break
         hi = min(cv[-1, 0], ref[-1, 0])
         sel = (cv[:, 0] > 0) & (cv[:, 0] <= hi)
         if sel.any():
@@ -768,9 +773,13 @@ def main(argv=None):
                     help="run one full discharge of WORKLOAD (naive controller, cutoff 1.9 V) and print "
                          "its wall time instead of the benchmark line")
     ap.add_argument("--discharge-rate", type=float, default=1.0, help="C-rate of --discharge")
-    ap.add_argument("--limiter", action="store_true", help="--discharge: limit every step's root (dg_limit)")
+    ap.add_argument("--limiter", action="store_true",
+                    help="--discharge, --controller-study: limit every step's root (dg_limit)")
     ap.add_argument("--max-wall", type=float, default=None, help="--discharge: stop after this many seconds")
     ap.add_argument("--t-stop", type=float, default=None, help="--discharge: stop at this simulated time [s]")
+    ap.add_argument("--strategies", default=None,
+                    help="--controller-study: comma-separated subset of backward_euler_dt0.1, naive, "
+                         "h211b_tol1e-8, h211b_tol1e-5")
     ap.add_argument("--controller-study", nargs=2, metavar=("NX", "F_C"), default=None,
                     help="the time-stepping comparison (backward Euler, naive, H211b at 1e-8 and 1e-5) on an "
                          "NX x 1 x 1 homogenised cathode at F_C (per hour); --max-wall caps each strategy")
@@ -809,7 +818,9 @@ def main(argv=None):
         return 0
     if args.controller_study:
         nx, fc = args.controller_study
-        print(json.dumps(controller_study(int(nx), float(fc), log, max_wall=args.max_wall or 240.0)), flush=True)
+        print(json.dumps(controller_study(int(nx), float(fc), log, max_wall=args.max_wall or 240.0,
+                                          limiter=int(args.limiter),
+                                          only=args.strategies.split(",") if args.strategies else None)), flush=True)
         return 0
     if args.discharge:
         out = discharge(args.discharge, args.discharge_rate, args.inner, args.coarse, args.coarse_agg, log,
