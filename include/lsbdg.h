@@ -500,13 +500,18 @@ int dg_batch_blockjacobi_apply(dg_batch* b, dg_prec prec, const void* x, void* y
  * per work item; persistent = k > 0 launches k workgroups per compute unit
  * (rounded down to a multiple of 8, at least 8, at most one per work item),
  * each looping over work items in a fixed stride, so every workgroup ends.
- * The shape changes only which workgroup computes a node: results are the
- * same in every shape.  Default: {32, 0}, unless dg_batch_autotune has run
- * in this process on a batch of the same precision and size class (the bit
- * length of E), whose choice a new batch starts from. */
+ * Among the tile shapes only the workgroup that computes a node changes:
+ * their results are the same.  The condensed tangent also has the brick
+ * shape {64, 0}: one 512-lane workgroup per brick of 4 x 4 x 4 voxels of a
+ * structure, each inner face evaluated once, as dg_jvp's Krylov operator;
+ * it gives every structure dg_jvp's values on it, and differs from the
+ * tile shapes by rounding only.  Defaults: {64, 0} for the condensed
+ * tangent, {32, 0} for the others, unless dg_batch_autotune has run in this
+ * process on a batch of the same precision and size class (the bit length
+ * of E), whose choice a new batch starts from. */
 typedef struct dg_batch_shape {
-  int32_t tile_voxels; /* 8, 16 or 32 */
-  int32_t persistent;  /* 0, or workgroups per compute unit in [1, 64] */
+  int32_t tile_voxels; /* 8, 16 or 32; 64 (bricks, condensed tangent only) */
+  int32_t persistent;  /* 0, or workgroups per compute unit in [1, 64] (tiles) */
 } dg_batch_shape;
 
 /* Batched operators whose launch shape is tunable. */
@@ -519,21 +524,23 @@ typedef enum dg_batch_op {
 typedef struct dg_batch_tuning {
   dg_batch_shape shape[3]; /* chosen shape, by dg_batch_op */
   double ms[3];            /* mean time per launch in that shape */
-  double ms_default[3];    /* mean time per launch in the default shape {32, 0} */
-  int32_t candidates;      /* shapes timed per operator (6, or 3 without occupancy data) */
+  double ms_default[3];    /* mean time per launch in the operator's default shape */
+  int32_t candidates;      /* tile shapes timed per operator (6, or 3 without occupancy
+                              data); the condensed tangent also times the brick shape */
   int32_t pad;
 } dg_batch_tuning;
 
 /* Set or read the launch shape of operator op (a dg_batch_op) in precision
  * prec.  DG_EINVAL for an unknown op or precision, tile_voxels outside
- * {8, 16, 32} or persistent outside [0, 64]. */
+ * {8, 16, 32} (or 64 for the condensed tangent, with persistent = 0) or
+ * persistent outside [0, 64]. */
 int dg_batch_set_shape(dg_batch* b, dg_prec prec, int32_t op, const dg_batch_shape* shape);
 int dg_batch_get_shape(const dg_batch* b, dg_prec prec, int32_t op, dg_batch_shape* shape);
 
 /* Autotuner: times the three tunable operators on these arrays in every
  * launch shape (tile sizes 8, 16 and 32, each with one workgroup per work
  * item and as a persistent grid at the occupancy the compiled kernel
- * allows), reps launches each after one warm-up (reps <= 0: 5; at most
+ * allows; bricks for the condensed tangent), reps launches each after one warm-up (reps <= 0: 5; at most
  * 1000), keeps the fastest shape per operator for this batch and for later
  * batches of its precision and size class, and fills report.  u, v: device,
  * 9 x E x 8 (the condensed tangent reads v's first 7 fields); m_old: device,

@@ -18,6 +18,7 @@
 
 #include "model.hpp"
 #include "resid_q1.hpp"
+#include "brick_q1.hpp"
 #include "blockjacobi.hpp"
 
 namespace lsbdg {
@@ -130,6 +131,28 @@ q1_block_batch_kernel(const S* __restrict__ U, const S* __restrict__ Cw, S* __re
   const int64_t o = t.base * 8;
   q1_block_node<S, Mode>(U + o, Cw + o, Bout + t.base * int64_t(NB) * NB, phase + t.base, *P, e,
                          int(threadIdx.x & 7), FS);
+}
+
+// Krylov operator of a batch on bricks of 4 x 4 x 4 voxels: one workgroup
+// per work item (structure s, brick v0 of its own brick grid, first voxel
+// base of the structure in the concatenation), with the structure's folded
+// parameters and the batch's field stride FS.  Each structure's values are
+// those of q1_brick_jvp_kernel on it (the same body, array bases offset).
+template <typename S>
+__global__ void __launch_bounds__(kBrickLanes)
+q1_brick_jvp_batch_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ Cw,
+                          S* __restrict__ Out, const uint8_t* __restrict__ phase, const KP<S>* __restrict__ Ks,
+                          const BatchTile* __restrict__ items, int64_t nitems, int64_t FS,
+                          int64_t nitems_padded) {
+  __shared__ BrickLds<S> L;
+  const int64_t blk = xcd_block(nitems_padded);
+  if (blk >= nitems) return;                     // a padding workgroup leaves as a whole
+  const BatchTile t = items[blk];
+  const int s = __builtin_amdgcn_readfirstlane(t.s);
+  const KP<S>& K = Ks[s];                        // read in place: a copy would go to scratch
+  const int nbx = (K.nx + kBE - 1) / kBE, nby = (K.ny + kBE - 1) / kBE;
+  const int64_t o = t.base;
+  brick_jvp(U + o * 8, V + o * 8, Cw + o * 8, Out + o * 8, phase + o, K, nbx, nby, int64_t(t.v0), FS, L);
 }
 
 // Linearisation coefficients of the condensed tangent (14 x E x 8).

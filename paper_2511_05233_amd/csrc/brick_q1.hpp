@@ -392,14 +392,15 @@ __device__ __forceinline__ void source_tangent(const KP<S>& K, int ph, const S* 
   dS[6] = -K.F * (dsE[0] + dsE[1] + dsE[2] + dsE[3] + dsE[4] + dsE[5]);
 }
 
+// The operator on one brick (index `brick` of the structure's nbx x nby x
+// nbz bricks, x fastest; an index past the last brick does nothing) of a
+// structure whose arrays start at U, V, Cw, Out and phase, with field
+// stride FS (the structure's own node count, or a batch's).
 template <typename S>
-__global__ void __launch_bounds__(kBrickLanes)
-q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ Cw,
-                    S* __restrict__ Out, const uint8_t* __restrict__ phase, KP<S> K, int nbx, int nby,
-                    int64_t nbricks_padded) {
-  __shared__ BrickLds<S> L;
-  const int64_t FS = K.Ne * 8;
-  const int64_t brick = xcd_block(nbricks_padded);
+__device__ __forceinline__ void brick_jvp(const S* __restrict__ U, const S* __restrict__ V,
+                                          const S* __restrict__ Cw, S* __restrict__ Out,
+                                          const uint8_t* __restrict__ phase, const KP<S>& K, int nbx, int nby,
+                                          int64_t brick, int64_t FS, BrickLds<S>& L) {
   const int lane = threadIdx.x;
   const int n = lane & 7, vb = lane >> 3;
   const int bx = vb & 3, by = (vb >> 2) & 3, bz = vb >> 4;
@@ -575,6 +576,16 @@ q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* _
     const bool on = (K.active >> f) & 1;
     Out[f * FS + e * 8 + n] = on ? acc[f] : S(0);
   }
+}
+
+// One structure: one workgroup per brick, XCD-aware order.
+template <typename S>
+__global__ void __launch_bounds__(kBrickLanes)
+q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ Cw,
+                    S* __restrict__ Out, const uint8_t* __restrict__ phase, KP<S> K, int nbx, int nby,
+                    int64_t nbricks_padded) {
+  __shared__ BrickLds<S> L;
+  brick_jvp(U, V, Cw, Out, phase, K, nbx, nby, xcd_block(nbricks_padded), K.Ne * 8, L);
 }
 
 }  // namespace lsbdg

@@ -1000,6 +1000,12 @@ struct dg_batch {
   int n_cu = 0;                        // compute units of the device
   DevParams* d_params = nullptr;
   DevParams* h_params = nullptr;       // pinned staging of d_params
+  BatchTile* d_bricks = nullptr;       // bricks of 4 x 4 x 4 voxels (v0 = brick index in its structure)
+  int64_t nbricks = 0;
+  KP<float>* d_kpf = nullptr;          // folded parameters of the brick operator, by precision
+  KP<double>* d_kpd = nullptr;
+  KP<float>* h_kpf = nullptr;          // pinned staging of d_kpf, d_kpd
+  KP<double>* h_kpd = nullptr;
   hipEvent_t staged = nullptr;         // recorded after each upload of h_params
   DevBuf lin, blocks, status;
   int lin_prec = -1, blocks_prec = -1;
@@ -1010,18 +1016,28 @@ namespace {
 
 // Per-structure parameter blocks at (t_new[s], dt[s]) (mass: at t = 0,
 // without a step) to the device, on the stream of the call that reads them.
+// With kp, also the brick operator's folded parameters in both precisions.
 int batch_params(dg_batch* b, const double* t_new, const double* dt, bool step, hipStream_t st,
-                 const char* fn) {
+                 const char* fn, bool kp = false) {
   const int n = int(b->subs.size());
   if (step) {
     if (!t_new || !dt) return fail(DG_EINVAL, std::string(fn) + ": null t_new or dt");
     for (int s = 0; s < n; ++s)
       if (!(dt[s] > 0)) return fail(DG_EINVAL, std::string(fn) + ": dt[" + std::to_string(s) + "] must be positive");
   }
-  DG_HIP(hipEventSynchronize(b->staged));   // the previous upload has left the staging buffer
-  for (int s = 0; s < n; ++s)
+  DG_HIP(hipEventSynchronize(b->staged));   // the previous upload has left the staging buffers
+  for (int s = 0; s < n; ++s) {
     b->h_params[s] = make_params(b->subs[s], step ? t_new[s] : 0.0, step ? dt[s] : 0.0);
+    if (kp) {
+      b->h_kpf[s] = make_kp<float>(b->h_params[s]);
+      b->h_kpd[s] = make_kp<double>(b->h_params[s]);
+    }
+  }
   DG_HIP(hipMemcpyAsync(b->d_params, b->h_params, size_t(n) * sizeof(DevParams), hipMemcpyHostToDevice, st));
+  if (kp) {
+    DG_HIP(hipMemcpyAsync(b->d_kpf, b->h_kpf, size_t(n) * sizeof(KP<float>), hipMemcpyHostToDevice, st));
+    DG_HIP(hipMemcpyAsync(b->d_kpd, b->h_kpd, size_t(n) * sizeof(KP<double>), hipMemcpyHostToDevice, st));
+  }
   DG_HIP(hipEventRecord(b->staged, st));
   return DG_OK;
 }
@@ -1041,6 +1057,11 @@ int size_class(int64_t E) {
 }
 
 constexpr dg_batch_shape kDefaultShape{kTileVoxels, 0};
+// The brick shape of the condensed tangent: work items of 4 x 4 x 4 voxels
+// (inner faces evaluated once), the default of that operator.
+constexpr dg_batch_shape kBrickShape{kBrickVox, 0};
+
+constexpr dg_batch_shape default_shape(int op) { return op == DG_BOP_JVP_CONDENSED7 ? kBrickShape : kDefaultShape; }
 
 template <typename S>
 constexpr int prec_index() { return std::is_same<S, double>::value ? DG_F64 : DG_F32; }
@@ -1116,9 +1137,29 @@ int q1_batch_resident(int tile_voxels) {
   return n;
 }
 
+// Condensed tangent at the batch linearisation on bricks of 4 x 4 x 4
+// voxels: one workgroup per brick of every structure, XCD-aware order.
+// Needs the folded parameters of batch_params(..., kp = true).
+template <typename S>
+void launch_brick_batch(const dg_batch* b, const void* u, const void* v, void* out, hipStream_t st) {
+  const int64_t nb = (b->nbricks + 7) / 8 * 8;
+  const KP<S>* Ks;
+  if constexpr (std::is_same<S, double>::value)
+    Ks = b->d_kpd;
+  else
+    Ks = b->d_kpf;
+  hipLaunchKernelGGL(q1_brick_jvp_batch_kernel<S>, dim3(unsigned(nb)), dim3(kBrickLanes), 0, st,
+                     static_cast<const S*>(u), static_cast<const S*>(v), b->lin.as<const S>(), static_cast<S*>(out),
+                     b->d_phase, Ks, b->d_bricks, b->nbricks, b->E * 8, nb);
+}
+
 template <typename S, typename N, int Mode>
 void launch_q1_batch(const dg_batch* b, const void* u, const void* v, const void* m, void* out, hipStream_t st) {
-  launch_q1_batch_shape<S, N, Mode>(b, b->shape[prec_index<S>()][op_index<Mode>()], u, v, m, out, st);
+  const dg_batch_shape sh = b->shape[prec_index<S>()][op_index<Mode>()];
+  if (Mode == kJvpCondensed && sh.tile_voxels == kBrickShape.tile_voxels)
+    launch_brick_batch<S>(b, u, v, out, st);
+  else
+    launch_q1_batch_shape<S, N, Mode>(b, sh, u, v, m, out, st);
 }
 
 template <typename S>
@@ -1944,11 +1985,16 @@ int dg_batch_destroy(dg_batch* b) {
   for (BatchTile* t : b->d_tiles_by)
     if (t) (void)hipFree(t);
   if (b->d_params) (void)hipFree(b->d_params);
+  if (b->d_bricks) (void)hipFree(b->d_bricks);
+  if (b->d_kpf) (void)hipFree(b->d_kpf);
+  if (b->d_kpd) (void)hipFree(b->d_kpd);
   if (b->staged) {
     (void)hipEventSynchronize(b->staged);
     (void)hipEventDestroy(b->staged);
   }
   if (b->h_params) (void)hipHostFree(b->h_params);
+  if (b->h_kpf) (void)hipHostFree(b->h_kpf);
+  if (b->h_kpd) (void)hipHostFree(b->h_kpd);
   b->lin.release();
   b->blocks.release();
   b->status.release();
@@ -1992,6 +2038,13 @@ int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phase
       for (int s = 0; s < n; ++s)
         for (int64_t v0 = 0; v0 < b->subs[s]->Ne; v0 += kTileChoices[ti])
           tiles[ti].push_back(BatchTile{int32_t(s), int32_t(v0), b->off[s]});
+    std::vector<BatchTile> bricks;
+    for (int s = 0; s < n; ++s) {
+      const dg_mesh& m = b->subs[s]->mesh;
+      const int64_t nbr = int64_t((m.nx + kBE - 1) / kBE) * ((m.ny + kBE - 1) / kBE) * ((m.nz + kBE - 1) / kBE);
+      for (int64_t k = 0; k < nbr; ++k) bricks.push_back(BatchTile{int32_t(s), int32_t(k), b->off[s]});
+    }
+    b->nbricks = int64_t(bricks.size());
     hipError_t e = hipMalloc(&b->d_phase, size_t(b->E));
     for (int ti = 0; ti < 3 && e == hipSuccess; ++ti) {
       b->ntiles_by[ti] = int64_t(tiles[ti].size());
@@ -2001,6 +2054,11 @@ int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phase
     b->ntiles = b->ntiles_by[2];
     if (e == hipSuccess) e = hipMalloc(&b->d_params, size_t(n) * sizeof(DevParams));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_params, size_t(n) * sizeof(DevParams));
+    if (e == hipSuccess) e = hipMalloc(&b->d_bricks, bricks.size() * sizeof(BatchTile));
+    if (e == hipSuccess) e = hipMalloc(&b->d_kpf, size_t(n) * sizeof(KP<float>));
+    if (e == hipSuccess) e = hipMalloc(&b->d_kpd, size_t(n) * sizeof(KP<double>));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_kpf, size_t(n) * sizeof(KP<float>));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_kpd, size_t(n) * sizeof(KP<double>));
     if (e != hipSuccess) return abandon(fail(DG_ENOMEM, std::string("dg_batch_setup: ") + hipGetErrorString(e)));
     int dev = 0;
     e = hipGetDevice(&dev);
@@ -2011,13 +2069,15 @@ int dg_batch_setup(int32_t n, const dg_mesh* meshes, const uint8_t* const* phase
     for (int ti = 0; ti < 3 && e == hipSuccess; ++ti)
       e = hipMemcpy(b->d_tiles_by[ti], tiles[ti].data(), tiles[ti].size() * sizeof(BatchTile),
                     hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_bricks, bricks.data(), bricks.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
     if (e != hipSuccess) return abandon(fail(DG_EHIP, std::string("dg_batch_setup: ") + hipGetErrorString(e)));
     {
       std::lock_guard<std::mutex> lk(g_shape_mu);
       for (int p = 0; p < 2; ++p)
         for (int op = 0; op < 3; ++op) {
           auto it = g_shape_cache.find({p, op, size_class(b->E)});
-          b->shape[p][op] = it == g_shape_cache.end() ? kDefaultShape : it->second;
+          b->shape[p][op] = it == g_shape_cache.end() ? default_shape(op) : it->second;
         }
     }
     *out = b;
@@ -2091,7 +2151,7 @@ int dg_batch_jvp(dg_batch* b, dg_prec prec, dg_jvp_mode mode, const void* u, con
   if (mode == DG_JVP_LINEARIZED7 && b->lin_prec != int(prec))
     return fail(DG_ESTATE, "dg_batch_jvp: no batch linearisation of this precision (dg_batch_linearize)");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_jvp")) return s;
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_jvp", mode != DG_JVP_FULL9)) return s;
   if (mode == DG_JVP_FULL9) {
     if (prec == DG_F64)
       launch_q1_batch<double, Dual<double>, kJvpFull>(b, u, v, nullptr, jv, st);
@@ -2238,31 +2298,43 @@ template <typename S, typename N, int Mode>
 int tune_op(dg_batch* b, const void* u, const void* v, const void* m, void* work, int reps, hipEvent_t t0,
             hipEvent_t t1, dg_batch_tuning* rep, hipStream_t st) {
   constexpr int op = op_index<Mode>();
-  dg_batch_shape best = kDefaultShape;
+  constexpr dg_batch_shape def = default_shape(op);
+  dg_batch_shape best = def;
   double best_ms = INFINITY, def_ms = NAN;
   int tried = 0;
+  auto time_shape = [&](dg_batch_shape sh, bool brick) -> int {
+    auto launch = [&] {
+      if (brick)
+        launch_brick_batch<S>(b, u, v, work, st);
+      else
+        launch_q1_batch_shape<S, N, Mode>(b, sh, u, v, m, work, st);
+    };
+    launch();   // warm-up
+    DG_HIP(hipEventRecord(t0, st));
+    for (int r = 0; r < reps; ++r) launch();
+    DG_HIP(hipGetLastError());
+    DG_HIP(hipEventRecord(t1, st));
+    DG_HIP(hipEventSynchronize(t1));
+    float ms = 0.f;
+    DG_HIP(hipEventElapsedTime(&ms, t0, t1));
+    const double per = double(ms) / reps;
+    if (sh.tile_voxels == def.tile_voxels && sh.persistent == def.persistent) def_ms = per;
+    if (per < best_ms) {
+      best_ms = per;
+      best = sh;
+    }
+    return DG_OK;
+  };
   for (int tv : kTileChoices) {
     const int occ = q1_batch_resident<S, N, Mode>(tv);
     const int forms = occ > 0 ? 2 : 1;             // occupancy unknown: no persistent form
     for (int f = 0; f < forms; ++f) {
-      const dg_batch_shape sh{tv, f == 0 ? 0 : occ};
-      launch_q1_batch_shape<S, N, Mode>(b, sh, u, v, m, work, st);   // warm-up
-      DG_HIP(hipEventRecord(t0, st));
-      for (int r = 0; r < reps; ++r) launch_q1_batch_shape<S, N, Mode>(b, sh, u, v, m, work, st);
-      DG_HIP(hipGetLastError());
-      DG_HIP(hipEventRecord(t1, st));
-      DG_HIP(hipEventSynchronize(t1));
-      float ms = 0.f;
-      DG_HIP(hipEventElapsedTime(&ms, t0, t1));
-      const double per = double(ms) / reps;
-      if (sh.tile_voxels == kDefaultShape.tile_voxels && sh.persistent == 0) def_ms = per;
-      if (per < best_ms) {
-        best_ms = per;
-        best = sh;
-      }
+      if (int s = time_shape(dg_batch_shape{tv, f == 0 ? 0 : occ}, false)) return s;
       tried += 1;
     }
   }
+  if (Mode == kJvpCondensed)
+    if (int s = time_shape(kBrickShape, true)) return s;
   b->shape[prec_index<S>()][op] = best;
   {
     std::lock_guard<std::mutex> lk(g_shape_mu);
@@ -2300,8 +2372,13 @@ int dg_batch_set_shape(dg_batch* b, dg_prec prec, int32_t op, const dg_batch_sha
   if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_batch_set_shape: bad precision");
   if (op < 0 || op > 2) return fail(DG_EINVAL, "dg_batch_set_shape: bad operator");
   const int tv = shape->tile_voxels;
-  if (std::find(std::begin(kTileChoices), std::end(kTileChoices), tv) == std::end(kTileChoices))
-    return fail(DG_EINVAL, "dg_batch_set_shape: tile_voxels must be 8, 16 or 32");
+  if (tv == kBrickShape.tile_voxels) {
+    if (op != DG_BOP_JVP_CONDENSED7)
+      return fail(DG_EINVAL, "dg_batch_set_shape: the brick shape (64) is for the condensed tangent only");
+    if (shape->persistent != 0) return fail(DG_EINVAL, "dg_batch_set_shape: the brick shape takes persistent = 0");
+  } else if (std::find(std::begin(kTileChoices), std::end(kTileChoices), tv) == std::end(kTileChoices)) {
+    return fail(DG_EINVAL, "dg_batch_set_shape: tile_voxels must be 8, 16, 32 or (condensed tangent) 64");
+  }
   if (shape->persistent < 0 || shape->persistent > 64)
     return fail(DG_EINVAL, "dg_batch_set_shape: persistent must be in [0, 64]");
   b->shape[prec][op] = *shape;
@@ -2326,7 +2403,7 @@ int dg_batch_autotune(dg_batch* b, dg_prec prec, const void* u, const void* v, c
   const int r = reps > 0 ? reps : 5;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::memset(report, 0, sizeof(*report));
-  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_autotune")) return s;
+  if (int s = batch_params(b, t_new, dt, true, st, "dg_batch_autotune", true)) return s;
   return prec == DG_F64
              ? batch_autotune<double>(b, static_cast<const double*>(u), static_cast<const double*>(v),
                                       static_cast<const double*>(m_old), static_cast<double*>(work), r, report, st)

@@ -226,6 +226,11 @@ def test_every_launch_shape_gives_the_same_results(shape_case, dtype):
         got = _operators(b, u, m, v, t, dt)
         for name, g, r in zip(lsbdg.BATCH_OPS, got, ref):
             assert torch.equal(g, r), (tv, pers, name)
+    # the brick shape of the condensed tangent sums in another order
+    b.set_shape(dtype, "jvp_condensed", 64, 0)
+    jb = b.jvp(u, v[:7].contiguous(), t, dt, condensed=True)
+    print(f"[batch] {dtype} bricks vs tiles: condensed JVP {_rel(jb, ref[2]):.2e}", flush=True)
+    assert _rel(jb, ref[2]) <= LOOSE[dtype]
     for op in lsbdg.BATCH_OPS:
         b.set_shape(dtype, op, 32, 0)
 
@@ -236,6 +241,8 @@ def test_set_shape_checks_its_arguments(shape_case):
     for tv, pers in [(4, 0), (64, 0), (32, -1), (32, 65)]:
         with pytest.raises(lsbdg.DgError, match="DG_EINVAL"):
             b.set_shape(torch.float32, "residual", tv, pers)
+    with pytest.raises(lsbdg.DgError, match="DG_EINVAL"):
+        b.set_shape(torch.float32, "jvp_condensed", 64, 1)
     assert b.get_shape(torch.float32, "residual") == (32, 0)
 
 
@@ -252,7 +259,7 @@ def test_autotune_keeps_the_fastest_timed_shape(shape_case):
     print(f"[batch] autotune: {tune}, {ncand} shapes per operator", flush=True)
     assert ncand in (3, 6)
     for op, (shape, ms, ms_def) in tune.items():
-        assert shape[0] in (8, 16, 32) and shape[1] >= 0
+        assert shape[0] in (8, 16, 32) and shape[1] >= 0 or op == "jvp_condensed" and shape == (64, 0)
         assert 0.0 < ms <= ms_def
         assert b.get_shape(torch.float32, op) == shape
     b2 = lsbdg.Batch(structs)
