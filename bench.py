@@ -585,7 +585,8 @@ def batch_throughput(dev, log, n=64, reps=10, t=0.1, dt=0.1, full=True, solves=F
     solve = batch_solves(structs, dof, log) if (full or solves) else None
     res = {
         "workload": f"{n} cubic structures, edges U{{24..64}} voxels, porosity U(0.4, 0.75), DG-Q1, "
-                    f"{E} voxels, {dof} DoF, {B.n_tiles} work items of 32 voxels",
+                    f"{E} voxels, {dof} DoF; residual in {B.n_tiles} tiles of 32 voxels, "
+                    f"Krylov operator on bricks of 4^3 voxels (its default shape)",
         "jvp_f32_ms": {"batched": round(ms_jvp_b, 3), "per_structure": round(ms_jvp_s, 3),
                        "per_structure_graph": round(ms_jvp_g, 3)},
         "jvp_f32_gdofs": {"batched": round(dof / ms_jvp_b / 1e6, 2),
