@@ -262,14 +262,15 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     ms_lin = time_launches(lambda: ctx.linearize(uS, t, dt), stream, 5)
     ms_jvp = time_launches(lambda: ctx.jvp(uS, v7, t, dt, out=y7, linearized=True), stream, reps)
     ms_res = time_launches(lambda: ctx.residual(u, m8, t, dt, out=r9), stream, reps)
-    q1 = ctx.n_nodes == 8                                   # the block preconditioner is Q1's
-    if q1:
+    q1 = ctx.n_nodes == 8
+    blocks = ctx.n_nodes in (8, 64)                         # element blocks at k = 1 and 3
+    ms_apply_h = None
+    if blocks:
         ctx.blockjacobi_setup(uS, t, dt)
         ms_apply = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7), stream, reps)
-        ms_apply_h = None
-        if S == torch.float32:
+        if q1 and S == torch.float32:
             ms_apply_h = time_launches(lambda: ctx.blockjacobi_apply(v7, out=y7, bf16=True), stream, reps)
-        ms_setup = time_launches(lambda: ctx.blockjacobi_setup(uS, t, dt), stream, 3)
+        ms_setup = time_launches(lambda: ctx.blockjacobi_setup(uS, t, dt), stream, 3 if q1 else 1)
 
     def gbs(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9
@@ -281,7 +282,8 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
     b_jvp = nodes * (9 + 7 + 7) * sb + ctx.n_elem           # u, v in; Jv out; phase
     b_lin = nodes * LIN_COEFFS * sb                         # stored linearisation read by the kernel
     b_res = nodes * (9 + 8 + 9) * 8 + ctx.n_elem            # u, old mass in; R out; phase
-    b_apply = ctx.n_elem * (56 * 56 + 2 * 56) * sb          # blocks, x in, y out
+    nb = 7 * ctx.n_nodes
+    b_apply = ctx.n_elem * (nb * nb + 2 * nb) * sb          # blocks, x in, y out
     b_apply_h = ctx.n_elem * (56 * 56 * 2 + 2 * 56 * 4)     # bfloat16 blocks, FP32 x in, y out
     kernels = {
         "jvp_condensed": {"ms": ms_jvp, "GB/s": gbs(b_jvp, ms_jvp), "bytes": b_jvp,
@@ -289,10 +291,15 @@ def time_kernels(ctx, u, t, dt, inner, stream, dev, log):
         "residual_f64": {"ms": ms_res, "GB/s": gbs(b_res, ms_res), "bytes": b_res},
         "linearize": {"ms": ms_lin},
     }
-    if q1:
+    if blocks:
         kernels["block_apply"] = {"ms": ms_apply, "GB/s": gbs(b_apply, ms_apply), "bytes": b_apply}
         kernels["block_setup"] = {"ms": ms_setup}
-    if q1 and ms_apply_h is not None:
+        if not q1:
+            # assembly: 2 colours x 448 probes of the Krylov operator; inversion:
+            # 2 nb^3 flop per element on the matrix cores (see the kernel trace)
+            kernels["block_setup"]["probes"] = 2 * nb
+            kernels["block_setup"]["inversion_flop"] = 2 * nb ** 3 * ctx.n_elem
+    if ms_apply_h is not None:
         kernels["block_apply_bf16"] = {"ms": ms_apply_h, "GB/s": gbs(b_apply_h, ms_apply_h), "bytes": b_apply_h}
     for k in kernels.values():
         if "GB/s" in k:

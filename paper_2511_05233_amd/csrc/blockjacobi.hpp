@@ -179,12 +179,15 @@ __host__ __device__ __forceinline__ int quad_index(int row, int col) {
 }
 
 // Wave-wide argmax of a non-negative key (-1 = excluded); returns the lane.
-__device__ __forceinline__ int wave_argmax(float key, int lane) {
-  float k = key;
+// The key keeps the block's precision: entries of trace-species rows lie
+// far below the FP32 range, where FP32 keys would all tie.
+template <typename S>
+__device__ __forceinline__ int wave_argmax(S key, int lane) {
+  S k = key;
   int l = lane;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    const float ok = __shfl_xor(k, off);
+    const S ok = __shfl_xor(k, off);
     const int ol = __shfl_xor(l, off);
     if (ok > k || (ok == k && ol < l)) {
       k = ok;
@@ -227,7 +230,7 @@ invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status,
   bool bad = false;
 #pragma unroll 1
   for (int k = 0; k < NB; ++k) {
-    const float key = used ? -1.0f : float(fabs(r[0]));
+    const S key = used ? S(-1) : S(fabs(r[0]));
     const int p = wave_argmax(key, lane);
     const S pv = bcast(r[0], p);
     if (!(fabs(pv) > S(0)) || !isfinite(pv)) bad = true;

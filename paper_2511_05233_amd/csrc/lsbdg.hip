@@ -29,6 +29,7 @@
 #include "resid_q3.hpp"
 #include "brick_q1.hpp"
 #include "blockjacobi.hpp"
+#include "blocks_q3.hpp"
 #include "solver.hpp"
 #include "outputs.hpp"
 #include "limiter.hpp"
@@ -52,8 +53,10 @@ struct dg_ctx {
   int np = 1;
   uint8_t* d_phase = nullptr;
   DevBuf phase;                     // device phase map (d_phase points into it)
-  // element block-Jacobi storage (condensed 56 x 56 inverses, column-major)
-  DevBuf blocks;
+  // element block-Jacobi storage (condensed inverses, 56 x 56 at k = 1 and
+  // 448 x 448 at k = 3, column-major); at k = 3 also the pivot lists and two
+  // 7-field vectors for the probes of the assembly
+  DevBuf blocks, qpiv, probe;
   int blocks_prec = -1;
   // linearisation coefficients of the condensed tangent (14 x nodes)
   DevBuf lin;
@@ -74,7 +77,7 @@ struct dg_ctx {
   bool owns_memory = true;
   template <typename F>
   void for_each_buf(F f) {
-    for (DevBuf* d : {&phase, &blocks, &lin, &cE, &cX, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
+    for (DevBuf* d : {&phase, &blocks, &qpiv, &probe, &lin, &cE, &cX, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
       f(*d);
     work.for_each(f);
   }
@@ -174,6 +177,17 @@ int check_q1(const dg_ctx* c, const char* fn) {
                                      " provides the operators only (mass, residual, tangents, linearisation)");
   return DG_OK;
 }
+
+// Entry points of the element block-Jacobi preconditioner: k = 1 and 3.
+int check_blocks_order(const dg_ctx* c, const char* fn) {
+  if (c->mesh.order != 1 && c->mesh.order != 3)
+    return fail(DG_EUNSUPPORTED, std::string(fn) + ": order " + std::to_string(c->mesh.order) +
+                                     " provides the operators only (mass, residual, tangents, linearisation)");
+  return DG_OK;
+}
+
+// Condensed block size: 7 fields x the element's nodes.
+int condensed_block_size(const dg_ctx* c) { return 7 * c->np; }
 
 }  // namespace
 
@@ -324,6 +338,46 @@ int blocks_setup(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st, b
   return DG_OK;
 }
 
+// The k = 3 blocks at uS: the linearisation, then two colours x 448
+// probes of the Krylov operator filed column by column, then the blocked
+// Gauss-Jordan inversion on the matrix cores.
+template <typename S>
+int blocks_setup_q3(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st) {
+  const int64_t Ne = ctx->Ne, FS = Ne * 64;
+  const size_t need = size_t(Ne) * kQ3NB * kQ3NB * sizeof(S);
+  if (ctx->blocks.ensure(need) != hipSuccess) return fail_mem(ctx, "dg_blockjacobi_setup: block storage", need);
+  if (ctx->qpiv.ensure(size_t(Ne) * kQ3NB * sizeof(int16_t)) != hipSuccess)
+    return fail_mem(ctx, "dg_blockjacobi_setup: pivot lists", size_t(Ne) * kQ3NB * sizeof(int16_t));
+  if (ctx->probe.ensure(size_t(14) * FS * sizeof(S)) != hipSuccess)
+    return fail_mem(ctx, "dg_blockjacobi_setup: probe vectors", size_t(14) * FS * sizeof(S));
+  if (ctx->status.ensure(sizeof(int)) != hipSuccess) return fail_mem(ctx, "dg_blockjacobi_setup: status flag", 4);
+  if (int s = linearize<S>(ctx, P, uS, st)) return s;
+  S* v = ctx->probe.as<S>();
+  S* w = v + 7 * FS;
+  S* B = ctx->blocks.as<S>();
+  const int nx = ctx->mesh.nx, ny = ctx->mesh.ny;
+  const unsigned g_seed = unsigned(std::min<int64_t>((7 * FS + 255) / 256, 8192));
+  const unsigned g_scat = unsigned(std::min<int64_t>((Ne * kQ3NB + 255) / 256, 8192));
+  for (int c = 0; c < 2; ++c)
+    for (int j = 0; j < kQ3NB; ++j) {
+      hipLaunchKernelGGL(seed_q3_kernel<S>, dim3(g_seed), dim3(256), 0, st, v, Ne, nx, ny, c, j);
+      launch_q1<S, Dual<S>, kJvpCondensed>(ctx, P, uS, v, ctx->lin.p, w, st);
+      hipLaunchKernelGGL(scatter_q3_kernel<S>, dim3(g_scat), dim3(256), 0, st, w, B, Ne, nx, ny, c, j);
+    }
+  DG_HIP(hipGetLastError());
+  DG_HIP(hipMemsetAsync(ctx->status.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(invert_q3_kernel<S>, dim3(unsigned(Ne)), dim3(256), 0, st, B, ctx->qpiv.as<int16_t>(),
+                     ctx->status.as<int>());
+  DG_HIP(hipGetLastError());
+  int h_status = 0;
+  DG_HIP(hipMemcpyAsync(&h_status, ctx->status.as<int>(), sizeof(int), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipStreamSynchronize(st));
+  ctx->blocks_prec = std::is_same<S, double>::value ? DG_F64 : DG_F32;
+  ctx->bh_valid = false;
+  if (h_status) return fail(DG_ENAN, "dg_blockjacobi_setup: singular or non-finite element block");
+  return DG_OK;
+}
+
 // Pinned done flags and events of the GMRES cycle (made once per context).
 int gmres_host_state(dg_ctx* ctx) {
   if (ctx->gm_flags) return DG_OK;
@@ -421,8 +475,14 @@ std::vector<std::pair<DevBuf*, size_t>> plan_workspace(dg_ctx* ctx, const dg_sol
       std::make_pair(&ctx->work.out_partial, size_t(kNumSums) * kOutBlocks * 8)};
   const bool step = features & (DG_WS_STEP | DG_WS_NAIVE | DG_WS_H211B);
   if (step || (features & DG_WS_BLOCKS)) {
-    out.push_back(std::make_pair(&ctx->blocks, size_t(ctx->Ne) * 56 * 56 * sS));
-    if (sS == 4 && o.block_bf16) out.push_back(std::make_pair(&ctx->bh, size_t(ctx->Ne) * 56 * 56 * 2));
+    const size_t nb = size_t(7) * ctx->np;
+    out.push_back(std::make_pair(&ctx->blocks, size_t(ctx->Ne) * nb * nb * sS));
+    if (ctx->np == 64) {
+      out.push_back(std::make_pair(&ctx->qpiv, size_t(ctx->Ne) * nb * sizeof(int16_t)));
+      out.push_back(std::make_pair(&ctx->probe, size_t(14) * FS * sS));
+    } else if (sS == 4 && o.block_bf16) {
+      out.push_back(std::make_pair(&ctx->bh, size_t(ctx->Ne) * 56 * 56 * 2));
+    }
   }
   need_rocsolver = false;
   nc = 0;
@@ -1357,9 +1417,13 @@ int dg_workspace_bytes(const dg_mesh* mesh, const dg_params* params, const dg_so
     std::vector<uint8_t> ones(size_t(Ne), 1);
     dg_ctx* c = nullptr;
     if (int s = make_context(mesh, ones.data(), params, "dg_workspace_bytes", &c)) return s;
-    if (c->mesh.order != 1 && (features & ~int32_t(DG_WS_OPERATORS))) {
+    const int32_t allowed = c->mesh.order == 1   ? int32_t(DG_WS_ALL)
+                            : c->mesh.order == 3 ? int32_t(DG_WS_OPERATORS | DG_WS_BLOCKS)
+                                                 : int32_t(DG_WS_OPERATORS);
+    if (features & ~allowed) {
       delete c;
-      return fail(DG_EUNSUPPORTED, "dg_workspace_bytes: orders 0 and 3 provide the operators only (DG_WS_OPERATORS)");
+      return fail(DG_EUNSUPPORTED, "dg_workspace_bytes: order 0 provides the operators only (DG_WS_OPERATORS), order 3 "
+                                   "the operators and blocks (DG_WS_BLOCKS)");
     }
     bool need_rs = false;
     int64_t nc = 0;
@@ -1396,9 +1460,13 @@ int dg_setup_ws(const dg_mesh* mesh, const uint8_t* phase, const dg_params* para
     if (int s = normalize_opts(opts, o, "dg_setup_ws")) return s;
     dg_ctx* c = nullptr;
     if (int s = make_context(mesh, phase, params, "dg_setup_ws", &c)) return s;
-    if (c->mesh.order != 1 && (features & ~int32_t(DG_WS_OPERATORS))) {
+    const int32_t allowed = c->mesh.order == 1   ? int32_t(DG_WS_ALL)
+                            : c->mesh.order == 3 ? int32_t(DG_WS_OPERATORS | DG_WS_BLOCKS)
+                                                 : int32_t(DG_WS_OPERATORS);
+    if (features & ~allowed) {
       delete c;
-      return fail(DG_EUNSUPPORTED, "dg_setup_ws: orders 0 and 3 provide the operators only (DG_WS_OPERATORS)");
+      return fail(DG_EUNSUPPORTED, "dg_setup_ws: order 0 provides the operators only (DG_WS_OPERATORS), order 3 "
+                                   "the operators and blocks (DG_WS_BLOCKS)");
     }
     double* scr = nullptr;
     if (int s = device_scratch(&scr)) {
@@ -1575,10 +1643,17 @@ constexpr int kNB = 56;   // condensed Q1 block size: 7 fields x 8 nodes
 int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt,
                          dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
-  if (int s = check_q1(ctx, "dg_blockjacobi_setup")) return s;
+  if (int s = check_blocks_order(ctx, "dg_blockjacobi_setup")) return s;
   if (!u) return fail(DG_EINVAL, "dg_blockjacobi_setup: null array");
   if (!(dt > 0)) return fail(DG_EINVAL, "dg_blockjacobi_setup: dt must be positive");
   if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_blockjacobi_setup: bad precision");
+  if (ctx->np == 64) {
+    const DevParams P = make_params(ctx, t_new, dt);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ctx->blocks_prec = -1;
+    return prec == DG_F64 ? blocks_setup_q3<double>(ctx, P, static_cast<const double*>(u), st)
+                          : blocks_setup_q3<float>(ctx, P, static_cast<const float*>(u), st);
+  }
   const size_t esz = prec == DG_F64 ? sizeof(double) : sizeof(float);
   const size_t need = size_t(ctx->Ne) * kNB * kNB * esz;
   if (ctx->blocks.ensure(need) != hipSuccess) return fail_mem(ctx, "dg_blockjacobi_setup: block storage", need);
@@ -1618,12 +1693,25 @@ int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new,
 
 int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_stream stream) {
   if (int s = check_ctx(ctx)) return s;
-  if (int s = check_q1(ctx, "dg_blockjacobi_apply")) return s;
+  if (int s = check_blocks_order(ctx, "dg_blockjacobi_apply")) return s;
   if (!x || !y) return fail(DG_EINVAL, "dg_blockjacobi_apply: null array");
   if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_apply: no setup yet");
   if (int(prec) != ctx->blocks_prec)
     return fail(DG_EINVAL, "dg_blockjacobi_apply: precision differs from the setup");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->np == 64) {
+    const dim3 g{unsigned(ctx->Ne), 1, 1}, b{512, 1, 1};
+    if (prec == DG_F64)
+      hipLaunchKernelGGL(apply_q3_kernel<double>, g, b, 0, st, ctx->blocks.as<const double>(),
+                         ctx->qpiv.as<const int16_t>(), static_cast<const double*>(x), static_cast<double*>(y),
+                         ctx->Ne);
+    else
+      hipLaunchKernelGGL(apply_q3_kernel<float>, g, b, 0, st, ctx->blocks.as<const float>(),
+                         ctx->qpiv.as<const int16_t>(), static_cast<const float*>(x), static_cast<float*>(y),
+                         ctx->Ne);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+  }
   const dim3 grid{unsigned((ctx->Ne + 3) / 4), 1, 1}, block{256, 1, 1};
   if (prec == DG_F64)
     hipLaunchKernelGGL((apply_blocks_kernel<double, 7>), grid, block, 0, st,
@@ -1664,7 +1752,7 @@ int dg_blockjacobi_info(const dg_ctx* ctx, int32_t* prec, int32_t* block_size) {
   if (!prec || !block_size) return fail(DG_EINVAL, "dg_blockjacobi_info: null argument");
   if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_info: no inverses stored");
   *prec = ctx->blocks_prec;
-  *block_size = kNB;
+  *block_size = condensed_block_size(ctx);
   return DG_OK;
 }
 
@@ -1673,6 +1761,16 @@ int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
   if (!out) return fail(DG_EINVAL, "dg_blockjacobi_export: null array");
   if (ctx->blocks_prec < 0) return fail(DG_ESTATE, "dg_blockjacobi_export: no setup yet");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->np == 64) {
+    if (ctx->blocks_prec == DG_F64)
+      hipLaunchKernelGGL(export_q3_kernel<double>, dim3(unsigned(ctx->Ne)), dim3(512), 0, st,
+                         ctx->blocks.as<const double>(), ctx->qpiv.as<const int16_t>(), static_cast<double*>(out));
+    else
+      hipLaunchKernelGGL(export_q3_kernel<float>, dim3(unsigned(ctx->Ne)), dim3(512), 0, st,
+                         ctx->blocks.as<const float>(), ctx->qpiv.as<const int16_t>(), static_cast<float*>(out));
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+  }
   if (ctx->blocks_prec == DG_F64)
     hipLaunchKernelGGL((export_blocks_kernel<double, kNB>), dim3(4096), dim3(256), 0, st,
                        ctx->blocks.as<const double>(), static_cast<double*>(out), ctx->Ne);

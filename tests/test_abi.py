@@ -129,8 +129,8 @@ def test_binding_constants_match_the_header_enums():
 
 
 def test_orders_and_workspace_sizes_are_checked_on_the_host(lib):
-    """Orders outside {0, 1, 3} are invalid, and orders 0 and 3 provide the
-    operators only; the workspace of the operator entry points holds the
+    """Orders outside {0, 1, 3} are invalid, order 0 provides the operators
+    only and order 3 the operators and element blocks; the workspace of the operator entry points holds the
     phase map, the status flag, the FP64 linearisation (14 values per node)
     and the output partial sums, each 256-byte aligned."""
     import ctypes as C
@@ -146,6 +146,12 @@ def test_orders_and_workspace_sizes_are_checked_on_the_host(lib):
     assert lib.dg_workspace_bytes(C.byref(mesh3), C.byref(p), None, lsbdg.DG_WS_OPERATORS, C.byref(n)) == 0
     al = lambda x: (x + 255) // 256 * 256
     assert n.value == al(al(al(al(12) + 4) + 14 * 12 * 64 * 8) + 15 * 1024 * 8)
+    # order 3 also sizes its element blocks (FP32 448 x 448 inverses, the
+    # pivot lists and two FP32 7-field probe vectors)
+    feats = lsbdg.DG_WS_OPERATORS | lsbdg.DG_WS_BLOCKS
+    assert lib.dg_workspace_bytes(C.byref(mesh3), C.byref(p), None, feats, C.byref(n)) == 0
+    ops = al(al(al(12) + 4) + 14 * 12 * 64 * 8) + 15 * 1024 * 8
+    assert n.value == al(al(al(al(ops) + 12 * 448 * 448 * 4) + 12 * 448 * 2) + 14 * 12 * 64 * 4)
     mesh = lsbdg.DgMesh(96, 96, 192, 1, 1e-6)
     assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, 64, C.byref(n)) == -1
     assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, lsbdg.DG_WS_OPERATORS, C.byref(n)) == 0

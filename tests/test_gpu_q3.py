@@ -5,8 +5,8 @@ element by element (GPU).  The oracle at k = 3 is pinned on the CPU by
 fourth-order manufactured rates (species, migration and charge rows) and
 its tangent by central differences.  Meshes of 60 and 84 voxels (15 and 21
 workgroups of four voxels, one of them ragged) with structure and pore
-voxels and the separator face.  Entry points beyond the operators refuse
-order 3."""
+voxels and the separator face.  Entry points beyond the operators and the
+element blocks refuse order 3."""
 import numpy as np
 import pytest
 
@@ -78,8 +78,8 @@ def test_q3_entry_points_beyond_the_operators_say_so():
     from paper_2511_05233_amd import lsbdg
     P, ctx, mask, u, _ = _case((3, 2, 2), 4)
     ut = torch.tensor(u, device="cuda:0")
-    for call in (lambda: ctx.step(ut, 0.0, 0.1), lambda: ctx.outputs(ut, 0.0),
-                 lambda: ctx.blockjacobi_setup(ut, 0.1, 0.1), lambda: ctx.limit(ut)):
+    for call in (lambda: ctx.step(ut, 0.0, 0.1), lambda: ctx.outputs(ut, 0.0), lambda: ctx.limit(ut),
+                 lambda: ctx.blockjacobi_apply(ut[:7].float().contiguous(), bf16=True)):
         with pytest.raises(lsbdg.DgError) as ei:
             call()
         assert ei.value.code == -7
