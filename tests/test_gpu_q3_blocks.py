@@ -23,11 +23,15 @@ torch = pytest.importorskip("torch")
 # largest) and FP32 elimination over 448 rows (448 x 6e-8).  The blocks
 # span 1e-55 to 1e-5, so this measure sees mostly the large entries; the
 # inverse itself is also compared with the inverse of the oracle's blocks,
-# relative to its largest entry.  Perturbing the oracle's blocks entrywise
-# by 6e-16 (2e-7) moves that inverse by up to 1e-12 (5e-6) in this measure:
-# bars 1e-10 (FP64) and 5e-4 (FP32).
+# relative to its largest entry.  FP64: perturbing the oracle's blocks
+# entrywise by 6e-16 moves that inverse by up to 1e-12 in this measure (bar
+# 1e-10; measured 8.4e-13).  FP32: the probed blocks carry the FP32
+# operator's errors, about 2e-7 of the element's largest entry and so far
+# larger relative errors on small entries; the inverse of the blocks as
+# probed differs from the GPU's by 2.5e-5 and from the oracle's by 2.7e-4
+# (bar 2e-3).
 TOL = {torch.float64: 1e-12, torch.float32: 1e-4}
-TOL_INV = {torch.float64: 1e-10, torch.float32: 5e-4}
+TOL_INV = {torch.float64: 1e-10, torch.float32: 2e-3}
 
 
 @pytest.fixture(scope="module")
