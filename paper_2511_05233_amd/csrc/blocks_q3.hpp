@@ -11,23 +11,25 @@
 // element: B[e][col][row].
 //
 // Inversion (invert_q3_kernel): blocked in-place Gauss-Jordan with partial
-// pivoting over all unused rows, one 256-lane workgroup per element, in
-// panels of W columns (32 in FP32, 16 in FP64).  For a panel C:
-//   1. the panel's columns go to LDS and W unblocked Gauss-Jordan steps
-//      run on them alone, each choosing as pivot the unused row with the
-//      largest magnitude in its column (ties: the lowest row).  With pivot
-//      rows R this leaves, in the panel columns, E's columns at R, where E
-//      is the row transformation of the W steps (E = I except in columns R;
-//      rows R of E are the inverse of A[R, C]);
+// pivoting over all unused rows, one 512-lane workgroup per element (lane i
+// owns row i), in panels of W columns (64 in FP32, 32 in FP64).  For a
+// panel C:
+//   1. each lane holds its row's W panel entries in registers and W
+//      unblocked Gauss-Jordan steps run on them alone, each choosing as
+//      pivot the unused row with the largest magnitude in its column (ties:
+//      the lowest row).  The registers rotate by one per step, so the
+//      active column is always register 0 and no register is indexed at
+//      run time; the argmax of the next column is taken in the same pass,
+//      and the pivot row reaches the other lanes through LDS: two barriers
+//      per step.  With pivot rows R this leaves, in the panel columns, E's
+//      columns at R, where E is the row transformation of the W steps (E = I
+//      except in columns R; rows R of E are the inverse of A[R, C]);
 //   2. every other column is updated at once with that transformation:
 //      A[i, X] = [i not in R] A[i, X] + sum_s E[i, R_s] A[R_s, X], a
 //      448 x W by W x 448 product on the matrix cores (16 x 16 x 4 MFMA
-//      tiles), the W pivot rows staged in LDS first.
-// This is arithmetically the unblocked algorithm with the same pivots: the
-// in-place result B satisfies A^-1[k][p_m] = B[p_k][m] for the pivot row
-// p_k of step k, which the apply and the export undo with the stored
-// pivot list (448 int16 per element).
-//
+//      tiles).  The panel goes to LDS as the left operand; each wavefront
+//      owns whole 16-column tiles, so it reads the pivot rows' entries of a
+//      tile into registers before it writes any of them.
 // Apply (apply_q3_kernel): y = A^-1 x as z = B x', x'_m = x[p_m], then
 // y_k = z[p_k]; one workgroup per element, lane r = row r, each wavefront
 // reading 64 consecutive rows of a column (256 bytes in FP32).
@@ -46,11 +48,11 @@ template <typename S>
 struct Q3Panel;
 template <>
 struct Q3Panel<float> {
-  static constexpr int W = 32;
+  static constexpr int W = 64;
 };
 template <>
 struct Q3Panel<double> {
-  static constexpr int W = 16;
+  static constexpr int W = 32;
 };
 
 typedef float v4f32 __attribute__((ext_vector_type(4)));
@@ -114,132 +116,131 @@ scatter_q3_kernel(const S* __restrict__ w, S* __restrict__ B, int64_t Ne, int nx
   }
 }
 
+// Largest key over the workgroup's 8 wavefronts (ties: the lowest row):
+// the wavefront's winner goes to red_v / red_i[wave].
+template <typename S>
+__device__ __forceinline__ void q3_pivot_partial(S key, int row, int lane, int wv, S* red_v, int* red_i) {
+  S best = key;
+  int bi = row;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const S ov = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ov > best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    red_v[wv] = best;
+    red_i[wv] = bi;
+  }
+}
+
+// Pivot key of a row: |a| (a NaN counts as 0), compared in S (entries of
+// trace-species rows lie far below the FP32 range); -1 for rows already
+// used and lanes without a row.
+template <typename S>
+__device__ __forceinline__ S q3_key(S a, bool avail) {
+  const S m = fabs(a);
+  return avail ? (m == m ? m : S(0)) : S(-1);
+}
+
 // In-place inversion of every element block (see the header comment); one
 // workgroup per element.  A pivot that is zero or not finite sets *status.
 template <typename S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 invert_q3_kernel(S* __restrict__ B, int16_t* __restrict__ piv, int* __restrict__ status) {
-  constexpr int NB = kQ3NB, W = Q3Panel<S>::W, NT = NB / 16;
+  constexpr int NB = kQ3NB, W = Q3Panel<S>::W, NT = NB / 16, NW = 8;
   static_assert(NB % W == 0 && W % 16 == 0, "panel width");
-  __shared__ S pan[W][NB];      // the panel, column by column
-  __shared__ S G[W][NB];        // the panel's pivot rows before its update
-  __shared__ S prow[W];
-  __shared__ S red_v[4];
-  __shared__ int red_i[4];
+  __shared__ S pan[W][NB];      // the eliminated panel: left operand of the update
+  __shared__ S prow[W];         // the pivot row of the current step (rotated as the registers)
+  __shared__ S red_v[NW];
+  __shared__ int red_i[NW];
   __shared__ int pivl[W];
-  __shared__ uint8_t used[NB];  // row was a pivot
   __shared__ uint8_t inpan[NB]; // row is a pivot of the current panel
-  __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool has_row = tid < NB;
   const int64_t e = blockIdx.x;
   S* __restrict__ Be = B + e * int64_t(NB) * NB;
-  for (int i = tid; i < NB; i += 256) {
-    used[i] = 0;
-    inpan[i] = 0;
-  }
-  if (tid == 0) bad = 0;
-  __syncthreads();
+  bool used = false, bad = false;
+  if (has_row) inpan[tid] = 0;
+  S r[W];
 #pragma unroll 1
   for (int c0 = 0; c0 < NB; c0 += W) {
-    for (int k = tid; k < W * NB; k += 256) {
-      const int t = k / NB, i = k - t * NB;
-      pan[t][i] = Be[int64_t(c0 + t) * NB + i];
-    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) r[j] = has_row ? Be[int64_t(c0 + j) * NB + tid] : S(0);
+    q3_pivot_partial(q3_key(r[0], has_row && !used), tid, lane, wv, red_v, red_i);
     __syncthreads();
 #pragma unroll 1
     for (int t = 0; t < W; ++t) {
-      // pivot: the unused row of largest magnitude (a NaN counts as 0),
-      // compared in S: entries of trace-species rows lie far below the FP32
-      // range, where a narrower key would tie them all
-      S best = S(-1);
-      int bi = NB;
-      for (int i = tid; i < NB; i += 256) {
-        if (used[i]) continue;
-        const S a = fabs(pan[t][i]);
-        const S key = a == a ? a : S(0);
-        if (key > best) {
-          best = key;
-          bi = i;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const S ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        red_v[wv] = best;
-        red_i[wv] = bi;
-      }
-      __syncthreads();
       S bv = red_v[0];
       int p = red_i[0];
 #pragma unroll
-      for (int w = 1; w < 4; ++w)
+      for (int w = 1; w < NW; ++w)
         if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < p)) {
           bv = red_v[w];
           p = red_i[w];
         }
-      if (tid < W) prow[tid] = pan[tid][p];
-      __syncthreads();
-      const S pv = prow[t];
+      const bool me = tid == p;
+      if (me) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) prow[j] = r[j];
+        inpan[p] = 1;
+        used = true;
+      }
       if (tid == 0) {
         pivl[t] = p;
-        used[p] = 1;
-        inpan[p] = 1;
         piv[e * NB + c0 + t] = int16_t(p);
-        if (!(fabs(pv) > S(0)) || !isfinite(pv)) bad = 1;
-      }
-      const S inv = S(1) / pv;
-      for (int i = tid; i < NB; i += 256) {
-        const S f = pan[t][i];
-        if (i == p) {
-          for (int s = 0; s < W; ++s) pan[s][i] = s == t ? inv : prow[s] * inv;
-        } else {
-          for (int s = 0; s < W; ++s) pan[s][i] = s == t ? -f * inv : pan[s][i] - f * (prow[s] * inv);
-        }
       }
       __syncthreads();
+      const S pv = prow[0];
+      if (!(fabs(pv) > S(0)) || !isfinite(pv)) bad = true;
+      const S inv = S(1) / pv;
+      const S f = r[0];
+#pragma unroll
+      for (int j = 1; j < W; ++j) {
+        const S pr = prow[j] * inv;
+        r[j - 1] = me ? pr : r[j] - f * pr;
+      }
+      r[W - 1] = me ? inv : -f * inv;
+      if (t + 1 < W) q3_pivot_partial(q3_key(r[0], has_row && !used), tid, lane, wv, red_v, red_i);
+      __syncthreads();
     }
-    // the pivot rows as they stand before this panel's update
-    for (int k = tid; k < W * NB; k += 256) {
-      const int s = k / NB, j = k - s * NB;
-      G[s][j] = Be[int64_t(j) * NB + pivl[s]];
+    // W rotations: register j holds panel column j again
+    if (has_row) {
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        pan[j][tid] = r[j];
+        Be[int64_t(c0 + j) * NB + tid] = r[j];
+      }
     }
     __syncthreads();
-    // every column outside the panel: A[i, j] = [i not in R] A[i, j] + sum_s pan[s][i] G[s][j]
-    for (int tile = wv; tile < NT * NT; tile += 4) {
-      const int it = tile % NT, jt = tile / NT;
-      const int i0 = it * 16, j0 = jt * 16;
+    for (int jt = wv; jt < NT; jt += NW) {
+      const int j0 = jt * 16;
       if (j0 >= c0 && j0 < c0 + W) continue;
-      typename Acc4<S>::T acc = {S(0), S(0), S(0), S(0)};
-#pragma unroll
-      for (int kk = 0; kk < W / 4; ++kk) {
-        const S a = pan[4 * kk + (lane >> 4)][i0 + (lane & 15)];
-        const S b = G[4 * kk + (lane >> 4)][j0 + (lane & 15)];
-        mfma_16x16x4(a, b, acc);
-      }
       const int j = j0 + (lane & 15);
+      S* __restrict__ colj = Be + int64_t(j) * NB;
+      S g[W / 4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + mfma_row<S>(lane, v);
-        S* q = Be + int64_t(j) * NB + i;
-        *q = (inpan[i] ? S(0) : *q) + acc[v];
+      for (int kk = 0; kk < W / 4; ++kk) g[kk] = colj[pivl[4 * kk + (lane >> 4)]];
+#pragma unroll 1
+      for (int it = 0; it < NT; ++it) {
+        const int i0 = it * 16;
+        typename Acc4<S>::T acc = {S(0), S(0), S(0), S(0)};
+#pragma unroll
+        for (int kk = 0; kk < W / 4; ++kk) mfma_16x16x4(pan[4 * kk + (lane >> 4)][i0 + (lane & 15)], g[kk], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + mfma_row<S>(lane, v);
+          colj[i] = (inpan[i] ? S(0) : colj[i]) + acc[v];
+        }
       }
     }
-    for (int k = tid; k < W * NB; k += 256) {
-      const int t = k / NB, i = k - t * NB;
-      Be[int64_t(c0 + t) * NB + i] = pan[t][i];
-    }
     __syncthreads();
-    if (tid < W) inpan[pivl[tid]] = 0;
-    __syncthreads();
+    if (has_row) inpan[tid] = 0;
   }
-  if (tid == 0 && bad) atomicOr(status, 1);
+  if (bad && tid == 0) atomicOr(status, 1);
 }
 
 // y_e = A_e^-1 x_e for 7-field vectors [f][e][n] (n < 64); one workgroup of

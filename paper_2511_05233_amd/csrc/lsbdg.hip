@@ -366,7 +366,7 @@ int blocks_setup_q3(dg_ctx* ctx, const DevParams& P, const S* uS, hipStream_t st
     }
   DG_HIP(hipGetLastError());
   DG_HIP(hipMemsetAsync(ctx->status.p, 0, sizeof(int), st));
-  hipLaunchKernelGGL(invert_q3_kernel<S>, dim3(unsigned(Ne)), dim3(256), 0, st, B, ctx->qpiv.as<int16_t>(),
+  hipLaunchKernelGGL(invert_q3_kernel<S>, dim3(unsigned(Ne)), dim3(512), 0, st, B, ctx->qpiv.as<int16_t>(),
                      ctx->status.as<int>());
   DG_HIP(hipGetLastError());
   int h_status = 0;
