@@ -17,7 +17,8 @@
  * (Eq. 05-06, 18-24).  Space: interior-penalty DG with harmonic-mean
  * coefficients (Eq. 43-47) on tensor-product Gauss-Legendre nodes of degree
  * k per axis: k = 1 (Q1, 8 nodes per voxel) for every entry point, k = 0
- * (Eq. 48) and k = 3 (64 nodes) for the operators; time: backward Euler
+ * (Eq. 48) for the operators, k = 3 (64 nodes) for the operators and the
+ * element block-Jacobi preconditioner; time: backward Euler
  * (Eq. 50).  The separator face
  * x = L_x receives the Li+ flux j_el/F and the ionic current j_el; all other
  * faces are no-flux (Eq. 47 with the paper's galvanostatic condition).
@@ -114,8 +115,9 @@ void dg_params_default(dg_params* p);
  *   mesh   mesh and degree: order 1 (Q1: every entry point); order 0
  *          (the finite-volume scheme of Eq. 48) and order 3 (tricubic,
  *          4 x 4 x 4 Gauss nodes per voxel, Eq. 43-47 with sigma = 16): the
- *          operators dg_mass, dg_residual, dg_linearize and dg_jvp; the
- *          other entry points return DG_EUNSUPPORTED for them
+ *          operators dg_mass, dg_residual, dg_linearize and dg_jvp, and at
+ *          order 3 also dg_blockjacobi_setup/apply/export/info; the other
+ *          entry points return DG_EUNSUPPORTED for them
  *   phase  HOST array of nx*ny*nz bytes, x fastest: 0 = pore voxel
  *          (electrolyte only, no reactions), 1 = cathode structure voxel
  *          (Eq. 57 localisation); copied, may be freed after the call
@@ -171,17 +173,22 @@ int dg_linearize(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double 
  * preconditioner of Sec. 2.9 inside GMRES).  Builds the exact
  * element-diagonal blocks of the condensed 7-field Jacobian at (u, t_new,
  * dt) -- volume, own-face, time and source terms of each voxel's rows with
- * respect to its own 56 unknowns (Q1) -- and inverts them in place (Gauss-
- * Jordan with partial pivoting) into library-owned device storage of
- * Ne * 56 * 56 values of precision prec (FP32 at the 96x96x192 slab: 22 GB).
+ * respect to its own nb = 7 * nodes unknowns (56 at k = 1, 448 at k = 3) --
+ * and inverts them in place (Gauss-Jordan with partial pivoting) into
+ * library-owned device storage of Ne * nb * nb values of precision prec
+ * (FP32: 22 GB for the 96x96x192 slab at k = 1, 88.8 GB for 48^3 voxels
+ * at k = 3).  At k = 3 the blocks are probed from the Krylov operator
+ * (2 x 448 applications, one checkerboard colour at a time; the
+ * linearisation at u is left stored) and inverted by a blocked
+ * Gauss-Jordan on the matrix cores, keeping a pivot list of Ne * 448 int16.
  * Synchronises the stream.  DG_ENAN if a block is singular or not finite;
- * DG_EUNSUPPORTED for orders other than 1. */
+ * DG_EUNSUPPORTED at order 0. */
 int dg_blockjacobi_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt,
                          dg_stream stream);
 
 /* y_e = B_e^{-1} x_e for every voxel e, with the blocks of the last setup.
  * x, y: device, 7 fields, precision of the setup (DG_EINVAL otherwise;
- * DG_ESTATE before any setup). x and y must not overlap. */
+ * DG_ESTATE before any setup). x and y must not overlap.  Orders 1 and 3. */
 int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_stream stream);
 
 /* As dg_blockjacobi_apply after an FP32 setup, but streaming a bfloat16
@@ -193,17 +200,18 @@ int dg_blockjacobi_apply(dg_ctx* ctx, dg_prec prec, const void* x, void* y, dg_s
  * bfloat16 copy, which this call then applies, and leave no FP32 inverses
  * (dg_blockjacobi_apply then needs a new setup).  x, y: device, FP32,
  * 7 fields, not overlapping.  DG_ESTATE without an FP32 setup or such a
- * solve before. */
+ * solve before; DG_EUNSUPPORTED at orders other than 1. */
 int dg_blockjacobi_apply_bf16(dg_ctx* ctx, const void* x, void* y, dg_stream stream);
 
-/* Copy the stored inverse blocks (Ne blocks of 56 x 56, column-major:
- * out[e][col][row], row/col = field * 8 + node) to the device buffer out,
- * in the precision of the setup (dg_blockjacobi_info); out must hold
- * Ne * 56 * 56 values of that precision.  DG_ESTATE when no inverses are
+/* Copy the stored inverse blocks (Ne blocks of nb x nb, column-major:
+ * out[e][col][row], row/col = field * nodes + node; at k = 3 with the
+ * pivoting undone) to the device buffer out, in the precision of the setup
+ * (dg_blockjacobi_info); out must hold Ne * nb * nb values of that
+ * precision.  DG_ESTATE when no inverses are
  * stored (none set up, or only the bfloat16 copy of a solve). */
 int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream);
 
-/* Precision (DG_F64 or DG_F32) and edge (56) of the stored inverse blocks,
+/* Precision (DG_F64 or DG_F32) and edge (56, or 448 at k = 3) of the stored inverse blocks,
  * so that a caller sizes the buffer of dg_blockjacobi_export from the
  * library's own state.  Host call, no device work.  DG_ESTATE when no
  * inverses are stored. */
@@ -275,7 +283,7 @@ void dg_solver_opts_default(dg_solver_opts* o);
  * (dg_batch_*) allocate their own storage. */
 typedef enum {
   DG_WS_OPERATORS = 1,  /* dg_mass, dg_residual, dg_jvp, dg_linearize, dg_outputs */
-  DG_WS_BLOCKS = 2,     /* dg_blockjacobi_setup/apply/export in opts->inner_prec */
+  DG_WS_BLOCKS = 2,     /* dg_blockjacobi_setup/apply/export in opts->inner_prec (k = 1, 3) */
   DG_WS_STEP = 4,       /* dg_step, dg_initial_state with opts */
   DG_WS_NAIVE = 8,      /* dg_advance, naive controller (one saved state) */
   DG_WS_H211B = 16,     /* dg_advance, H211b (three saved states) */
@@ -288,7 +296,9 @@ typedef enum {
  * call (it queries rocSOLVER for the scratch of the coarse LU).  The
  * slab of 96 x 96 x 192 voxels with FP32 inner solves, bfloat16 inverses
  * and the naive controller needs about 60 GB.  Errors: DG_EINVAL (null
- * pointer, mesh, unknown feature bits, bad options). */
+ * pointer, mesh, unknown feature bits, bad options); DG_EUNSUPPORTED for
+ * uses beyond DG_WS_OPERATORS at order 0 and beyond DG_WS_OPERATORS |
+ * DG_WS_BLOCKS at order 3. */
 int dg_workspace_bytes(const dg_mesh* mesh, const dg_params* params, const dg_solver_opts* opts,
                        int32_t features, size_t* bytes);
 
