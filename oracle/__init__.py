@@ -29,6 +29,10 @@ What it computes, in the paper's order and notation (arXiv 2511.05233):
                     (Eq. 51-54).
 * outputs.py     -- cell voltage, volume means (Eq. A1-A3) and the discrete
                     conservation invariants.
+* multigrid.py   -- the multilevel aggregation preconditioner of the Krylov
+                    system (the GPU stand-in for the algebraic multigrid of
+                    Sec. 2.9): Galerkin operators on nested voxel aggregates,
+                    damped block-Jacobi smoothing, the V-cycle.
 
 Every function is written to accept complex input where it can be reached
 by a complex-step derivative: comparisons look at real parts only.
