@@ -421,7 +421,7 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
     ctx = lsbdg.Context(w.nx, w.ny, w.nz, w.h, w.order, w.mask(), D0=D0, kE=i0 / FARADAY, f_C=f_C)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    u, _ = ctx.initial_state(inner=inner, coarse=coarse, coarse_agg=coarse_agg)
+    u, _ = ctx.initial_state(inner=inner, coarse=coarse, coarse_agg=coarse_agg, **SOLVER_EXTRA)
     ctrl = lsbdg.controller("naive", dt0=dt0)
     t, t_end = 0.0, 3600.0 / f_C
     tot = {"steps": 0, "trials": 0, "halvings": 0, "newton_its": 0, "gmres_its": 0}
@@ -432,7 +432,8 @@ def discharge(workload, f_C, inner, coarse, coarse_agg, log, dt0=0.1, cutoff=1.9
             break
         if t_stop is not None and t >= t_stop:
             break
-        t, rep = ctx.advance(ctrl, t, u, inner=inner, coarse=coarse, coarse_agg=coarse_agg, limiter=limiter)
+        t, rep = ctx.advance(ctrl, t, u, inner=inner, coarse=coarse, coarse_agg=coarse_agg, limiter=limiter,
+                             **SOLVER_EXTRA)
         for k in ("trials", "halvings", "newton_its", "gmres_its"):
             tot[k] += rep[k]
         tot["steps"] += 1
@@ -799,6 +800,10 @@ def main(argv=None):
     ap.add_argument("--step-only", action="store_true",
                     help="time the steps only (no kernel timings, comparisons or baselines): "
                          "the run a kernel trace of the timed step is taken on")
+    ap.add_argument("--mg-levels", type=int, default=0,
+                    help="coarse solve by a V-cycle over this many aggregate levels (2..8; level-1 edge "
+                         "--coarse-agg, 0: 4)")
+    ap.add_argument("--mg-sweeps", type=int, default=2, help="block-Jacobi sweeps per level of the V-cycle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--oracle-timing", nargs=2, metavar=("WORKLOAD", "SECONDS"), default=None,
@@ -809,6 +814,9 @@ def main(argv=None):
         return 0
     if args.fp32_blocks:
         SOLVER_EXTRA["block_bf16"] = 0
+    if args.mg_levels:
+        SOLVER_EXTRA["mg_levels"] = args.mg_levels
+        SOLVER_EXTRA["mg_sweeps"] = args.mg_sweeps
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; "
               "run with --gpus 1.", file=sys.stderr)
@@ -933,7 +941,8 @@ def main(argv=None):
                             "FP64 update" if args.mode == "newton" else
                             "accepted step of the naive time controller (backward-Euler Newton-GMRES "
                             "solves, halving dt on failure)"),
-                   "coarse": args.coarse, "coarse_agg": args.coarse_agg, "timed_steps": done, **{k: v for k, v in tot.items()}},
+                   "coarse": args.coarse, "coarse_agg": args.coarse_agg, "mg_levels": args.mg_levels,
+                   "mg_sweeps": args.mg_sweeps if args.mg_levels else None, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(w.name, k_op),

@@ -262,9 +262,67 @@ typedef struct {
                             to zero and continue additively (roots with
                             negative nodal values are reached before
                             limiting).  0 (default): no limiter */
+  int32_t mg_levels;     /* coarse = 3, 4: 0 (default) solves the coarse
+                            system exactly (dense LU); 2..8 replaces that
+                            solve by one V-cycle over mg_levels levels of
+                            nested voxel aggregates (the multigrid stand-in
+                            for Sec. 2.9's algebraic multigrid): level 1 has
+                            aggregates of coarse_agg voxels per edge (0: 4),
+                            each further level groups 2 x 2 x 2 aggregates
+                            of the one above, operators are Galerkin
+                            products, the last level (at most 8192
+                            unknowns) is solved exactly; see dg_mg_setup */
+  int32_t mg_sweeps;     /* damped block-Jacobi sweeps before and after each
+                            coarse correction of the cycle, 0..8 (default 2) */
+  double mg_omega;       /* their damping, in (0, 1] (default 0.7) */
 } dg_solver_opts;
 
 void dg_solver_opts_default(dg_solver_opts* o);
+
+/* ---- Multilevel coarse correction (multigrid for the elliptic coupling) ----
+ *
+ * The paper preconditions its Krylov solves with algebraic multigrid,
+ * tuned for the potential coupling (Sec. 2.9).  Here the coarse correction
+ * of the element block-Jacobi preconditioner can be a V-cycle over nested
+ * voxel aggregates (dg_solver_opts.mg_levels); these two calls expose that
+ * cycle on its own, with unit basis weights:
+ *   Z (fine -> level 1): 1 on every node of a field's aggregate;
+ *   P_l (level l+1 -> l): 1 from a parent aggregate to each of its
+ *     (up to) 2 x 2 x 2 children; coarse vectors are (field, aggregate),
+ *     aggregates x fastest;
+ *   E_1 = Z^T J Z with J the condensed 7-field tangent at u (the Krylov
+ *     operator, DG_JVP_LINEARIZED7), E_{l+1} = P_l^T E_l P_l;
+ *   V-cycle: on every level but the last, opts->mg_sweeps damped
+ *     block-Jacobi sweeps x <- x + mg_omega D^-1 (b - E x) from x = 0 (D:
+ *     the 7 x 7 blocks of one aggregate's fields), the next level's cycle on
+ *     P^T (b - E x), its prolongation added, mg_sweeps more sweeps; the
+ *     last level solved exactly (FP64 LU of the equilibrated operator).
+ * Level operators and vectors are FP64 whatever prec is.
+ *
+ * dg_mg_setup: linearises at u (as dg_linearize, precision prec; u: 9
+ * fields) and builds the hierarchy for opts->mg_levels (2..8) levels with
+ * level-1 aggregates of opts->coarse_agg voxels per edge (0: 4).  Replaces
+ * the stored linearisation.  Q1 only.  Synchronises the stream.  Errors:
+ * DG_EINVAL (null array, dt <= 0, bad precision or options, a last level
+ * of more than 8192 unknowns), DG_EUNSUPPORTED (order != 1), DG_ENOMEM,
+ * DG_ENAN (singular last level), DG_EHIP.  A later dg_step with
+ * mg_levels >= 2 reuses these buffers and ends this hierarchy's validity.
+ *
+ * dg_mg_apply: out = Z V_1(Z^T r) for 7-field vectors r, out of precision
+ * prec (that of the setup); out is overwritten.  Errors: DG_EINVAL (null
+ * array, other precision), DG_ESTATE (no current dg_mg_setup). */
+int dg_mg_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt, const dg_solver_opts* opts,
+                dg_stream stream);
+int dg_mg_apply(dg_ctx* ctx, dg_prec prec, const void* r, void* out, dg_stream stream);
+
+/* The operator E_level (level 1..mg_levels) of the current dg_mg_setup
+ * hierarchy, copied to the device array out of n >= 343 na doubles (na:
+ * the level's aggregates), as seven 7 x 7 blocks per aggregate:
+ * out[((s 7 + g) 7 + f) na + a] = E[(g, a), (f, neighbour s of a)], slots
+ * s = itself, -x, +x, -y, +y, -z, +z (zero where the neighbour lies
+ * outside).  Errors: DG_EINVAL (null array, level, n too small), DG_ESTATE
+ * (no current setup). */
+int dg_mg_export(dg_ctx* ctx, int32_t level, double* out, int64_t n, dg_stream stream);
 
 /* ---- Caller-owned device workspace ----
  *
@@ -288,7 +346,8 @@ typedef enum {
   DG_WS_NAIVE = 8,      /* dg_advance, naive controller (one saved state) */
   DG_WS_H211B = 16,     /* dg_advance, H211b (three saved states) */
   DG_WS_LIMITER = 32,   /* dg_limit (implied for steps when opts->limiter = 1) */
-  DG_WS_ALL = 63
+  DG_WS_MG = 64,        /* dg_mg_setup/apply with opts->mg_levels, coarse_agg */
+  DG_WS_ALL = 127
 } dg_workspace_use;
 
 /* Bytes of device workspace a dg_setup_ws context of this mesh needs for

@@ -34,6 +34,7 @@
 #include "outputs.hpp"
 #include "limiter.hpp"
 #include "coarse.hpp"
+#include "multigrid.hpp"
 #include "batch.hpp"
 
 #include <rocblas/rocblas.h>
@@ -72,6 +73,18 @@ struct dg_ctx {
   int lin_prec = -1;
   DevBuf status;                    // singular-block flag of the block setup
   SolverWork work;
+  // multilevel coarse correction (multigrid.hpp): level grids, stencil
+  // operators, inverses of their self blocks, right sides and two iterates
+  // per level; unit scales and two probe vectors of dg_mg_setup
+  struct Multigrid {
+    int levels = 0, nu = 2;
+    double omega = 0.7;
+    AggGrid G{};                      // level-1 aggregates on the voxels
+    MgGrid g[kMgMaxLevels]{};
+    DevBuf E[kMgMaxLevels], Dinv[kMgMaxLevels], b[kMgMaxLevels], xa[kMgMaxLevels], xb[kMgMaxLevels];
+    DevBuf ones, pv, pjv;
+    int prec = -1;                    // precision of a dg_mg_setup hierarchy (-1: none current)
+  } mg;
   // caller-owned workspace (dg_setup_ws): every DevBuf above is carved from it
   Arena arena;
   bool owns_memory = true;
@@ -79,6 +92,9 @@ struct dg_ctx {
   void for_each_buf(F f) {
     for (DevBuf* d : {&phase, &blocks, &qpiv, &probe, &lin, &cE, &cX, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
       f(*d);
+    for (int l = 0; l < kMgMaxLevels; ++l)
+      for (DevBuf* d : {&mg.E[l], &mg.Dinv[l], &mg.b[l], &mg.xa[l], &mg.xb[l]}) f(*d);
+    for (DevBuf* d : {&mg.ones, &mg.pv, &mg.pjv}) f(*d);
     work.for_each(f);
   }
   // GMRES cycle: pinned done flags of the last two iterations and their events
@@ -422,12 +438,47 @@ AggGrid coarse_grid(const dg_mesh& mesh, const dg_solver_opts& o) {
   int A = o.coarse_agg;
   if (A <= 0) {
     A = 4;
-    while (7 * naggs(A) > 8192) ++A;
+    if (o.mg_levels < 2)
+      while (7 * naggs(A) > 8192) ++A;
   }
   G.nx = nx; G.ny = ny; G.nz = nz; G.A = A;
   G.nax = (nx + A - 1) / A; G.nay = (ny + A - 1) / A; G.naz = (nz + A - 1) / A;
   G.na = naggs(A);
   return G;
+}
+
+// Level grids of the multilevel coarse correction: the level-1 aggregates
+// of G, then 2 x 2 x 2 groups of the level above.
+void mg_grids(const AggGrid& G, int levels, MgGrid* g) {
+  g[0] = MgGrid{G.nax, G.nay, G.naz, 0, G.na};
+  for (int l = 1; l < levels; ++l) g[l] = mg_coarser(g[l - 1]);
+}
+
+// Unknowns of the dense coarse solve: the aggregation coarse space itself,
+// or the last level of the multilevel correction.
+int64_t coarse_dense_size(const dg_mesh& mesh, const dg_solver_opts& o) {
+  const AggGrid G = coarse_grid(mesh, o);
+  if (o.mg_levels < 2) return 7 * G.na;
+  MgGrid g[kMgMaxLevels];
+  mg_grids(G, o.mg_levels, g);
+  return 7 * g[o.mg_levels - 1].na;
+}
+
+// Device buffers of the multilevel levels (FP64): stencil operators on
+// every level, inverses of the self blocks on all but the last, a right
+// side and two iterates per level.
+std::vector<std::pair<DevBuf*, size_t>> mg_buffers(dg_ctx* ctx, int levels, const MgGrid* g) {
+  std::vector<std::pair<DevBuf*, size_t>> out;
+  auto& M = ctx->mg;
+  for (int l = 0; l < levels; ++l) {
+    const size_t na = size_t(g[l].na);
+    out.push_back(std::make_pair(&M.E[l], 343 * na * 8));
+    if (l + 1 < levels) out.push_back(std::make_pair(&M.Dinv[l], 49 * na * 8));
+    out.push_back(std::make_pair(&M.b[l], 7 * na * 8));
+    out.push_back(std::make_pair(&M.xa[l], 7 * na * 8));
+    out.push_back(std::make_pair(&M.xb[l], 7 * na * 8));
+  }
+  return out;
 }
 
 std::vector<std::pair<DevBuf*, size_t>> coarse_buffers(dg_ctx* ctx, int64_t nc) {
@@ -489,7 +540,22 @@ std::vector<std::pair<DevBuf*, size_t>> plan_workspace(dg_ctx* ctx, const dg_sol
   if (step) {
     for (const auto& pr : solver_buffers(ctx, o, sS)) out.push_back(pr);
     if (o.coarse == 3 || o.coarse == 4) {
-      nc = 7 * coarse_grid(ctx->mesh, o).na;
+      nc = coarse_dense_size(ctx->mesh, o);
+      for (const auto& pr : coarse_buffers(ctx, nc)) out.push_back(pr);
+      need_rocsolver = true;
+    }
+  }
+  if ((features & DG_WS_MG) || (step && (o.coarse == 3 || o.coarse == 4) && o.mg_levels >= 2)) {
+    MgGrid g[kMgMaxLevels];
+    mg_grids(coarse_grid(ctx->mesh, o), o.mg_levels, g);
+    for (const auto& pr : mg_buffers(ctx, o.mg_levels, g)) out.push_back(pr);
+  }
+  if (features & DG_WS_MG) {
+    // dg_mg_setup / dg_mg_apply: unit scales, two probe vectors, the dense
+    // last level (shared with the solver's when both are planned)
+    for (DevBuf* d : {&ctx->mg.ones, &ctx->mg.pv, &ctx->mg.pjv}) out.push_back(std::make_pair(d, size_t(7) * FS * sS));
+    if (!need_rocsolver) {
+      nc = coarse_dense_size(ctx->mesh, o);
       for (const auto& pr : coarse_buffers(ctx, nc)) out.push_back(pr);
       need_rocsolver = true;
     }
@@ -502,6 +568,116 @@ std::vector<std::pair<DevBuf*, size_t>> plan_workspace(dg_ctx* ctx, const dg_sol
     out.push_back(std::make_pair(&ctx->work.zF, size_t(9) * FS * 8));
   }
   return out;
+}
+
+// Explicit inverse of the equilibrated coarse operator: cE holds the
+// dense nc x nc operator (column-major); afterwards cd holds the
+// equilibration d and cX the inverse of D cE D (rocSOLVER LU, then the
+// solve of its factors against the identity: level-3 triangular solves,
+// where an in-place inverse runs on latency-bound panels).
+int coarse_dense_inverse(dg_ctx* ctx, int64_t nc, hipStream_t st) {
+  const dim3 blk{256, 1, 1};
+  double* cE = ctx->cE.as<double>();
+  double* cX = ctx->cX.as<double>();
+  double* cd = ctx->cd.as<double>();
+  rocblas_int* cipiv = ctx->cipiv.as<rocblas_int>();
+  rocblas_int* cinfo = ctx->cinfo.as<rocblas_int>();
+  hipLaunchKernelGGL(coarse_diag_kernel, grid1(nc), blk, 0, st, cE, nc, nc, cd);
+  hipLaunchKernelGGL(coarse_scale_kernel, dim3(8192), blk, 0, st, cE, nc, nc, cd);
+  DG_HIP(hipGetLastError());
+  if (rocsolver_dgetrf(ctx->blas, rocblas_int(nc), rocblas_int(nc), cE, rocblas_int(nc), cipiv, cinfo) !=
+      rocblas_status_success)
+    return fail(DG_EHIP, "rocsolver_dgetrf failed");
+  rocblas_int hinfo = 0;
+  DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  DG_HIP(hipStreamSynchronize(st));
+  if (hinfo != 0) return fail(DG_ENAN, "singular aggregation coarse operator");
+  hipLaunchKernelGGL(identity_kernel, dim3(8192), blk, 0, st, cX, nc);
+  if (rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), rocblas_int(nc), cE, rocblas_int(nc),
+                       cipiv, cX, rocblas_int(nc)) != rocblas_status_success)
+    return fail(DG_EHIP, "rocsolver_dgetrs failed");
+  return DG_OK;
+}
+
+// Multilevel hierarchy at the stored linearisation (precision S; the
+// context's mg levels, grids, sweeps and damping set): level 1 from 7 x 7
+// coloured probes of the Krylov operator with basis scales `scales`
+// (fields outside `active` keep zero rows and columns), the Galerkin
+// products, the inverses of the self blocks and the explicit inverse of
+// the last level.  v, Jv: two 7-field vectors of scratch.
+template <typename S>
+int mg_build(dg_ctx* ctx, const DevParams& P, const S* uS, const S* scales, S* v, S* Jv, int active,
+             hipStream_t st) {
+  auto& M = ctx->mg;
+  const int L = M.levels;
+  const int64_t FS = ctx->Ne * ctx->np;
+  const dim3 blk{256, 1, 1};
+  hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(343 * M.g[0].na), blk, 0, st, M.E[0].as<double>(), 343 * M.g[0].na, 0.0);
+  for (int f = 0; f < 7; ++f) {
+    if (!((active >> f) & 1)) continue;
+    for (int c = 0; c < 7; ++c) {
+      hipLaunchKernelGGL(agg_probe_kernel<S>, grid1(7 * FS), blk, 0, st, scales, f, c, M.G, FS, v);
+      launch_brick_jvp<S>(ctx, P, uS, v, ctx->lin.p, Jv, st);
+      hipLaunchKernelGGL(mg_probe_stencil_kernel<S>, dim3(unsigned(M.G.na)), blk, 0, st, scales, Jv, f, c, M.G, FS,
+                         M.E[0].as<double>());
+    }
+  }
+  for (int l = 1; l < L; ++l)
+    hipLaunchKernelGGL(mg_galerkin_kernel, mg_grid(49 * M.g[l].na), blk, 0, st, M.E[l - 1].as<const double>(),
+                       M.g[l - 1], M.E[l].as<double>(), M.g[l]);
+  for (int l = 0; l + 1 < L; ++l)
+    hipLaunchKernelGGL(mg_block_inverse_kernel, mg_grid(M.g[l].na), blk, 0, st, M.E[l].as<const double>(), M.g[l].na,
+                       M.Dinv[l].as<double>());
+  const int64_t nc = 7 * M.g[L - 1].na;
+  hipLaunchKernelGGL(mg_fill_kernel<double>, dim3(8192), blk, 0, st, ctx->cE.as<double>(), nc * nc, 0.0);
+  hipLaunchKernelGGL(mg_dense_kernel, grid1(343 * M.g[L - 1].na), blk, 0, st, M.E[L - 1].as<const double>(),
+                     M.g[L - 1], ctx->cE.as<double>());
+  DG_HIP(hipGetLastError());
+  return coarse_dense_inverse(ctx, nc, st);
+}
+
+// One V-cycle of the multilevel correction on the right side in mg.b[0];
+// returns the level-1 result (one of the level's two iterates).
+const double* mg_vcycle(dg_ctx* ctx, hipStream_t st) {
+  auto& M = ctx->mg;
+  const int L = M.levels;
+  const dim3 blk{256, 1, 1};
+  double* cur[kMgMaxLevels] = {};
+  auto sweep = [&](int l, double*& x) {
+    double* out = (x == M.xa[l].as<double>()) ? M.xb[l].as<double>() : M.xa[l].as<double>();
+    hipLaunchKernelGGL(mg_smooth_kernel, mg_grid(M.g[l].na), blk, 0, st, M.E[l].as<const double>(),
+                       M.Dinv[l].as<const double>(), M.g[l], M.b[l].as<const double>(),
+                       static_cast<const double*>(x), out, M.omega);
+    x = out;
+  };
+  for (int l = 0; l + 1 < L; ++l) {
+    double* x = nullptr;                      // zero
+    for (int k = 0; k < M.nu; ++k) sweep(l, x);
+    hipLaunchKernelGGL(mg_residual_restrict_kernel, mg_grid(M.g[l + 1].na), blk, 0, st, M.E[l].as<const double>(),
+                       M.g[l], M.b[l].as<const double>(), static_cast<const double*>(x), M.g[l + 1],
+                       M.b[l + 1].as<double>());
+    cur[l] = x;
+  }
+  const int64_t nc = 7 * M.g[L - 1].na;
+  const int64_t chunk = (nc + kCoarseChunks - 1) / kCoarseChunks;
+  hipLaunchKernelGGL(coarse_gemv_partial_kernel, dim3(unsigned((nc + 255) / 256), kCoarseChunks, 1), blk, 0, st,
+                     ctx->cX.as<const double>(), nc, M.b[L - 1].as<const double>(), ctx->cd.as<const double>(), chunk,
+                     ctx->cpart.as<double>());
+  hipLaunchKernelGGL(coarse_gemv_finish_kernel, grid1(nc), blk, 0, st, ctx->cpart.as<const double>(), nc,
+                     ctx->cd.as<const double>(), M.xa[L - 1].as<double>());
+  cur[L - 1] = M.xa[L - 1].as<double>();
+  for (int l = L - 2; l >= 0; --l) {
+    double* x = cur[l];
+    if (!x) {
+      x = M.xa[l].as<double>();
+      hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(7 * M.g[l].na), blk, 0, st, x, 7 * M.g[l].na, 0.0);
+    }
+    hipLaunchKernelGGL(mg_prolong_add_kernel, mg_grid(M.g[l].na), blk, 0, st, static_cast<const double*>(cur[l + 1]),
+                       M.g[l + 1], M.g[l], x);
+    for (int k = 0; k < M.nu; ++k) sweep(l, x);
+    cur[l] = x;
+  }
+  return cur[0];
 }
 
 template <typename S>
@@ -552,10 +728,23 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   AggGrid G{};
   int64_t nc = 0;
   const bool agg = (o.coarse == 3 || o.coarse == 4);
+  const bool mgm = agg && o.mg_levels >= 2;    // the coarse solve by a multilevel V-cycle
+  auto& MG = ctx->mg;
   if (agg) {
     G = coarse_grid(ctx->mesh, o);
-    nc = 7 * G.na;
+    nc = coarse_dense_size(ctx->mesh, o);
     if (nc > (int64_t(1) << 20)) return fail(DG_EINVAL, "dg_step: coarse space too large (raise coarse_agg)");
+    if (mgm) {
+      if (nc > 8192) return fail(DG_EINVAL, "dg_step: the last multigrid level has more than 8192 unknowns (add levels)");
+      MG.prec = -1;                              // the hierarchy becomes the solver's
+      MG.levels = o.mg_levels;
+      MG.nu = o.mg_sweeps;
+      MG.omega = o.mg_omega;
+      MG.G = G;
+      mg_grids(G, MG.levels, MG.g);
+      for (const auto& pr : mg_buffers(ctx, MG.levels, MG.g))
+        if (pr.first->ensure(pr.second) != hipSuccess) return fail_mem(ctx, "multigrid levels", pr.second);
+    }
     for (const auto& pr : coarse_buffers(ctx, nc))
       if (pr.first->ensure(pr.second) != hipSuccess) return fail_mem(ctx, "coarse space", pr.second);
     if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success)
@@ -600,6 +789,13 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // explicit inverse Einv of the equilibrated operator, applied as one dense
   // GEMV (triangular solves with the LU factors run far below HBM speed)
   auto coarse_solve_into = [&](const S* r, S* out, bool add, const S* div = nullptr) {
+    if (mgm) {
+      hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, MG.b[0].as<double>());
+      const double* y = mg_vcycle(ctx, st);
+      if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
+      hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(FS), blk, 0, st, scc, y, G, FS, out, div);
+      return;
+    }
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
     const int64_t chunk = (nc + kCoarseChunks - 1) / kCoarseChunks;
     hipLaunchKernelGGL(coarse_gemv_partial_kernel, dim3(unsigned((nc + 255) / 256), kCoarseChunks, 1), blk, 0, st,
@@ -738,31 +934,21 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
       // Z keeps the unknown scales of this rebuild (scc)
       coarse_built = it;
       hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), sc, S(0), scc, n7);
-      DG_HIP(hipMemsetAsync(cE, 0, size_t(nc) * nc * 8, st));
-      for (int f = 0; f < 7; ++f) {
-        if (!((active >> f) & 1)) continue;
-        for (int c = 0; c < 7; ++c) {
-          hipLaunchKernelGGL(agg_probe_kernel<S>, grid1(n7), blk, 0, st, scc, f, c, G, FS, t);
-          jvp_cond(t, pJ);
-          hipLaunchKernelGGL(agg_probe_reduce_kernel<S>, gagg, blk, 0, st, scc, pJ, f, c, G, FS, cE, nc);
+      if (mgm) {
+        if (int s = mg_build<S>(ctx, P, uS, scc, t, pJ, active, st))
+          return fail(s, std::string("dg_step: ") + g_last_error);
+      } else {
+        DG_HIP(hipMemsetAsync(cE, 0, size_t(nc) * nc * 8, st));
+        for (int f = 0; f < 7; ++f) {
+          if (!((active >> f) & 1)) continue;
+          for (int c = 0; c < 7; ++c) {
+            hipLaunchKernelGGL(agg_probe_kernel<S>, grid1(n7), blk, 0, st, scc, f, c, G, FS, t);
+            jvp_cond(t, pJ);
+            hipLaunchKernelGGL(agg_probe_reduce_kernel<S>, gagg, blk, 0, st, scc, pJ, f, c, G, FS, cE, nc);
+          }
         }
+        if (int s = coarse_dense_inverse(ctx, nc, st)) return fail(s, std::string("dg_step: ") + g_last_error);
       }
-      hipLaunchKernelGGL(coarse_diag_kernel, grid1(nc), blk, 0, st, cE, nc, nc, cd);
-      hipLaunchKernelGGL(coarse_scale_kernel, dim3(8192), blk, 0, st, cE, nc, nc, cd);
-      DG_HIP(hipGetLastError());
-      if (rocsolver_dgetrf(ctx->blas, rocblas_int(nc), rocblas_int(nc), cE, rocblas_int(nc), cipiv, cinfo) !=
-          rocblas_status_success)
-        return fail(DG_EHIP, "dg_step: rocsolver_dgetrf failed");
-      rocblas_int hinfo = 0;
-      DG_HIP(hipMemcpyAsync(&hinfo, cinfo, sizeof(hinfo), hipMemcpyDeviceToHost, st));
-      DG_HIP(hipStreamSynchronize(st));
-      if (hinfo != 0) return fail(DG_ENAN, "dg_step: singular aggregation coarse operator");
-      // E^-1 = the solve of the LU factors against the identity: level-3
-      // triangular solves (an in-place inverse runs on latency-bound panels)
-      hipLaunchKernelGGL(identity_kernel, dim3(8192), blk, 0, st, cX, nc);
-      if (rocsolver_dgetrs(ctx->blas, rocblas_operation_none, rocblas_int(nc), rocblas_int(nc), cE,
-                           rocblas_int(nc), cipiv, cX, rocblas_int(nc)) != rocblas_status_success)
-        return fail(DG_EHIP, "dg_step: rocsolver_dgetrs failed");
     }
     // coarse operator Ac[g][f] = sum_g sc_g (J Z_f)_g
     if (o.coarse == 1 || o.coarse == 2) {
@@ -1013,6 +1199,14 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
   if (o.coarse_every == 0) o.coarse_every = 3;
   if (o.coarse_every < 0) return fail(DG_EINVAL, std::string(fn) + ": coarse_every must be >= 0");
   if (o.limiter != 0 && o.limiter != 1) return fail(DG_EINVAL, std::string(fn) + ": limiter must be 0 or 1");
+  if (o.mg_levels != 0) {
+    if (o.mg_levels < 2 || o.mg_levels > kMgMaxLevels)
+      return fail(DG_EINVAL, std::string(fn) + ": mg_levels must be 0 or 2..8");
+    if (o.mg_sweeps < 0 || o.mg_sweeps > 8) return fail(DG_EINVAL, std::string(fn) + ": mg_sweeps must be in 0..8");
+    if (!(o.mg_omega > 0.0 && o.mg_omega <= 1.0))
+      return fail(DG_EINVAL, std::string(fn) + ": mg_omega must be in (0, 1]");
+  }
+  if (o.coarse_agg < 0) return fail(DG_EINVAL, std::string(fn) + ": coarse_agg must be >= 0");
   return DG_OK;
 }
 
@@ -1410,6 +1604,8 @@ int dg_workspace_bytes(const dg_mesh* mesh, const dg_params* params, const dg_so
     *bytes = 0;
     dg_solver_opts o;
     if (int s = normalize_opts(opts, o, "dg_workspace_bytes")) return s;
+    if ((features & DG_WS_MG) && o.mg_levels < 2)
+      return fail(DG_EINVAL, "dg_workspace_bytes: DG_WS_MG needs opts->mg_levels >= 2");
     // a host-only context of the mesh (an all-structure map: the sizes do
     // not depend on the phases)
     const int64_t Ne = int64_t(mesh->nx) * mesh->ny * mesh->nz;
@@ -1458,6 +1654,8 @@ int dg_setup_ws(const dg_mesh* mesh, const uint8_t* phase, const dg_params* para
     if (features & ~int32_t(DG_WS_ALL)) return fail(DG_EINVAL, "dg_setup_ws: unknown feature bits");
     dg_solver_opts o;
     if (int s = normalize_opts(opts, o, "dg_setup_ws")) return s;
+    if ((features & DG_WS_MG) && o.mg_levels < 2)
+      return fail(DG_EINVAL, "dg_setup_ws: DG_WS_MG needs opts->mg_levels >= 2");
     dg_ctx* c = nullptr;
     if (int s = make_context(mesh, phase, params, "dg_setup_ws", &c)) return s;
     const int32_t allowed = c->mesh.order == 1   ? int32_t(DG_WS_ALL)
@@ -1782,6 +1980,115 @@ int dg_blockjacobi_export(dg_ctx* ctx, void* out, dg_stream stream) {
 }
 
 
+// Multilevel coarse correction through the C ABI (multigrid.hpp), with
+// unit basis scales: dg_mg_setup linearises at u and builds the hierarchy,
+// dg_mg_apply returns Z V(Z^T r).
+int dg_mg_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double dt, const dg_solver_opts* opts,
+                dg_stream stream) {
+  try {
+    if (int s = check_ctx(ctx)) return s;
+    if (int s = check_q1(ctx, "dg_mg_setup")) return s;
+    if (!u) return fail(DG_EINVAL, "dg_mg_setup: null array");
+    if (!(dt > 0)) return fail(DG_EINVAL, "dg_mg_setup: dt must be positive");
+    if (prec != DG_F64 && prec != DG_F32) return fail(DG_EINVAL, "dg_mg_setup: bad precision");
+    dg_solver_opts o;
+    if (int s = normalize_opts(opts, o, "dg_mg_setup")) return s;
+    if (o.mg_levels < 2) return fail(DG_EINVAL, "dg_mg_setup: mg_levels must be in 2..8");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto& M = ctx->mg;
+    M.prec = -1;
+    const AggGrid G = coarse_grid(ctx->mesh, o);
+    MgGrid g[kMgMaxLevels];
+    mg_grids(G, o.mg_levels, g);
+    const int64_t nc = 7 * g[o.mg_levels - 1].na;
+    if (nc > 8192) return fail(DG_EINVAL, "dg_mg_setup: the last level has more than 8192 unknowns (add levels)");
+    const int64_t FS = ctx->Ne * ctx->np;
+    const size_t sS = prec == DG_F64 ? 8 : 4;
+    for (const auto& pr : mg_buffers(ctx, o.mg_levels, g))
+      if (pr.first->ensure(pr.second) != hipSuccess) return fail_mem(ctx, "dg_mg_setup: levels", pr.second);
+    for (const auto& pr : coarse_buffers(ctx, nc))
+      if (pr.first->ensure(pr.second) != hipSuccess) return fail_mem(ctx, "dg_mg_setup: last level", pr.second);
+    for (DevBuf* d : {&M.ones, &M.pv, &M.pjv})
+      if (d->ensure(size_t(7) * FS * sS) != hipSuccess) return fail_mem(ctx, "dg_mg_setup: probe vectors", 7 * FS * sS);
+    if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success)
+      return fail(DG_EHIP, "rocblas_create_handle failed");
+    if (rocblas_set_stream(ctx->blas, st) != rocblas_status_success) return fail(DG_EHIP, "rocblas_set_stream failed");
+    if (!ctx->owns_memory && ctx->blasws.bytes == 0) {
+      size_t need = 0;
+      if (!rocsolver_scratch_bytes(ctx->blas, nc, need))
+        return fail(DG_EHIP, "dg_mg_setup: rocSOLVER scratch size query failed");
+      if (int s = give_blas_scratch(ctx, need)) return s;
+    }
+    M.levels = o.mg_levels;
+    M.nu = o.mg_sweeps;
+    M.omega = o.mg_omega;
+    M.G = G;
+    for (int l = 0; l < M.levels; ++l) M.g[l] = g[l];
+    const DevParams P = make_params(ctx, t_new, dt);
+    const dim3 blk{256, 1, 1};
+    int s = DG_OK;
+    if (prec == DG_F64) {
+      hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(7 * FS), blk, 0, st, M.ones.as<double>(), 7 * FS, 1.0);
+      s = linearize<double>(ctx, P, static_cast<const double*>(u), st);
+      if (!s)
+        s = mg_build<double>(ctx, P, static_cast<const double*>(u), M.ones.as<const double>(), M.pv.as<double>(),
+                             M.pjv.as<double>(), kAllFields, st);
+    } else {
+      hipLaunchKernelGGL(mg_fill_kernel<float>, grid1(7 * FS), blk, 0, st, M.ones.as<float>(), 7 * FS, 1.0f);
+      s = linearize<float>(ctx, P, static_cast<const float*>(u), st);
+      if (!s)
+        s = mg_build<float>(ctx, P, static_cast<const float*>(u), M.ones.as<const float>(), M.pv.as<float>(),
+                            M.pjv.as<float>(), kAllFields, st);
+    }
+    if (s) return fail(s, std::string("dg_mg_setup: ") + g_last_error);
+    DG_HIP(hipStreamSynchronize(st));
+    M.prec = int(prec);
+    return DG_OK;
+  } catch (...) {
+    return fail(DG_EINVAL, "dg_mg_setup: unexpected exception");
+  }
+}
+
+int dg_mg_export(dg_ctx* ctx, int32_t level, double* out, int64_t n, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!out) return fail(DG_EINVAL, "dg_mg_export: null array");
+  if (ctx->mg.prec < 0) return fail(DG_ESTATE, "dg_mg_export: no dg_mg_setup hierarchy is current");
+  if (level < 1 || level > ctx->mg.levels) return fail(DG_EINVAL, "dg_mg_export: no such level");
+  const int64_t need = 343 * ctx->mg.g[level - 1].na;
+  if (n < need) return fail(DG_EINVAL, "dg_mg_export: out holds fewer than 343 x (aggregates of the level) entries");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DG_HIP(hipMemcpyAsync(out, ctx->mg.E[level - 1].p, size_t(need) * 8, hipMemcpyDeviceToDevice, st));
+  return DG_OK;
+}
+
+int dg_mg_apply(dg_ctx* ctx, dg_prec prec, const void* r, void* out, dg_stream stream) {
+  if (int s = check_ctx(ctx)) return s;
+  if (!r || !out) return fail(DG_EINVAL, "dg_mg_apply: null array");
+  if (ctx->mg.prec < 0) return fail(DG_ESTATE, "dg_mg_apply: no dg_mg_setup hierarchy is current");
+  if (int(prec) != ctx->mg.prec) return fail(DG_EINVAL, "dg_mg_apply: precision differs from the setup");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto& M = ctx->mg;
+  const int64_t FS = ctx->Ne * ctx->np, n7 = 7 * FS;
+  const dim3 blk{256, 1, 1}, gagg{unsigned(M.G.na), 1, 1};
+  if (prec == DG_F64) {
+    hipLaunchKernelGGL(agg_restrict_kernel<double>, gagg, blk, 0, st, M.ones.as<const double>(),
+                       static_cast<const double*>(r), M.G, FS, M.b[0].as<double>());
+    const double* y = mg_vcycle(ctx, st);
+    hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(n7), blk, 0, st, static_cast<double*>(out), n7, 0.0);
+    hipLaunchKernelGGL(agg_prolong_add_kernel<double>, grid1(FS), blk, 0, st, M.ones.as<const double>(), y, M.G, FS,
+                       static_cast<double*>(out), static_cast<const double*>(nullptr));
+  } else {
+    hipLaunchKernelGGL(agg_restrict_kernel<float>, gagg, blk, 0, st, M.ones.as<const float>(),
+                       static_cast<const float*>(r), M.G, FS, M.b[0].as<double>());
+    const double* y = mg_vcycle(ctx, st);
+    hipLaunchKernelGGL(mg_fill_kernel<float>, grid1(n7), blk, 0, st, static_cast<float*>(out), n7, 0.0f);
+    hipLaunchKernelGGL(agg_prolong_add_kernel<float>, grid1(FS), blk, 0, st, M.ones.as<const float>(), y, M.G, FS,
+                       static_cast<float*>(out), static_cast<const float*>(nullptr));
+  }
+  DG_HIP(hipGetLastError());
+  return DG_OK;
+}
+
 void dg_solver_opts_default(dg_solver_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -1796,6 +2103,9 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->block_bf16 = 1;       // FP32 inner solves stream bfloat16 block inverses
   o->verbose = 0;
   o->coarse_every = 3;     // aggregation coarse operator rebuilt every third iterate
+  o->mg_levels = 0;        // the dense coarse solve (no multilevel cycle)
+  o->mg_sweeps = 2;
+  o->mg_omega = 0.7;
 }
 
 int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,

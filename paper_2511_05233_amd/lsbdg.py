@@ -42,6 +42,9 @@ _SIGNATURES = {
     "dg_blockjacobi_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_blockjacobi_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dg_solver_opts_default": (None, [C.c_void_p]),
+    "dg_mg_setup": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "dg_mg_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dg_mg_export": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
     "dg_step": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p]),
     "dg_initial_state": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -96,7 +99,8 @@ class DgSolverOpts(C.Structure):
                 ("newton_maxit", C.c_int32), ("gmres_rtol", C.c_double), ("gmres_rtol_final", C.c_double),
                 ("newton_tol", C.c_double),
                 ("coarse", C.c_int32), ("coarse_agg", C.c_int32), ("block_bf16", C.c_int32),
-                ("verbose", C.c_int32), ("coarse_every", C.c_int32), ("limiter", C.c_int32)]
+                ("verbose", C.c_int32), ("coarse_every", C.c_int32), ("limiter", C.c_int32),
+                ("mg_levels", C.c_int32), ("mg_sweeps", C.c_int32), ("mg_omega", C.c_double)]
 
 
 class DgStepReport(C.Structure):
@@ -126,7 +130,8 @@ class DgBatchTuning(C.Structure):
 
 DG_CTRL_NAIVE, DG_CTRL_H211B = 0, 1
 DG_WS_OPERATORS, DG_WS_BLOCKS, DG_WS_STEP, DG_WS_NAIVE, DG_WS_H211B, DG_WS_LIMITER = 1, 2, 4, 8, 16, 32
-DG_WS_ALL = 63
+DG_WS_MG = 64
+DG_WS_ALL = 127
 
 
 class DgController(C.Structure):
@@ -422,6 +427,33 @@ class Context:
             return out
         _check("dg_blockjacobi_apply", self._lib.dg_blockjacobi_apply(
             self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def mg_setup(self, u, t_new, dt, levels, agg=0, sweeps=2, omega=0.7, dtype=None):
+        """dg_mg_setup: linearise at u (precision dtype) and build the
+        multilevel hierarchy (levels 2..8, level-1 aggregate edge agg)."""
+        self._check_arr(u, 9)
+        uu = u if dtype is None or u.dtype == dtype else u.to(dtype)
+        o = _solver_opts("f32", {"mg_levels": int(levels), "coarse_agg": int(agg), "mg_sweeps": int(sweeps),
+                                 "mg_omega": float(omega)})
+        _check("dg_mg_setup", self._lib.dg_mg_setup(self._h, _prec(uu), _ptr(uu), float(t_new), float(dt),
+                                                    C.byref(o), _stream()))
+
+    def mg_apply(self, r, out=None):
+        """dg_mg_apply: out = Z V(Z^T r) for a 7-field vector r."""
+        import torch
+        self._check_arr(r, 7)
+        if out is None:
+            out = torch.empty_like(r)
+        self._check_arr(out, 7, like=r)
+        _check("dg_mg_apply", self._lib.dg_mg_apply(self._h, _prec(r), _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def mg_export(self, level, n_aggregates):
+        """dg_mg_export: level operator as (7 slots, 7, 7, aggregates) FP64."""
+        import torch
+        out = torch.empty((7, 7, 7, int(n_aggregates)), dtype=torch.float64, device="cuda")
+        _check("dg_mg_export", self._lib.dg_mg_export(self._h, int(level), _ptr(out), out.numel(), _stream()))
         return out
 
     def blockjacobi_export(self):

@@ -120,7 +120,7 @@ def test_binding_constants_match_the_header_enums():
     for body in re.findall(r"typedef\s+enum\s*\w*\s*\{(.*?)\}", src, flags=re.S):
         for name, val in re.findall(r"\b(DG_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
             enums[name] = int(val)
-    assert len(enums) == 25, sorted(enums)   # status 8, precision 2, JVP 3, controller 2, batch op 3, workspace 7
+    assert len(enums) == 26, sorted(enums)   # status 8, precision 2, JVP 3, controller 2, batch op 3, workspace 8
     for name, val in enums.items():
         if hasattr(lsbdg, name):
             assert getattr(lsbdg, name) == val, name

@@ -157,6 +157,21 @@ def test_step_with_aggregation_coarse_space(small_case, inner, tol, coarse):
     assert np.all(err < tol), err
 
 
+@pytest.mark.parametrize("coarse", [3, 4])
+@pytest.mark.parametrize("inner,tol", [("f64", 1e-10), ("f32", 1e-8)])
+def test_step_with_multigrid_coarse_correction(small_case, inner, tol, coarse):
+    """The coarse solve replaced by a three-level V-cycle (aggregates of 1,
+    2 and 4 voxels per edge: 5x4x3, 3x2x2 and 2x1x1 of them) reaches the
+    same root."""
+    P, ctx, u0, u1 = small_case
+    ut = torch.tensor(u0, device="cuda:0")
+    rep = ctx.step(ut, 0.0, 0.1, inner=inner, coarse=coarse, coarse_agg=1, mg_levels=3, verbose=1)
+    print(f"[step] multigrid coarse={coarse} {inner} report {rep}", flush=True)
+    err = rel_l2(ut.cpu().numpy(), u1)
+    print("  relative L2 per field", err, flush=True)
+    assert np.all(err < tol), err
+
+
 def test_aggregation_coarse_space_cuts_gmres_on_cube16():
     """16^3 cube, first implicit step from the GPU initial state: the
     aggregation coarse space needs fewer GMRES iterations than the global
@@ -171,7 +186,13 @@ def test_aggregation_coarse_space_cuts_gmres_on_cube16():
         reps[coarse] = ctx.step(ut, 0.0, 0.1, inner="f32", coarse=coarse)
         roots[coarse] = ut.cpu().numpy()
         print(f"[step] cube16 coarse={coarse}: {reps[coarse]}", flush=True)
-    for c in (3, 4):
+    # the multilevel V-cycle on 8^3, 4^3 and 2^3 aggregates of 2, 4, 8 voxels
+    ut = u0.clone()
+    reps["mg"] = ctx.step(ut, 0.0, 0.1, inner="f32", coarse=3, coarse_agg=2, mg_levels=3)
+    roots["mg"] = ut.cpu().numpy()
+    print(f"[step] cube16 multigrid: {reps['mg']}", flush=True)
+    assert reps["mg"]["gmres_its"] < reps[1]["gmres_its"]
+    for c in (3, 4, "mg"):
         err = rel_l2(roots[c], roots[1])
         print(f"  relative L2 between the roots (coarse {c} vs 1)", err, flush=True)
         assert np.all(err[:7] < 1e-8), err

@@ -88,3 +88,33 @@ def test_too_small_a_workspace_is_refused():
     with pytest.raises(lsbdg.DgError) as ei:
         _make(ws, feats)
     assert ei.value.code == -2 and "workspace lacks" in str(ei.value)
+
+
+def test_multigrid_on_a_workspace_context():
+    """dg_mg_setup / dg_mg_apply on a workspace sized with DG_WS_MG equal the
+    allocating context's bit for bit and allocate nothing."""
+    from paper_2511_05233_amd import lsbdg
+    feats = lsbdg.DG_WS_OPERATORS | lsbdg.DG_WS_MG
+    opts = {"mg_levels": 2, "coarse_agg": 2}
+    n = lsbdg.workspace_bytes(5, 4, 3, 1e-6, 1, feats, inner="f64", **opts)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    ref = _make()
+    ctx = _make(ws, feats, "f64", **opts)
+    u = torch.tensor(synth.random_state(60, 8, 5, phase=synth.porosity_mask((3, 4, 5), 0.6, 1)), device="cuda:0")
+    r = torch.tensor(synth.random_vector(7, 60, 8, 6), device="cuda:0")
+    ref.mg_setup(u, 0.3, 0.1, levels=2, agg=2)
+    y_ref = ref.mg_apply(r)
+    y = torch.empty_like(y_ref)
+    assert torch.equal(y_ref, y_ref)                 # loads torch's comparison kernels before measuring
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    ctx.mg_setup(u, 0.3, 0.1, levels=2, agg=2)
+    ctx.mg_apply(r, out=y)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    assert torch.equal(y, y_ref)
+    with pytest.raises(lsbdg.DgError) as ei:
+        ctx.mg_setup(u, 0.3, 0.1, levels=3, agg=2)   # more levels than the workspace was sized for
+    assert ei.value.code == -2
+    ctx.close()
+    ref.close()
