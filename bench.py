@@ -800,9 +800,10 @@ def main(argv=None):
     ap.add_argument("--step-only", action="store_true",
                     help="time the steps only (no kernel timings, comparisons or baselines): "
                          "the run a kernel trace of the timed step is taken on")
-    ap.add_argument("--mg-levels", type=int, default=0,
+    ap.add_argument("--mg-levels", type=int, default=None,
                     help="coarse solve by a V-cycle over this many aggregate levels (2..8; level-1 edge "
-                         "--coarse-agg, 0: 4)")
+                         "--coarse-agg, 0: 4); 0: the exact two-level solve; default: the library's "
+                         "automatic choice")
     ap.add_argument("--mg-sweeps", type=int, default=2, help="block-Jacobi sweeps per level of the V-cycle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -814,9 +815,9 @@ def main(argv=None):
         return 0
     if args.fp32_blocks:
         SOLVER_EXTRA["block_bf16"] = 0
-    if args.mg_levels:
+    if args.mg_levels is not None:
         SOLVER_EXTRA["mg_levels"] = args.mg_levels
-        SOLVER_EXTRA["mg_sweeps"] = args.mg_sweeps
+    SOLVER_EXTRA["mg_sweeps"] = args.mg_sweeps
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; "
               "run with --gpus 1.", file=sys.stderr)
@@ -885,6 +886,7 @@ def main(argv=None):
             tot["newton_its"] += rep["newton_its"]
             tot["gmres_its"] += rep["gmres_its"]
             tot["implicit_steps"] += 1
+            tot["mg_levels_used"] = rep.get("mg_levels", 0)
             if rep["newton_its"] < 1:
                 break
             if rep.get("converged"):
@@ -941,8 +943,8 @@ def main(argv=None):
                             "FP64 update" if args.mode == "newton" else
                             "accepted step of the naive time controller (backward-Euler Newton-GMRES "
                             "solves, halving dt on failure)"),
-                   "coarse": args.coarse, "coarse_agg": args.coarse_agg, "mg_levels": args.mg_levels,
-                   "mg_sweeps": args.mg_sweeps if args.mg_levels else None, "timed_steps": done, **{k: v for k, v in tot.items()}},
+                   "coarse": args.coarse, "coarse_agg": args.coarse_agg, "mg_levels": "auto" if args.mg_levels is None else args.mg_levels,
+                   "mg_sweeps": args.mg_sweeps, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(w.name, k_op),

@@ -262,8 +262,8 @@ typedef struct {
                             to zero and continue additively (roots with
                             negative nodal values are reached before
                             limiting).  0 (default): no limiter */
-  int32_t mg_levels;     /* coarse = 3, 4: 0 (default) solves the coarse
-                            system exactly (dense LU); 2..8 replaces that
+  int32_t mg_levels;     /* coarse = 3, 4: 0 solves the coarse system
+                            exactly (dense LU); 2..8 replaces that
                             solve by one V-cycle over mg_levels levels of
                             nested voxel aggregates (the multigrid stand-in
                             for Sec. 2.9's algebraic multigrid): level 1 has
@@ -271,7 +271,13 @@ typedef struct {
                             each further level groups 2 x 2 x 2 aggregates
                             of the one above, operators are Galerkin
                             products, the last level (at most 8192
-                            unknowns) is solved exactly; see dg_mg_setup */
+                            unknowns) is solved exactly; see dg_mg_setup.
+                            -1 (default): automatic -- 0 while
+                            aggregates of coarse_agg voxels per edge (0:
+                            8) give at most 8192 coarse unknowns, else
+                            level-1 aggregates of coarse_agg (0: 4) voxels
+                            and the fewest levels whose last has at most
+                            4096 unknowns (3 on the 96 x 96 x 192 slab) */
   int32_t mg_sweeps;     /* damped block-Jacobi sweeps before and after each
                             coarse correction of the cycle, 0..8 (default 2) */
   double mg_omega;       /* their damping, in (0, 1] (default 0.7) */
@@ -376,7 +382,8 @@ typedef struct {
   int32_t newton_its, gmres_its, line_search_cuts, status;
   int32_t stalled;        /* 1: stopped because full steps no longer shrank the
                              update (below 1e-7): the attainable accuracy */
-  int32_t pad;
+  int32_t mg_levels;      /* levels of the multilevel coarse correction the
+                             solve used (0: none; see dg_solver_opts) */
   double merit0;          /* preconditioned scaled residual norm at the start */
   double merit_final;     /* ... after the last accepted update */
   double last_update;     /* largest relative change of the last update */

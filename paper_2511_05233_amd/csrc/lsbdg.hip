@@ -429,8 +429,34 @@ std::vector<std::pair<DevBuf*, size_t>> solver_buffers(dg_ctx* ctx, const dg_sol
           std::make_pair(&W.gstate, sizeof(GmresState))};
 }
 
+// Levels of the multilevel coarse correction for options o on this mesh:
+// o.mg_levels when set (0: none), else (-1) automatic.  The exact two-level
+// solve is kept while it can use aggregates of at most 8 voxels per edge
+// (coarse_agg if set) within 8192 coarse unknowns; beyond that its
+// aggregates grow coarse and the cycle does better: level-1 aggregates of
+// coarse_agg (0: 4) voxels per edge, and as many 2 x 2 x 2 coarsenings as
+// bring the last level to at most 4096 unknowns.
+int mg_levels_for(const dg_mesh& mesh, const dg_solver_opts& o) {
+  if (o.mg_levels >= 0) return o.mg_levels;
+  if (o.coarse != 3 && o.coarse != 4) return 0;
+  auto naggs = [&](int a) {
+    return int64_t((mesh.nx + a - 1) / a) * ((mesh.ny + a - 1) / a) * ((mesh.nz + a - 1) / a);
+  };
+  if (7 * naggs(o.coarse_agg > 0 ? o.coarse_agg : 8) <= 8192) return 0;
+  const int A = o.coarse_agg > 0 ? o.coarse_agg : 4;
+  MgGrid g{(mesh.nx + A - 1) / A, (mesh.ny + A - 1) / A, (mesh.nz + A - 1) / A, 0, 0};
+  g.na = int64_t(g.ax) * g.ay * g.az;
+  int L = 1;
+  while (7 * g.na > 4096 && L < kMgMaxLevels) {
+    g = mg_coarser(g);
+    ++L;
+  }
+  return L;
+}
+
 // Aggregates of the two-level coarse space: opts.coarse_agg voxels per
-// edge, or the smallest edge >= 4 with at most 8192 coarse unknowns.
+// edge, or the smallest edge >= 4 with at most 8192 coarse unknowns (4
+// under the multilevel correction).
 AggGrid coarse_grid(const dg_mesh& mesh, const dg_solver_opts& o) {
   AggGrid G{};
   const int nx = mesh.nx, ny = mesh.ny, nz = mesh.nz;
@@ -438,7 +464,7 @@ AggGrid coarse_grid(const dg_mesh& mesh, const dg_solver_opts& o) {
   int A = o.coarse_agg;
   if (A <= 0) {
     A = 4;
-    if (o.mg_levels < 2)
+    if (mg_levels_for(mesh, o) < 2)
       while (7 * naggs(A) > 8192) ++A;
   }
   G.nx = nx; G.ny = ny; G.nz = nz; G.A = A;
@@ -458,10 +484,11 @@ void mg_grids(const AggGrid& G, int levels, MgGrid* g) {
 // or the last level of the multilevel correction.
 int64_t coarse_dense_size(const dg_mesh& mesh, const dg_solver_opts& o) {
   const AggGrid G = coarse_grid(mesh, o);
-  if (o.mg_levels < 2) return 7 * G.na;
+  const int L = mg_levels_for(mesh, o);
+  if (L < 2) return 7 * G.na;
   MgGrid g[kMgMaxLevels];
-  mg_grids(G, o.mg_levels, g);
-  return 7 * g[o.mg_levels - 1].na;
+  mg_grids(G, L, g);
+  return 7 * g[L - 1].na;
 }
 
 // Device buffers of the multilevel levels (FP64): stencil operators on
@@ -545,10 +572,11 @@ std::vector<std::pair<DevBuf*, size_t>> plan_workspace(dg_ctx* ctx, const dg_sol
       need_rocsolver = true;
     }
   }
-  if ((features & DG_WS_MG) || (step && (o.coarse == 3 || o.coarse == 4) && o.mg_levels >= 2)) {
+  const int mgL = mg_levels_for(ctx->mesh, o);
+  if ((features & DG_WS_MG) || (step && (o.coarse == 3 || o.coarse == 4) && mgL >= 2)) {
     MgGrid g[kMgMaxLevels];
-    mg_grids(coarse_grid(ctx->mesh, o), o.mg_levels, g);
-    for (const auto& pr : mg_buffers(ctx, o.mg_levels, g)) out.push_back(pr);
+    mg_grids(coarse_grid(ctx->mesh, o), mgL, g);
+    for (const auto& pr : mg_buffers(ctx, mgL, g)) out.push_back(pr);
   }
   if (features & DG_WS_MG) {
     // dg_mg_setup / dg_mg_apply: unit scales, two probe vectors, the dense
@@ -728,7 +756,8 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   AggGrid G{};
   int64_t nc = 0;
   const bool agg = (o.coarse == 3 || o.coarse == 4);
-  const bool mgm = agg && o.mg_levels >= 2;    // the coarse solve by a multilevel V-cycle
+  const int mgL = mg_levels_for(ctx->mesh, o);
+  const bool mgm = agg && mgL >= 2;            // the coarse solve by a multilevel V-cycle
   auto& MG = ctx->mg;
   if (agg) {
     G = coarse_grid(ctx->mesh, o);
@@ -737,7 +766,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     if (mgm) {
       if (nc > 8192) return fail(DG_EINVAL, "dg_step: the last multigrid level has more than 8192 unknowns (add levels)");
       MG.prec = -1;                              // the hierarchy becomes the solver's
-      MG.levels = o.mg_levels;
+      MG.levels = mgL;
       MG.nu = o.mg_sweeps;
       MG.omega = o.mg_omega;
       MG.G = G;
@@ -906,6 +935,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   resid64(u, R);
   DG_HIP(hipGetLastError());
   dg_step_report r{};
+  r.mg_levels = mgm ? mgL : 0;
   int status = DG_ENOCONV;
   // Near the root the linear-solve tolerance is tightened, and the iteration
   // stops once a full step no longer shrinks the update: the attainable
@@ -1200,8 +1230,8 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
   if (o.coarse_every < 0) return fail(DG_EINVAL, std::string(fn) + ": coarse_every must be >= 0");
   if (o.limiter != 0 && o.limiter != 1) return fail(DG_EINVAL, std::string(fn) + ": limiter must be 0 or 1");
   if (o.mg_levels != 0) {
-    if (o.mg_levels < 2 || o.mg_levels > kMgMaxLevels)
-      return fail(DG_EINVAL, std::string(fn) + ": mg_levels must be 0 or 2..8");
+    if (o.mg_levels != -1 && (o.mg_levels < 2 || o.mg_levels > kMgMaxLevels))
+      return fail(DG_EINVAL, std::string(fn) + ": mg_levels must be -1, 0 or 2..8");
     if (o.mg_sweeps < 0 || o.mg_sweeps > 8) return fail(DG_EINVAL, std::string(fn) + ": mg_sweeps must be in 0..8");
     if (!(o.mg_omega > 0.0 && o.mg_omega <= 1.0))
       return fail(DG_EINVAL, std::string(fn) + ": mg_omega must be in (0, 1]");
@@ -2103,7 +2133,7 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->block_bf16 = 1;       // FP32 inner solves stream bfloat16 block inverses
   o->verbose = 0;
   o->coarse_every = 3;     // aggregation coarse operator rebuilt every third iterate
-  o->mg_levels = 0;        // the dense coarse solve (no multilevel cycle)
+  o->mg_levels = -1;       // multilevel cycle where the exact two-level space would need coarse aggregates
   o->mg_sweeps = 2;
   o->mg_omega = 0.7;
 }

@@ -105,7 +105,7 @@ class DgSolverOpts(C.Structure):
 
 class DgStepReport(C.Structure):
     _fields_ = [("newton_its", C.c_int32), ("gmres_its", C.c_int32), ("line_search_cuts", C.c_int32),
-                ("status", C.c_int32), ("stalled", C.c_int32), ("pad", C.c_int32), ("merit0", C.c_double), ("merit_final", C.c_double),
+                ("status", C.c_int32), ("stalled", C.c_int32), ("mg_levels", C.c_int32), ("merit0", C.c_double), ("merit_final", C.c_double),
                 ("last_update", C.c_double), ("gmres_last_rel", C.c_double)]
 
     def as_dict(self):
