@@ -82,6 +82,7 @@ struct dg_ctx {
     AggGrid G{};                      // level-1 aggregates on the voxels
     MgGrid g[kMgMaxLevels]{};
     DevBuf E[kMgMaxLevels], Dinv[kMgMaxLevels], b[kMgMaxLevels], xa[kMgMaxLevels], xb[kMgMaxLevels];
+    DevBuf r[kMgMaxLevels];
     DevBuf ones, pv, pjv;
     int prec = -1;                    // precision of a dg_mg_setup hierarchy (-1: none current)
   } mg;
@@ -93,7 +94,7 @@ struct dg_ctx {
     for (DevBuf* d : {&phase, &blocks, &qpiv, &probe, &lin, &cE, &cX, &cd, &crc, &crc2, &cipiv, &cinfo, &cpart, &bh, &blasws, &status})
       f(*d);
     for (int l = 0; l < kMgMaxLevels; ++l)
-      for (DevBuf* d : {&mg.E[l], &mg.Dinv[l], &mg.b[l], &mg.xa[l], &mg.xb[l]}) f(*d);
+      for (DevBuf* d : {&mg.E[l], &mg.Dinv[l], &mg.b[l], &mg.xa[l], &mg.xb[l], &mg.r[l]}) f(*d);
     for (DevBuf* d : {&mg.ones, &mg.pv, &mg.pjv}) f(*d);
     work.for_each(f);
   }
@@ -447,7 +448,7 @@ int mg_levels_for(const dg_mesh& mesh, const dg_solver_opts& o) {
   MgGrid g{(mesh.nx + A - 1) / A, (mesh.ny + A - 1) / A, (mesh.nz + A - 1) / A, 0, 0};
   g.na = int64_t(g.ax) * g.ay * g.az;
   int L = 1;
-  while (7 * g.na > 4096 && L < kMgMaxLevels) {
+  while (8 * g.na > 4096 && L < kMgMaxLevels) {
     g = mg_coarser(g);
     ++L;
   }
@@ -488,7 +489,7 @@ int64_t coarse_dense_size(const dg_mesh& mesh, const dg_solver_opts& o) {
   if (L < 2) return 7 * G.na;
   MgGrid g[kMgMaxLevels];
   mg_grids(G, L, g);
-  return 7 * g[L - 1].na;
+  return 8 * g[L - 1].na;                      // the padded ordering of the last level
 }
 
 // Device buffers of the multilevel levels (FP64): stencil operators on
@@ -499,11 +500,12 @@ std::vector<std::pair<DevBuf*, size_t>> mg_buffers(dg_ctx* ctx, int levels, cons
   auto& M = ctx->mg;
   for (int l = 0; l < levels; ++l) {
     const size_t na = size_t(g[l].na);
-    out.push_back(std::make_pair(&M.E[l], 343 * na * 8));
-    if (l + 1 < levels) out.push_back(std::make_pair(&M.Dinv[l], 49 * na * 8));
-    out.push_back(std::make_pair(&M.b[l], 7 * na * 8));
-    out.push_back(std::make_pair(&M.xa[l], 7 * na * 8));
-    out.push_back(std::make_pair(&M.xb[l], 7 * na * 8));
+    out.push_back(std::make_pair(&M.E[l], 392 * na * 8));
+    if (l + 1 < levels) out.push_back(std::make_pair(&M.Dinv[l], 56 * na * 8));
+    out.push_back(std::make_pair(&M.b[l], 8 * na * 8));
+    out.push_back(std::make_pair(&M.xa[l], 8 * na * 8));
+    out.push_back(std::make_pair(&M.xb[l], 8 * na * 8));
+    if (l + 1 < levels) out.push_back(std::make_pair(&M.r[l], 8 * na * 8));
   }
   return out;
 }
@@ -640,7 +642,7 @@ int mg_build(dg_ctx* ctx, const DevParams& P, const S* uS, const S* scales, S* v
   const int L = M.levels;
   const int64_t FS = ctx->Ne * ctx->np;
   const dim3 blk{256, 1, 1};
-  hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(343 * M.g[0].na), blk, 0, st, M.E[0].as<double>(), 343 * M.g[0].na, 0.0);
+  hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(392 * M.g[0].na), blk, 0, st, M.E[0].as<double>(), 392 * M.g[0].na, 0.0);
   for (int f = 0; f < 7; ++f) {
     if (!((active >> f) & 1)) continue;
     for (int c = 0; c < 7; ++c) {
@@ -651,14 +653,14 @@ int mg_build(dg_ctx* ctx, const DevParams& P, const S* uS, const S* scales, S* v
     }
   }
   for (int l = 1; l < L; ++l)
-    hipLaunchKernelGGL(mg_galerkin_kernel, mg_grid(49 * M.g[l].na), blk, 0, st, M.E[l - 1].as<const double>(),
+    hipLaunchKernelGGL(mg_galerkin_kernel, mg_grid(56 * M.g[l].na), blk, 0, st, M.E[l - 1].as<const double>(),
                        M.g[l - 1], M.E[l].as<double>(), M.g[l]);
   for (int l = 0; l + 1 < L; ++l)
     hipLaunchKernelGGL(mg_block_inverse_kernel, mg_grid(M.g[l].na), blk, 0, st, M.E[l].as<const double>(), M.g[l].na,
                        M.Dinv[l].as<double>());
-  const int64_t nc = 7 * M.g[L - 1].na;
+  const int64_t nc = 8 * M.g[L - 1].na;
   hipLaunchKernelGGL(mg_fill_kernel<double>, dim3(8192), blk, 0, st, ctx->cE.as<double>(), nc * nc, 0.0);
-  hipLaunchKernelGGL(mg_dense_kernel, grid1(343 * M.g[L - 1].na), blk, 0, st, M.E[L - 1].as<const double>(),
+  hipLaunchKernelGGL(mg_dense_kernel, grid1(392 * M.g[L - 1].na), blk, 0, st, M.E[L - 1].as<const double>(),
                      M.g[L - 1], ctx->cE.as<double>());
   DG_HIP(hipGetLastError());
   return coarse_dense_inverse(ctx, nc, st);
@@ -673,7 +675,7 @@ const double* mg_vcycle(dg_ctx* ctx, hipStream_t st) {
   double* cur[kMgMaxLevels] = {};
   auto sweep = [&](int l, double*& x) {
     double* out = (x == M.xa[l].as<double>()) ? M.xb[l].as<double>() : M.xa[l].as<double>();
-    hipLaunchKernelGGL(mg_smooth_kernel, mg_grid(M.g[l].na), blk, 0, st, M.E[l].as<const double>(),
+    hipLaunchKernelGGL(mg_smooth_kernel, mg_grid(8 * M.g[l].na), blk, 0, st, M.E[l].as<const double>(),
                        M.Dinv[l].as<const double>(), M.g[l], M.b[l].as<const double>(),
                        static_cast<const double*>(x), out, M.omega);
     x = out;
@@ -681,12 +683,13 @@ const double* mg_vcycle(dg_ctx* ctx, hipStream_t st) {
   for (int l = 0; l + 1 < L; ++l) {
     double* x = nullptr;                      // zero
     for (int k = 0; k < M.nu; ++k) sweep(l, x);
-    hipLaunchKernelGGL(mg_residual_restrict_kernel, mg_grid(M.g[l + 1].na), blk, 0, st, M.E[l].as<const double>(),
-                       M.g[l], M.b[l].as<const double>(), static_cast<const double*>(x), M.g[l + 1],
-                       M.b[l + 1].as<double>());
+    hipLaunchKernelGGL(mg_residual_kernel, mg_grid(8 * M.g[l].na), blk, 0, st, M.E[l].as<const double>(), M.g[l],
+                       M.b[l].as<const double>(), static_cast<const double*>(x), M.r[l].as<double>());
+    hipLaunchKernelGGL(mg_restrict_kernel, mg_grid(8 * M.g[l + 1].na), blk, 0, st, M.r[l].as<const double>(),
+                       M.g[l], M.g[l + 1], M.b[l + 1].as<double>());
     cur[l] = x;
   }
-  const int64_t nc = 7 * M.g[L - 1].na;
+  const int64_t nc = 8 * M.g[L - 1].na;
   const int64_t chunk = (nc + kCoarseChunks - 1) / kCoarseChunks;
   hipLaunchKernelGGL(coarse_gemv_partial_kernel, dim3(unsigned((nc + 255) / 256), kCoarseChunks, 1), blk, 0, st,
                      ctx->cX.as<const double>(), nc, M.b[L - 1].as<const double>(), ctx->cd.as<const double>(), chunk,
@@ -698,10 +701,10 @@ const double* mg_vcycle(dg_ctx* ctx, hipStream_t st) {
     double* x = cur[l];
     if (!x) {
       x = M.xa[l].as<double>();
-      hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(7 * M.g[l].na), blk, 0, st, x, 7 * M.g[l].na, 0.0);
+      hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(8 * M.g[l].na), blk, 0, st, x, 8 * M.g[l].na, 0.0);
     }
-    hipLaunchKernelGGL(mg_prolong_add_kernel, mg_grid(M.g[l].na), blk, 0, st, static_cast<const double*>(cur[l + 1]),
-                       M.g[l + 1], M.g[l], x);
+    hipLaunchKernelGGL(mg_prolong_add_kernel, mg_grid(8 * M.g[l].na), blk, 0, st,
+                       static_cast<const double*>(cur[l + 1]), M.g[l + 1], M.g[l], x);
     for (int k = 0; k < M.nu; ++k) sweep(l, x);
     cur[l] = x;
   }
@@ -819,10 +822,10 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
   // GEMV (triangular solves with the LU factors run far below HBM speed)
   auto coarse_solve_into = [&](const S* r, S* out, bool add, const S* div = nullptr) {
     if (mgm) {
-      hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, MG.b[0].as<double>());
+      hipLaunchKernelGGL(mg_restrict_fine_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, MG.b[0].as<double>());
       const double* y = mg_vcycle(ctx, st);
       if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
-      hipLaunchKernelGGL(agg_prolong_add_kernel<S>, grid1(FS), blk, 0, st, scc, y, G, FS, out, div);
+      hipLaunchKernelGGL(mg_prolong_fine_kernel<S>, grid1(FS), blk, 0, st, scc, y, G, FS, out, div);
       return;
     }
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
@@ -2030,7 +2033,7 @@ int dg_mg_setup(dg_ctx* ctx, dg_prec prec, const void* u, double t_new, double d
     const AggGrid G = coarse_grid(ctx->mesh, o);
     MgGrid g[kMgMaxLevels];
     mg_grids(G, o.mg_levels, g);
-    const int64_t nc = 7 * g[o.mg_levels - 1].na;
+    const int64_t nc = 8 * g[o.mg_levels - 1].na;
     if (nc > 8192) return fail(DG_EINVAL, "dg_mg_setup: the last level has more than 8192 unknowns (add levels)");
     const int64_t FS = ctx->Ne * ctx->np;
     const size_t sS = prec == DG_F64 ? 8 : 4;
@@ -2087,7 +2090,9 @@ int dg_mg_export(dg_ctx* ctx, int32_t level, double* out, int64_t n, dg_stream s
   const int64_t need = 343 * ctx->mg.g[level - 1].na;
   if (n < need) return fail(DG_EINVAL, "dg_mg_export: out holds fewer than 343 x (aggregates of the level) entries");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  DG_HIP(hipMemcpyAsync(out, ctx->mg.E[level - 1].p, size_t(need) * 8, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(mg_export_kernel, grid1(need), dim3(256), 0, st, ctx->mg.E[level - 1].as<const double>(),
+                     ctx->mg.g[level - 1], out);
+  DG_HIP(hipGetLastError());
   return DG_OK;
 }
 
@@ -2101,18 +2106,18 @@ int dg_mg_apply(dg_ctx* ctx, dg_prec prec, const void* r, void* out, dg_stream s
   const int64_t FS = ctx->Ne * ctx->np, n7 = 7 * FS;
   const dim3 blk{256, 1, 1}, gagg{unsigned(M.G.na), 1, 1};
   if (prec == DG_F64) {
-    hipLaunchKernelGGL(agg_restrict_kernel<double>, gagg, blk, 0, st, M.ones.as<const double>(),
+    hipLaunchKernelGGL(mg_restrict_fine_kernel<double>, gagg, blk, 0, st, M.ones.as<const double>(),
                        static_cast<const double*>(r), M.G, FS, M.b[0].as<double>());
     const double* y = mg_vcycle(ctx, st);
     hipLaunchKernelGGL(mg_fill_kernel<double>, grid1(n7), blk, 0, st, static_cast<double*>(out), n7, 0.0);
-    hipLaunchKernelGGL(agg_prolong_add_kernel<double>, grid1(FS), blk, 0, st, M.ones.as<const double>(), y, M.G, FS,
+    hipLaunchKernelGGL(mg_prolong_fine_kernel<double>, grid1(FS), blk, 0, st, M.ones.as<const double>(), y, M.G, FS,
                        static_cast<double*>(out), static_cast<const double*>(nullptr));
   } else {
-    hipLaunchKernelGGL(agg_restrict_kernel<float>, gagg, blk, 0, st, M.ones.as<const float>(),
+    hipLaunchKernelGGL(mg_restrict_fine_kernel<float>, gagg, blk, 0, st, M.ones.as<const float>(),
                        static_cast<const float*>(r), M.G, FS, M.b[0].as<double>());
     const double* y = mg_vcycle(ctx, st);
     hipLaunchKernelGGL(mg_fill_kernel<float>, grid1(n7), blk, 0, st, static_cast<float*>(out), n7, 0.0f);
-    hipLaunchKernelGGL(agg_prolong_add_kernel<float>, grid1(FS), blk, 0, st, M.ones.as<const float>(), y, M.G, FS,
+    hipLaunchKernelGGL(mg_prolong_fine_kernel<float>, grid1(FS), blk, 0, st, M.ones.as<const float>(), y, M.G, FS,
                        static_cast<float*>(out), static_cast<const float*>(nullptr));
   }
   DG_HIP(hipGetLastError());
