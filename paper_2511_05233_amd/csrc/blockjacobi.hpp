@@ -11,7 +11,8 @@
 // In-place Gauss-Jordan with partial pivoting and no physical row swaps:
 // at step k the unused row p with the largest |a_ik| becomes the pivot of
 // column k, its row is broadcast with readlane, every other row is
-// eliminated, and column k is replaced by the corresponding column of the
+// eliminated and the pivot row scaled (one multiply-add per entry on every
+// lane), and column k is replaced by the corresponding column of the
 // partial inverse.  Rotating each row left by one after every step keeps
 // the active column at register 0, so no register is indexed dynamically.
 // With pivot rows p_0..p_{n-1} the result B satisfies
@@ -240,13 +241,13 @@ invert_blocks_kernel(S* __restrict__ B, int64_t Ne, int* __restrict__ status,
       kk = k;
     }
     const S inv = S(1) / pv;
-    const S f = r[0];
+    // one multiply-add per entry on every lane: the other rows take
+    // r_j - f inv p_j, the pivot row (whose broadcast entry is its own)
+    // r_j + (inv - 1) r_j = inv r_j
+    const S c = (lane == p) ? inv - S(1) : -r[0] * inv;
 #pragma unroll
-    for (int j = 1; j < NB; ++j) {
-      const S prow = bcast(r[j], p) * inv;
-      r[j - 1] = (lane == p) ? prow : r[j] - f * prow;
-    }
-    r[NB - 1] = (lane == p) ? inv : -f * inv;
+    for (int j = 1; j < NB; ++j) r[j - 1] = fma(c, bcast(r[j], p), r[j]);
+    r[NB - 1] = (lane == p) ? inv : c;
   }
   if (bad && lane == 0) atomicOr(status, 1);
 #pragma unroll
