@@ -804,7 +804,8 @@ def main(argv=None):
                     help="coarse solve by a V-cycle over this many aggregate levels (2..8; level-1 edge "
                          "--coarse-agg, 0: 4); 0: the exact two-level solve; default: the library's "
                          "automatic choice")
-    ap.add_argument("--mg-sweeps", type=int, default=2, help="block-Jacobi sweeps per level of the V-cycle")
+    ap.add_argument("--mg-sweeps", type=int, default=None,
+                    help="block-Jacobi sweeps per level of the V-cycle (default: the library's)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--oracle-timing", nargs=2, metavar=("WORKLOAD", "SECONDS"), default=None,
@@ -817,7 +818,8 @@ def main(argv=None):
         SOLVER_EXTRA["block_bf16"] = 0
     if args.mg_levels is not None:
         SOLVER_EXTRA["mg_levels"] = args.mg_levels
-    SOLVER_EXTRA["mg_sweeps"] = args.mg_sweeps
+    if args.mg_sweeps is not None:
+        SOLVER_EXTRA["mg_sweeps"] = args.mg_sweeps
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; "
               "run with --gpus 1.", file=sys.stderr)
@@ -944,7 +946,7 @@ def main(argv=None):
                             "accepted step of the naive time controller (backward-Euler Newton-GMRES "
                             "solves, halving dt on failure)"),
                    "coarse": args.coarse, "coarse_agg": args.coarse_agg, "mg_levels": "auto" if args.mg_levels is None else args.mg_levels,
-                   "mg_sweeps": args.mg_sweeps, "timed_steps": done, **{k: v for k, v in tot.items()}},
+                   "mg_sweeps": "library default" if args.mg_sweeps is None else args.mg_sweeps, "timed_steps": done, **{k: v for k, v in tot.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(w.name, k_op),

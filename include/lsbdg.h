@@ -231,7 +231,9 @@ typedef struct {
   double newton_tol;     /* converged when a full step changes no unknown by
                             more than this relative amount (default 1e-11) */
   int32_t coarse;        /* coarse space of the preconditioner: 0 = default
-                            (3), 1 = global per-field constants,
+                            (3, or 4 where the multilevel cycle of
+                            mg_levels is used), 1 = global per-field
+                            constants,
                             additive, 2 = global per-field constants with
                             deflation (exact coarse solve), 3 = per-field
                             constants on voxel aggregates, additive (a
@@ -279,7 +281,7 @@ typedef struct {
                             and the fewest levels whose last has at most
                             4096 unknowns (3 on the 96 x 96 x 192 slab) */
   int32_t mg_sweeps;     /* damped block-Jacobi sweeps before and after each
-                            coarse correction of the cycle, 0..8 (default 2) */
+                            coarse correction of the cycle, 0..8 (default 3) */
   double mg_omega;       /* their damping, in (0, 1] (default 0.7) */
 } dg_solver_opts;
 

@@ -429,7 +429,7 @@ class Context:
             self._h, _prec(x), _ptr(x), _ptr(out), _stream()))
         return out
 
-    def mg_setup(self, u, t_new, dt, levels, agg=0, sweeps=2, omega=0.7, dtype=None):
+    def mg_setup(self, u, t_new, dt, levels, agg=0, sweeps=3, omega=0.7, dtype=None):
         """dg_mg_setup: linearise at u (precision dtype) and build the
         multilevel hierarchy (levels 2..8, level-1 aggregate edge agg)."""
         self._check_arr(u, 9)
