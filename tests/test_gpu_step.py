@@ -172,6 +172,26 @@ def test_step_with_multigrid_coarse_correction(small_case, inner, tol, coarse):
     assert np.all(err < tol), err
 
 
+def test_automatic_multigrid_choice():
+    """mg_levels = -1 (the default) runs the multilevel cycle only where the
+    exact two-level space would need coarse aggregates: on 24^3 voxels with
+    2^3-voxel aggregates (1,728 aggregates, 12,096 coarse unknowns) a
+    two-level cycle down to 6^3 aggregates, with 4^3-voxel aggregates (1,512
+    unknowns) and by default (edge up to 8) the exact solve.  The report
+    names the levels used; every choice reaches the same root."""
+    P, ctx, mask = problem_and_context(24, 24, 24, porosity=0.6, mask_seed=5, param_seed=5, f_C=0.1)
+    u0, _ = ctx.initial_state(inner="f32")
+    roots, levels = {}, {}
+    for name, opts in (("agg2", {"coarse_agg": 2}), ("agg4", {"coarse_agg": 4}), ("default", {})):
+        ut = u0.clone()
+        rep = ctx.step(ut, 0.0, 0.1, inner="f32", **opts)
+        roots[name], levels[name] = ut.cpu().numpy(), rep["mg_levels"]
+        print(f"[step] 24^3 {name}: {rep}", flush=True)
+    assert levels == {"agg2": 2, "agg4": 0, "default": 0}, levels
+    for name in ("agg2", "agg4"):
+        assert np.all(rel_l2(roots[name], roots["default"])[:7] < 1e-8)
+
+
 def test_aggregation_coarse_space_cuts_gmres_on_cube16():
     """16^3 cube, first implicit step from the GPU initial state: the
     aggregation coarse space needs fewer GMRES iterations than the global
