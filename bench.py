@@ -806,6 +806,8 @@ def main(argv=None):
                          "automatic choice")
     ap.add_argument("--mg-sweeps", type=int, default=None,
                     help="block-Jacobi sweeps per level of the V-cycle (default: the library's)")
+    ap.add_argument("--block-reuse", type=float, default=None,
+                    help="keep the element blocks while Newton updates stay below this relative size")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--oracle-timing", nargs=2, metavar=("WORKLOAD", "SECONDS"), default=None,
@@ -820,6 +822,8 @@ def main(argv=None):
         SOLVER_EXTRA["mg_levels"] = args.mg_levels
     if args.mg_sweeps is not None:
         SOLVER_EXTRA["mg_sweeps"] = args.mg_sweeps
+    if args.block_reuse is not None:
+        SOLVER_EXTRA["block_reuse"] = args.block_reuse
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; "
               "run with --gpus 1.", file=sys.stderr)

@@ -283,6 +283,13 @@ typedef struct {
   int32_t mg_sweeps;     /* damped block-Jacobi sweeps before and after each
                             coarse correction of the cycle, 0..8 (default 3) */
   double mg_omega;       /* their damping, in (0, 1] (default 0.7) */
+  double block_reuse;    /* > 0 (default 1): the element blocks are built
+                            at the first Newton iterate and rebuilt after an
+                            update whose largest relative change of an
+                            unknown exceeded block_reuse (the blocks of an
+                            earlier iterate precondition the later ones;
+                            only the preconditioner changes, not the root);
+                            0: rebuilt at every iterate */
 } dg_solver_opts;
 
 void dg_solver_opts_default(dg_solver_opts* o);
@@ -390,6 +397,8 @@ typedef struct {
   double merit_final;     /* ... after the last accepted update */
   double last_update;     /* largest relative change of the last update */
   double gmres_last_rel;  /* relative GMRES residual of the last solve */
+  int32_t block_builds;   /* element-block assemblies and inversions */
+  int32_t pad2;
 } dg_step_report;
 
 /* One backward-Euler step (Eq. 50) from t_n to t_n + dt: on entry u holds

@@ -974,7 +974,14 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     hipLaunchKernelGGL((cast_kernel<double, S>), grid1(n9), blk, 0, st, u, uS, n9);
     if (int s = linearize<S>(ctx, P, uS, st)) return s;
     // FP32 inner solves with block_bf16 use only the bfloat16 inverses
-    if (int s = blocks_setup<S>(ctx, P, uS, st, std::is_same<S, float>::value && o.block_bf16 != 0)) return s;
+    // the element blocks are rebuilt at every iterate, or (block_reuse > 0)
+    // only at the first and after an update whose largest relative change
+    // exceeded block_reuse: near the root the Jacobian moves by the size of
+    // the update, and blocks of an earlier iterate precondition as well
+    if (it == 1 || !(o.block_reuse > 0.0) || r.last_update > o.block_reuse) {
+      if (int s = blocks_setup<S>(ctx, P, uS, st, std::is_same<S, float>::value && o.block_bf16 != 0)) return s;
+      ++r.block_builds;
+    }
     hipLaunchKernelGGL(scales_kernel<S>, grid1(n7), blk, 0, st, u, sc, FS, phi_floor);
     // the aggregation coarse operator is rebuilt at the first iterate, after
     // an update whose largest relative change of an unknown exceeded 2 (E
@@ -1259,6 +1266,7 @@ int normalize_opts(const dg_solver_opts* in, dg_solver_opts& o, const char* fn) 
       return fail(DG_EINVAL, std::string(fn) + ": mg_omega must be in (0, 1]");
   }
   if (o.coarse_agg < 0) return fail(DG_EINVAL, std::string(fn) + ": coarse_agg must be >= 0");
+  if (!(o.block_reuse >= 0.0)) return fail(DG_EINVAL, std::string(fn) + ": block_reuse must be >= 0");
   return DG_OK;
 }
 
@@ -2161,6 +2169,7 @@ void dg_solver_opts_default(dg_solver_opts* o) {
   o->mg_levels = -1;       // multilevel cycle where the exact two-level space would need coarse aggregates
   o->mg_sweeps = 3;
   o->mg_omega = 0.7;
+  o->block_reuse = 1.0;    // element blocks kept while updates change no unknown by more than 100%
 }
 
 int dg_step(dg_ctx* ctx, double t_n, double dt, void* u, const dg_solver_opts* opts,

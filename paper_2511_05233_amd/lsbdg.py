@@ -100,16 +100,18 @@ class DgSolverOpts(C.Structure):
                 ("newton_tol", C.c_double),
                 ("coarse", C.c_int32), ("coarse_agg", C.c_int32), ("block_bf16", C.c_int32),
                 ("verbose", C.c_int32), ("coarse_every", C.c_int32), ("limiter", C.c_int32),
-                ("mg_levels", C.c_int32), ("mg_sweeps", C.c_int32), ("mg_omega", C.c_double)]
+                ("mg_levels", C.c_int32), ("mg_sweeps", C.c_int32), ("mg_omega", C.c_double),
+                ("block_reuse", C.c_double)]
 
 
 class DgStepReport(C.Structure):
     _fields_ = [("newton_its", C.c_int32), ("gmres_its", C.c_int32), ("line_search_cuts", C.c_int32),
                 ("status", C.c_int32), ("stalled", C.c_int32), ("mg_levels", C.c_int32), ("merit0", C.c_double), ("merit_final", C.c_double),
-                ("last_update", C.c_double), ("gmres_last_rel", C.c_double)]
+                ("last_update", C.c_double), ("gmres_last_rel", C.c_double), ("block_builds", C.c_int32),
+                ("pad2", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad2"}
 
 
 DG_BOP_RESIDUAL, DG_BOP_JVP_FULL9, DG_BOP_JVP_CONDENSED7 = 0, 1, 2
