@@ -319,9 +319,11 @@ void dg_solver_opts_default(dg_solver_opts* o);
  * level-1 aggregates of opts->coarse_agg voxels per edge (0: 4).  Replaces
  * the stored linearisation.  Q1 only.  Synchronises the stream.  Errors:
  * DG_EINVAL (null array, dt <= 0, bad precision or options, a last level
- * of more than 8192 unknowns), DG_EUNSUPPORTED (order != 1), DG_ENOMEM,
- * DG_ENAN (singular last level), DG_EHIP.  A later dg_step with
- * mg_levels >= 2 reuses these buffers and ends this hierarchy's validity.
+ * of more than 1024 aggregates: it is solved densely with 8 unknowns per
+ * aggregate, the seven fields and a zero pad), DG_EUNSUPPORTED (order !=
+ * 1), DG_ENOMEM, DG_ENAN (singular last level), DG_EHIP.  A later solve
+ * (dg_step, dg_initial_state, dg_advance) that runs the multilevel cycle
+ * reuses these buffers and ends this hierarchy's validity.
  *
  * dg_mg_apply: out = Z V_1(Z^T r) for 7-field vectors r, out of precision
  * prec (that of the setup); out is overwritten.  Errors: DG_EINVAL (null
