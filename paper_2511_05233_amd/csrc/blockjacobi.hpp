@@ -24,7 +24,8 @@
 // that lane r of the apply reads four columns of its row with one 16-byte
 // (FP32) load and a wavefront's load covers a contiguous 56 x 16 bytes.
 //
-// Apply: y_e = B_e^{-1} x_e, one wavefront per element, lane r = row r.
+// Apply: y_e = B_e^{-1} x_e, one wavefront per element, lane r = row r;
+// optionally (y + a) / d entrywise in the same pass.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -277,7 +278,8 @@ export_blocks_kernel(const S* __restrict__ B, S* __restrict__ out, int64_t Ne) {
 // y_e = B_e x_e for vectors in the field-major layout [f][e][n] (NF fields).
 template <typename S, int NF>
 __global__ void __launch_bounds__(256)
-apply_blocks_kernel(const S* __restrict__ B, const S* __restrict__ X, S* __restrict__ Y, int64_t Ne) {
+apply_blocks_kernel(const S* __restrict__ B, const S* __restrict__ X, S* __restrict__ Y, int64_t Ne,
+                    const S* __restrict__ A = nullptr, const S* __restrict__ D = nullptr) {
   constexpr int NB = NF * 8;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -299,7 +301,13 @@ apply_blocks_kernel(const S* __restrict__ B, const S* __restrict__ X, S* __restr
     acc += q.c * bcast(xl, 4 * c4 + 2);
     acc += q.d * bcast(xl, 4 * c4 + 3);
   }
-  if (act) Y[fl * FS + e * 8 + nl] = acc;
+  if (act) {
+    // optional epilogue of the two-level preconditioner: (B x + A) / D
+    const int64_t idx = fl * FS + e * 8 + nl;
+    if (A) acc = A[idx] + acc;
+    if (D) acc = acc / D[idx];
+    Y[idx] = acc;
+  }
 }
 
 template <int NB>
@@ -317,7 +325,7 @@ blocks_to_bf16_kernel(const float* __restrict__ B, uint16_t* __restrict__ H, int
 template <int NF>
 __global__ void __launch_bounds__(256)
 apply_blocks_bf16_kernel(const uint16_t* __restrict__ H, const float* __restrict__ X, float* __restrict__ Y,
-                         int64_t Ne) {
+                         int64_t Ne, const float* __restrict__ A = nullptr, const float* __restrict__ D = nullptr) {
   constexpr int NB = NF * 8;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -340,7 +348,13 @@ apply_blocks_bf16_kernel(const uint16_t* __restrict__ H, const float* __restrict
       acc += __uint_as_float(wd[t] & 0xffff0000u) * bcast(xl, 8 * c8 + 2 * t + 1);
     }
   }
-  if (act) Y[fl * FS + e * 8 + nl] = acc;
+  if (act) {
+    // optional epilogue of the two-level preconditioner: (B x + A) / D
+    const int64_t idx = fl * FS + e * 8 + nl;
+    if (A) acc = A[idx] + acc;
+    if (D) acc = acc / D[idx];
+    Y[idx] = acc;
+  }
 }
 
 }  // namespace lsbdg

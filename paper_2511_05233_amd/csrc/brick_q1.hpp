@@ -400,7 +400,8 @@ template <typename S>
 __device__ __forceinline__ void brick_jvp(const S* __restrict__ U, const S* __restrict__ V,
                                           const S* __restrict__ Cw, S* __restrict__ Out,
                                           const uint8_t* __restrict__ phase, const KP<S>& K, int nbx, int nby,
-                                          int64_t brick, int64_t FS, BrickLds<S>& L) {
+                                          int64_t brick, int64_t FS, BrickLds<S>& L,
+                                          const S* __restrict__ Rsub = nullptr) {
   const int lane = threadIdx.x;
   const int n = lane & 7, vb = lane >> 3;
   const int bx = vb & 3, by = (vb >> 2) & 3, bz = vb >> 4;
@@ -574,18 +575,22 @@ __device__ __forceinline__ void brick_jvp(const S* __restrict__ U, const S* __re
 #pragma unroll
   for (int f = 0; f < 7; ++f) {
     const bool on = (K.active >> f) & 1;
-    Out[f * FS + e * 8 + n] = on ? acc[f] : S(0);
+    const int64_t idx = f * FS + e * 8 + n;
+    const S jv = on ? acc[f] : S(0);
+    Out[idx] = Rsub ? Rsub[idx] - jv : jv;
   }
 }
 
-// One structure: one workgroup per brick, XCD-aware order.
+// One structure: one workgroup per brick, XCD-aware order.  Rsub
+// (optional): Out = Rsub - J v instead (the residual the multiplicative
+// preconditioner leaves to the element blocks).
 template <typename S>
 __global__ void __launch_bounds__(kBrickLanes)
 q1_brick_jvp_kernel(const S* __restrict__ U, const S* __restrict__ V, const S* __restrict__ Cw,
                     S* __restrict__ Out, const uint8_t* __restrict__ phase, KP<S> K, int nbx, int nby,
-                    int64_t nbricks_padded) {
+                    int64_t nbricks_padded, const S* __restrict__ Rsub = nullptr) {
   __shared__ BrickLds<S> L;
-  brick_jvp(U, V, Cw, Out, phase, K, nbx, nby, xcd_block(nbricks_padded), K.Ne * 8, L);
+  brick_jvp(U, V, Cw, Out, phase, K, nbx, nby, xcd_block(nbricks_padded), K.Ne * 8, L, Rsub);
 }
 
 }  // namespace lsbdg

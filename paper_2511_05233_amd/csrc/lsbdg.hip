@@ -283,13 +283,13 @@ void launch_q1(const dg_ctx* ctx, const DevParams& P, const void* u, const void*
 // workgroup per brick of 4 x 4 x 4 voxels (inner faces evaluated once).
 template <typename S>
 void launch_brick_jvp(const dg_ctx* ctx, const DevParams& P, const void* u, const void* v, const void* lin,
-                      void* out, hipStream_t st) {
+                      void* out, hipStream_t st, const void* rsub = nullptr) {
   const int nbx = (ctx->mesh.nx + kBE - 1) / kBE, nby = (ctx->mesh.ny + kBE - 1) / kBE;
   const int64_t nbz = (ctx->mesh.nz + kBE - 1) / kBE;
   const int64_t nb = (int64_t(nbx) * nby * nbz + 7) / 8 * 8;
   hipLaunchKernelGGL(q1_brick_jvp_kernel<S>, dim3(unsigned(nb)), dim3(kBrickLanes), 0, st,
                      static_cast<const S*>(u), static_cast<const S*>(v), static_cast<const S*>(lin),
-                     static_cast<S*>(out), ctx->d_phase, make_kp<S>(P), nbx, nby, nb);
+                     static_cast<S*>(out), ctx->d_phase, make_kp<S>(P), nbx, nby, nb, static_cast<const S*>(rsub));
 }
 
 // Linearisation coefficients of the condensed tangent at u (precision S).
@@ -843,8 +843,7 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     if (mgm) {
       hipLaunchKernelGGL(mg_restrict_fine_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, MG.b[0].as<double>());
       const double* y = mg_vcycle(ctx, st);
-      if (!add) hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(0), out, S(0), out, n7);
-      hipLaunchKernelGGL(mg_prolong_fine_kernel<S>, grid1(FS), blk, 0, st, scc, y, G, FS, out, div);
+      hipLaunchKernelGGL(mg_prolong_fine_kernel<S>, grid1(FS), blk, 0, st, scc, y, G, FS, out, div, !add);
       return;
     }
     hipLaunchKernelGGL(agg_restrict_kernel<S>, gagg, blk, 0, st, scc, r, G, FS, crc);
@@ -861,23 +860,22 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
     auto unscale = [&]() { hipLaunchKernelGGL((emul_kernel<S, true>), grid1(n7), blk, 0, st, sc, out, out, n7); };
     if (o.coarse == 4) {
       // multiplicative two-level: coarse solve, then the element blocks on
-      // the remaining residual: out = c + B^-1 (r - J c), c = Z E^-1 Z^T r
+      // the remaining residual: out = (c + B^-1 (r - J c)) / sc with
+      // c = Z E^-1 Z^T r; the Krylov operator forms r - J c and the block
+      // apply adds c and divides by the scales in their own passes
       coarse_solve_into(r, pc, false);
-      jvp_cond(pc, pc2);
-      hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), r, S(-1), pc2, n7);
+      launch_brick_jvp<S>(ctx, P, uS, pc, ctx->lin.p, pc2, st, r);
       if constexpr (std::is_same<S, float>::value) {
         if (o.block_bf16)
           hipLaunchKernelGGL((apply_blocks_bf16_kernel<7>), gw, blk, 0, st, ctx->bh.as<const uint16_t>(), pc2,
-                             out, ctx->Ne);
+                             out, ctx->Ne, pc, sc);
         else
           hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, ctx->blocks.as<const S>(),
-                             pc2, out, ctx->Ne);
+                             pc2, out, ctx->Ne, pc, sc);
       } else {
         hipLaunchKernelGGL((apply_blocks_kernel<S, 7>), gw, blk, 0, st, ctx->blocks.as<const S>(), pc2,
-                           out, ctx->Ne);
+                           out, ctx->Ne, pc, sc);
       }
-      hipLaunchKernelGGL(axpby_kernel<S>, grid1(n7), blk, 0, st, S(1), pc, S(1), out, n7);
-      unscale();
       return;
     }
     deflate(r);

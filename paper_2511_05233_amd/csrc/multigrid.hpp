@@ -95,17 +95,18 @@ mg_restrict_fine_kernel(const S* __restrict__ sc, const S* __restrict__ r, AggGr
   if (threadIdx.x < 8) b[a * 8 + threadIdx.x] = threadIdx.x < 7 ? acc[threadIdx.x] : 0.0;
 }
 
-// Level-1-to-fine prolongation out += Z y (y[a][8]), one thread per node;
-// div (optional): the sum divided entrywise by div in the same pass.
+// Level-1-to-fine prolongation out += Z y (y[a][8]), or out = Z y when
+// set, one thread per node; div (optional): the result divided entrywise
+// by div in the same pass.
 template <typename S>
 __global__ void __launch_bounds__(256)
 mg_prolong_fine_kernel(const S* __restrict__ sc, const double* __restrict__ y, AggGrid G, int64_t FS,
-                       S* __restrict__ out, const S* __restrict__ div) {
+                       S* __restrict__ out, const S* __restrict__ div, bool set = false) {
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < FS; k += int64_t(gridDim.x) * 256) {
     const int64_t a = agg_of_voxel(G, k >> 3);
 #pragma unroll
     for (int g = 0; g < 7; ++g) {
-      const S v = out[g * FS + k] + sc[g * FS + k] * S(y[a * 8 + g]);
+      const S v = (set ? S(0) : out[g * FS + k]) + sc[g * FS + k] * S(y[a * 8 + g]);
       out[g * FS + k] = div ? v / div[g * FS + k] : v;
     }
   }
