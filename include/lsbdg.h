@@ -410,10 +410,12 @@ typedef struct {
  * are updated multiplicatively (Newton in their logarithms).  Each linear
  * solve is GMRES(m) on the condensed 7-field Jacobian, scaled by the unknown
  * magnitudes and preconditioned by the element blocks plus a coarse
- * correction (opts.coarse), in the inner precision of opts (NULL:
- * defaults).  The operator and the element blocks are rebuilt at every
- * Newton iterate, the aggregation coarse operator every opts.coarse_every
- * iterates.  Device workspace is allocated on first use and kept (a
+ * correction (opts.coarse: an exact two-level solve, or the multigrid
+ * V-cycle of opts.mg_levels), in the inner precision of opts (NULL:
+ * defaults).  The operator is rebuilt at every Newton iterate, the element
+ * blocks at the first and after large updates (opts.block_reuse), the
+ * coarse operator every opts.coarse_every iterates and after large
+ * updates.  Device workspace is allocated on first use and kept (a
  * context of dg_setup_ws takes it from the caller's workspace).
  * Converged when a full step changes no unknown by more than newton_tol,
  * or, once an update below 1e-7 has been reached (the attainable accuracy
