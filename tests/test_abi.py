@@ -153,7 +153,17 @@ def test_orders_and_workspace_sizes_are_checked_on_the_host(lib):
     ops = al(al(al(12) + 4) + 14 * 12 * 64 * 8) + 15 * 1024 * 8
     assert n.value == al(al(al(al(ops) + 12 * 448 * 448 * 4) + 12 * 448 * 2) + 14 * 12 * 64 * 4)
     mesh = lsbdg.DgMesh(96, 96, 192, 1, 1e-6)
-    assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, 64, C.byref(n)) == -1
+    assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, 128, C.byref(n)) == -1   # unknown bit
+    # the multigrid workspace needs explicit levels; bad solver options are
+    # refused before any device call
+    assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, lsbdg.DG_WS_MG, C.byref(n)) == -1
+    for field, bad in (("mg_levels", 1), ("mg_levels", 9), ("mg_levels", -2), ("mg_sweeps", 9), ("mg_omega", 0.0),
+                       ("mg_omega", 1.5), ("block_reuse", -1.0), ("coarse_agg", -1), ("coarse", 5)):
+        o = lsbdg._solver_opts("f32", {field: bad})
+        assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), C.byref(o), lsbdg.DG_WS_OPERATORS,
+                                      C.byref(n)) == -1, (field, bad)
+    o = lsbdg._solver_opts("f32", {})
+    assert (o.mg_levels, o.mg_sweeps, o.mg_omega, o.block_reuse, o.coarse) == (-1, 3, 0.7, 1.0, 0)
     assert lib.dg_workspace_bytes(C.byref(mesh), C.byref(p), None, lsbdg.DG_WS_OPERATORS, C.byref(n)) == 0
     al = lambda x: (x + 255) // 256 * 256
     Ne = 96 * 96 * 192
