@@ -86,31 +86,6 @@ __device__ __forceinline__ void store_block_sums(S (&acc)[kMaxDots], int nv, S (
   if (i < nv) partial[i * gridDim.x + blockIdx.x] = sh[0][i] + sh[1][i] + sh[2][i] + sh[3][i];
 }
 
-// partial[i * gridDim + b] = sum over block b's share of V_i . w, i < nv
-template <typename S>
-__global__ void __launch_bounds__(256)
-multi_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ w, int64_t n,
-                 S* __restrict__ partial) {
-  // four consecutive entries per thread (n and ldv are multiples of 4:
-  // Krylov vectors hold 7 fields x 8 nodes per voxel)
-  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
-  __shared__ S sh[4][kMaxDots];
-  S acc[kMaxDots];
-#pragma unroll
-  for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
-  const int64_t n4 = n >> 2;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
-    const Q wk = reinterpret_cast<const Q*>(w)[k];
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nv) {
-        const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
-        acc[i] += v.a * wk.a + v.b * wk.b + v.c * wk.c + v.d * wk.d;
-      }
-  }
-  store_block_sums(acc, nv, sh, partial);
-}
-
 // out[i] = sum_b partial[i * nb + b]; one block per i
 template <typename S>
 __global__ void __launch_bounds__(256) finish_sum_kernel(const S* __restrict__ partial, int nb,
@@ -146,86 +121,6 @@ multi_axpy_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restr
     wk.d += sign * acc.d;
     reinterpret_cast<Q*>(w)[k] = wk;
   }
-}
-
-// One sweep of classical Gram-Schmidt applied twice: w -= sum_i h[i] V_i
-// (the first pass's update), then partial sums of V_i . w for the updated w
-// (the second pass's projections).  Each thread holds its quads of the
-// basis in registers between the two, so the basis streams from HBM once
-// for both; the arithmetic per entry is that of multi_axpy_kernel and
-// multi_dot_kernel.  Launch with the grid of multi_dot_kernel.
-template <typename S>
-__global__ void __launch_bounds__(256)
-multi_axpy_dot_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h,
-                      S* __restrict__ w, int64_t n, S* __restrict__ partial) {
-  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
-  __shared__ S sh[4][kMaxDots];
-  S acc[kMaxDots];
-#pragma unroll
-  for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
-  const int64_t n4 = n >> 2;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
-    Q vq[kMaxDots];
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nv) vq[i] = reinterpret_cast<const Q*>(V + i * ldv)[k];
-    Q s{S(0), S(0), S(0), S(0)};
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nv) {
-        const S hi = h[i];
-        s.a += hi * vq[i].a;
-        s.b += hi * vq[i].b;
-        s.c += hi * vq[i].c;
-        s.d += hi * vq[i].d;
-      }
-    Q wk = reinterpret_cast<Q*>(w)[k];
-    wk.a += S(-1) * s.a;
-    wk.b += S(-1) * s.b;
-    wk.c += S(-1) * s.c;
-    wk.d += S(-1) * s.d;
-    reinterpret_cast<Q*>(w)[k] = wk;
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nv) acc[i] += vq[i].a * wk.a + vq[i].b * wk.b + vq[i].c * wk.c + vq[i].d * wk.d;
-  }
-  store_block_sums(acc, nv, sh, partial);
-}
-
-// The second pass's update w -= sum_i h[i] V_i with partial sums of |w|^2
-// of the result in FP64 (one per block).
-template <typename S>
-__global__ void __launch_bounds__(256)
-multi_axpy_sumsq_kernel(const S* __restrict__ V, int64_t ldv, int nv, const S* __restrict__ h,
-                        S* __restrict__ w, int64_t n, double* __restrict__ partial) {
-  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
-  __shared__ double sh[4];
-  double acc = 0.0;
-  const int64_t n4 = n >> 2;
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
-    Q s{S(0), S(0), S(0), S(0)};
-    for (int i = 0; i < nv; ++i) {
-      const S hi = h[i];
-      const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
-      s.a += hi * v.a;
-      s.b += hi * v.b;
-      s.c += hi * v.c;
-      s.d += hi * v.d;
-    }
-    Q wk = reinterpret_cast<Q*>(w)[k];
-    wk.a += S(-1) * s.a;
-    wk.b += S(-1) * s.b;
-    wk.c += S(-1) * s.c;
-    wk.d += S(-1) * s.d;
-    reinterpret_cast<Q*>(w)[k] = wk;
-    const double a = double(wk.a), b = double(wk.b), c = double(wk.c), d = double(wk.d);
-    acc += a * a;
-    acc += b * b;
-    acc += c * c;
-    acc += d * d;
-  }
-  const double sum = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = sum;
 }
 
 // partial sums per field f < 7 of a_f * b_f (field stride FS)
@@ -499,6 +394,14 @@ struct GmresState {
   int32_t converged;               // the stopping test held
   int32_t cols;                    // columns of the cycle (j + 1 at the end)
   int32_t its;                     // iterations of the whole solve
+  // delayed reorthogonalisation (dcgs_* kernels): the unrotated Hessenberg
+  // matrix, the second-pass coefficients c and the norm ratio gam of the
+  // newest basis vector (stored once orthogonalised, unit norm), this
+  // iteration's first-pass coefficients h1 and the factor alpha
+  double Hu[kMaxDots * kMaxDots];
+  double c[kMaxDots];
+  double h1[kMaxDots];
+  double gam, alpha;
 };
 
 // Start of a cycle: beta = |r0| from block partials of its square; g = beta
@@ -525,22 +428,171 @@ gmres_start_kernel(GmresState* __restrict__ st, const double* __restrict__ parti
   st->done = ok ? 0 : 1;
   st->converged = ok ? 0 : 1;
   st->scale = ok ? 1.0 / beta : 0.0;
+  st->gam = 1.0;                   // the first basis vector is exact
 }
 
-// Column j of the cycle from one Gram-Schmidt step's device sums
-// gs = [|w|^2 (FP64)][h1 (kMaxDots x S)][h2 (kMaxDots x S)]: h_ij = h1_i +
-// h2_i, h_{j+1,j} = |w|; the previous rotations, a new one, the rotated
-// right side and the stopping test.  One thread (m <= 30: a few hundred
-// flops); no-op once the cycle is done.
+// ---- Classical Gram-Schmidt applied twice, the second pass delayed ----
+//
+// The second projection of iteration j is not applied at once: the basis
+// vector is stored once orthogonalised, vt_{j+1} = w1 / |w1| (unit norm),
+// with its second-pass coefficients c = h2 / |w1| and gam = |w2| / |w1|
+// (|w2|^2 = |w1|^2 - |h2|^2 for orthonormal V).  The next iteration applies
+// the operator to vt_{j+1}, z = A vt_{j+1}, and in one sweep over the basis
+// both corrects the vector, v_{j+1} = (vt_{j+1} - V c) / gam, and forms the
+// projections V^T z and vt^T z.  Since A v = (z - A V c) / gam and, by the
+// Arnoldi relation of the earlier columns (unrotated Hessenberg Hu),
+// A V c = V (Hu c), the first-pass coefficients of A v_{j+1} follow from those
+// dots without another sweep, and one further sweep forms w1 and its
+// second-pass projections.  Two sweeps over the basis per iteration instead
+// of three; in exact arithmetic the iterates are those of the undelayed
+// method.
+
+// Sweep 1 of iteration j: V_j <- (V_j - sum_{i<j} c_i V_i) / gam (skipped
+// once the cycle is done), with partial sums of V_i . z (i < j) and of the
+// uncorrected V_j . z (slot j).
+template <typename S>
+__global__ void __launch_bounds__(256)
+dcgs_sweep1_kernel(const GmresState* __restrict__ st, S* __restrict__ V, int64_t ldv, int j,
+                   const S* __restrict__ z, int64_t n, S* __restrict__ partial) {
+  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
+  __shared__ S sh[4][kMaxDots];
+  const bool write = !st->done;
+  S cs[kMaxDots];
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) cs[i] = i < j ? S(st->c[i]) : S(0);
+  const S ig = S(1.0 / st->gam);
+  S acc[kMaxDots];
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
+  const int64_t n4 = n >> 2;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    const Q zk = reinterpret_cast<const Q*>(z)[k];
+    const Q vt = reinterpret_cast<const Q*>(V + j * ldv)[k];
+    Q s{S(0), S(0), S(0), S(0)};
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < j) {
+        const Q v = reinterpret_cast<const Q*>(V + i * ldv)[k];
+        acc[i] += v.a * zk.a + v.b * zk.b + v.c * zk.c + v.d * zk.d;
+        s.a += cs[i] * v.a;
+        s.b += cs[i] * v.b;
+        s.c += cs[i] * v.c;
+        s.d += cs[i] * v.d;
+      }
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i == j) acc[i] += vt.a * zk.a + vt.b * zk.b + vt.c * zk.c + vt.d * zk.d;
+    if (write && j > 0) {
+      Q o;
+      o.a = (vt.a - s.a) * ig;
+      o.b = (vt.b - s.b) * ig;
+      o.c = (vt.c - s.c) * ig;
+      o.d = (vt.d - s.d) * ig;
+      reinterpret_cast<Q*>(V + j * ldv)[k] = o;
+    }
+  }
+  store_block_sums(acc, j + 1, sh, partial);
+}
+
+// Coefficients of iteration j from sweep 1's sums d (d_i = V_i . z, i < j;
+// d_j = vt_j . z): g = Hu[0..j, 0..j-1] c, V^T z with (V^T z)_j =
+// (d_j - c . d) / gam, h1 = (V^T z - g) / gam (kept in the state), and
+// sweep 2's w1 = alpha z - V beta with alpha = 1 / gam, beta = g / gam + h1.
+// One thread; no-op once the cycle is done.
 template <typename S>
 __global__ void __launch_bounds__(64)
-gmres_column_kernel(GmresState* __restrict__ st, const double* __restrict__ gs, int j, int m) {
+dcgs_coef_kernel(GmresState* __restrict__ st, const S* __restrict__ d, int j, S* __restrict__ beta) {
   if (threadIdx.x != 0 || st->done) return;
-  const S* h1 = reinterpret_cast<const S*>(gs + 1);
-  const S* h2 = h1 + kMaxDots;
+  const double gam = st->gam;
+  double cd = 0.0;
+  for (int i = 0; i < j; ++i) cd += st->c[i] * double(d[i]);
+  for (int k = 0; k <= j; ++k) {
+    double g = 0.0;
+    for (int i = 0; i < j; ++i) g += st->Hu[k * kMaxDots + i] * st->c[i];
+    const double vz = k < j ? double(d[k]) : (double(d[j]) - cd) / gam;
+    const double h1 = (vz - g) / gam;
+    st->h1[k] = h1;
+    beta[k] = S(g / gam + h1);
+  }
+  st->alpha = 1.0 / gam;
+}
+
+// Sweep 2 of iteration j: w <- alpha w - sum_{i<nv} beta_i V_i (w holds z on
+// entry), with partial sums of V_i . w (the second-pass projections) and
+// FP64 partial sums of |w|^2.
+template <typename S>
+__global__ void __launch_bounds__(256)
+dcgs_sweep2_kernel(const GmresState* __restrict__ st, const S* __restrict__ V, int64_t ldv, int nv,
+                   const S* __restrict__ beta, S* __restrict__ w, int64_t n, S* __restrict__ partial,
+                   double* __restrict__ partial64) {
+  struct alignas(4 * sizeof(S)) Q { S a, b, c, d; };
+  __shared__ S sh[4][kMaxDots];
+  __shared__ double sh64[4];
+  const S al = S(st->alpha);
+  S acc[kMaxDots];
+#pragma unroll
+  for (int i = 0; i < kMaxDots; ++i) acc[i] = S(0);
+  double nrm = 0.0;
+  const int64_t n4 = n >> 2;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n4; k += int64_t(gridDim.x) * 256) {
+    Q vq[kMaxDots];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) vq[i] = reinterpret_cast<const Q*>(V + i * ldv)[k];
+    Q s{S(0), S(0), S(0), S(0)};
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) {
+        const S bi = beta[i];
+        s.a += bi * vq[i].a;
+        s.b += bi * vq[i].b;
+        s.c += bi * vq[i].c;
+        s.d += bi * vq[i].d;
+      }
+    Q wk = reinterpret_cast<Q*>(w)[k];
+    wk.a = al * wk.a - s.a;
+    wk.b = al * wk.b - s.b;
+    wk.c = al * wk.c - s.c;
+    wk.d = al * wk.d - s.d;
+    reinterpret_cast<Q*>(w)[k] = wk;
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nv) acc[i] += vq[i].a * wk.a + vq[i].b * wk.b + vq[i].c * wk.c + vq[i].d * wk.d;
+    const double a = double(wk.a), b = double(wk.b), c = double(wk.c), d = double(wk.d);
+    nrm += a * a;
+    nrm += b * b;
+    nrm += c * c;
+    nrm += d * d;
+  }
+  store_block_sums(acc, nv, sh, partial);
+  const double t = block_sum(nrm, sh64);
+  if (threadIdx.x == 0) partial64[blockIdx.x] = t;
+}
+
+// Column j from sweep 2's sums gs = [|w1|^2 (FP64)][.. (kMaxDots x S)][h2
+// (kMaxDots x S)]: Hu[:, j] = h1 + h2, Hu[j+1, j] = |w2| = sqrt(|w1|^2 -
+// |h2|^2); the rotations, the rotated right side and the stopping test as
+// gmres_column_kernel; then c = h2 / |w1|, gam = |w2| / |w1| and the scale
+// 1 / |w1| of the next (once orthogonalised) basis vector.  One thread;
+// no-op once the cycle is done.
+template <typename S>
+__global__ void __launch_bounds__(64)
+dcgs_column_kernel(GmresState* __restrict__ st, const double* __restrict__ gs, int j, int m) {
+  if (threadIdx.x != 0 || st->done) return;
+  const S* h2 = reinterpret_cast<const S*>(gs + 1) + kMaxDots;
   double* H = st->H;
-  for (int i = 0; i <= j; ++i) H[i * kMaxDots + j] = double(h1[i]) + double(h2[i]);
-  const double hn = sqrt(gs[0]);
+  const double nw1 = sqrt(gs[0]);
+  double h2sq = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    const double h = double(h2[i]);
+    h2sq += h * h;
+    st->Hu[i * kMaxDots + j] = st->h1[i] + h;
+    H[i * kMaxDots + j] = st->h1[i] + h;
+  }
+  const double w2sq = gs[0] - h2sq;
+  const double hn = w2sq > 0.0 ? sqrt(w2sq) : 0.0;
+  st->Hu[(j + 1) * kMaxDots + j] = hn;
+  for (int i = j + 2; i < kMaxDots; ++i) st->Hu[i * kMaxDots + j] = 0.0;   // Hessenberg: below is zero
   H[(j + 1) * kMaxDots + j] = hn;
   for (int i = 0; i < j; ++i) {
     const double a = H[i * kMaxDots + j], c = H[(i + 1) * kMaxDots + j];
@@ -559,11 +611,13 @@ gmres_column_kernel(GmresState* __restrict__ st, const double* __restrict__ gs, 
   st->cols = j + 1;
   st->its += 1;
   const bool conv = st->rel <= st->rtol;
-  if (conv || !(hn > 0.0) || j + 1 == m) {
+  if (conv || !(hn > 0.0) || !(nw1 > 0.0) || j + 1 == m) {
     st->done = 1;
     st->converged = conv ? 1 : 0;
   } else {
-    st->scale = 1.0 / hn;
+    for (int i = 0; i <= j; ++i) st->c[i] = double(h2[i]) / nw1;
+    st->gam = hn / nw1;
+    st->scale = 1.0 / nw1;
   }
 }
 

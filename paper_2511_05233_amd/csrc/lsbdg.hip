@@ -1094,19 +1094,22 @@ int newton_solve(dg_ctx* ctx, double t_n, double dt, double* u, const dg_solver_
         if (hflag[0]) break;                       // zero residual: nothing to do
         for (int jj = 0; jj < m && its + jj < maxit; ++jj) {
           opA(V + int64_t(jj) * n7, w);
-          // classical Gram-Schmidt applied twice: with FP32 basis vectors a
-          // single pass (even with a reorthogonalisation test) loses enough
-          // orthogonality to slow the two-level preconditioned iteration
-          // (three sweeps over the basis: projections; first update fused
-          // with the second projections; second update fused with |w|^2)
+          // classical Gram-Schmidt applied twice (with FP32 basis vectors a
+          // single pass, even with a reorthogonalisation test, loses enough
+          // orthogonality to slow the preconditioned iteration), its second
+          // pass delayed to the next iteration (krylov.hpp): two sweeps over
+          // the basis, sweep 1 correcting the previous vector and projecting
+          // the operator's output, sweep 2 forming w1 with its second-pass
+          // projections and |w1|^2
           const dim3 gj{unsigned(jj + 1), 1, 1};
-          hipLaunchKernelGGL(multi_dot_kernel<S>, gred, blk, 0, st, V, n7, jj + 1, w, n7, partial);
+          hipLaunchKernelGGL(dcgs_sweep1_kernel<S>, gred, blk, 0, st, gst, V, n7, jj, w, n7, partial);
           hipLaunchKernelGGL(finish_sum_kernel<S>, gj, blk, 0, st, partial, nred, gs_h1);
-          hipLaunchKernelGGL(multi_axpy_dot_kernel<S>, gred, blk, 0, st, V, n7, jj + 1, gs_h1, w, n7, partial);
+          hipLaunchKernelGGL(dcgs_coef_kernel<S>, g1, dim3(64), 0, st, gst, gs_h1, jj, hbuf);
+          hipLaunchKernelGGL(dcgs_sweep2_kernel<S>, gred, blk, 0, st, gst, V, n7, jj + 1, hbuf, w, n7, partial,
+                             partial64);
           hipLaunchKernelGGL(finish_sum_kernel<S>, gj, blk, 0, st, partial, nred, gs_h2);
-          hipLaunchKernelGGL(multi_axpy_sumsq_kernel<S>, gred, blk, 0, st, V, n7, jj + 1, gs_h2, w, n7, partial64);
           hipLaunchKernelGGL(finish_sum_kernel<double>, g1, blk, 0, st, partial64, nred, gs);
-          hipLaunchKernelGGL(gmres_column_kernel<S>, g1, dim3(64), 0, st, gst, gs, jj, m);
+          hipLaunchKernelGGL(dcgs_column_kernel<S>, g1, dim3(64), 0, st, gst, gs, jj, m);
           hipLaunchKernelGGL(gmres_scale_kernel<S>, grid1(n7), blk, 0, st, gst, w, V + int64_t(jj + 1) * n7, n7);
           DG_HIP(hipMemcpyAsync(&hflag[jj & 1], &gst->done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
           DG_HIP(hipEventRecord(ctx->gm_ev[jj & 1], st));
