@@ -3,8 +3,10 @@
     python bench.py [--steps K] [--warmup W] [--mode newton|controller] [--dt S]
                     [--inner f32|f64] [--workload slab96_q1] [--compare-f64]
                     [--no-cpu-baseline] [--no-mixed] [--no-batch] [--kernels-only] [--copy-probe]
-                    [--batch] [--fp32-blocks]
-                    [--discharge WORKLOAD [--discharge-rate C]]
+                    [--step-only] [--batch] [--fp32-blocks]
+                    [--coarse C] [--coarse-agg A] [--mg-levels L] [--mg-sweeps NU] [--block-reuse X]
+                    [--discharge WORKLOAD [--discharge-rate C] [--limiter] [--t-stop T] [--max-wall S]]
+                    [--controller-study NX F_C]
 
 Workload (default): the 96 x 96 x 192 voxel cathode slab (x = transport
 axis, 1 um voxels), DG-Q1, 9 unknowns per node of which 7 are transported
@@ -15,22 +17,27 @@ All inputs are synthetic, seeded and resident in HBM before timing starts.
 Set-up (untimed): the context and the initial state of the discharge on the
 GPU (equilibrium concentrations and the steady potential).
 
-A step (--mode newton, the default) is one Newton iteration of the first
-implicit step of the discharge (dt = 0.1 s): FP64 residual, linearisation,
-element block-Jacobi assembly and inversion, the full GMRES solve (condensed
-JVP, block apply, coarse correction, Gram-Schmidt) and the line-searched
-FP64 update -- every part of the hot path but the time controller.  The W
-warm-up and the K timed iterations each run as one dg_step call limited to
-that many Newton iterations.  --mode controller times K accepted steps of
-the naive controller instead (an implicit step is 10-20 Newton iterations).
+A step (--mode newton, the default) is one Newton iteration of the implicit
+steps of the discharge from the initial state (dt = 0.1 s): FP64 residual,
+linearisation, the element blocks (assembled and inverted where the solver
+rebuilds them), the full GMRES solve (Krylov operator, block apply, coarse
+correction -- the multigrid V-cycle on this slab --, Gram-Schmidt) and the
+line-searched FP64 update: every part of the hot path but the time
+controller.  Exactly K iterations are timed after W of warm-up on a copy of
+the state; a step that converges hands over to the next implicit step.
+--mode controller times K accepted steps of the naive controller instead
+(an implicit step is 10-20 Newton iterations).  The solver runs with the
+library's defaults unless the --coarse, --mg-*, --block-reuse or
+--fp32-blocks flags change them.
 
 value = DG operator GDoF/s: transported DoF / mean duration of one
 application of the Krylov operator (the condensed tangent at a stored
 linearisation, in the inner precision), timed with HIP events on the stream
-it runs on.  roofline = the kernel with the largest share of a Newton
-iteration (the block apply of the solver, by default from bfloat16
-inverses: one per GMRES iteration) against the HBM peak; the other kernels
-are listed beside it.
+it runs on.  roofline = that kernel against the HBM peak, with its
+algorithmic bytes, the HBM bytes and vector-ALU counts of the committed
+rocprofv3 summaries (while they were taken on the current kernel sources)
+and the library's STREAM triad for the achievable bandwidth; the other
+kernels of a GMRES iteration are listed beside it.
 
 Beside the line (skipped with --no-mixed): five steps on the 16^3 cube and a
 full 1C discharge of it to the 1.9 V cutoff, each with FP64 and with mixed
